@@ -1,0 +1,240 @@
+"""Measurements that pin a solver to what the paper and the mathematics fix.
+
+Each function takes ``make(params, **fields)`` returning an object with ``step(n)``,
+``fields()`` (dict of (ny, nx) arrays rho, ux, uy, T, C) and ``observables()``, so the
+same pin runs on the FP64 oracle and on the GPU library.  Every reference value below
+is computed from a closed form, a limit or an independent scalar recurrence, never by
+re-running the solver's own formulas.
+"""
+import numpy as np
+
+PERIODIC = ("periodic",) * 4
+NO_FLOW = dict(direct=1, gbT=0.0, gbC=0.0, Fphi=0.0)
+
+
+def conduction_profile(make, nx=16, ny=4, sigma=2.0, phi=0.7, steps=6000, **extra):
+    """Pure conduction between a hot left and a cold right wall (no buoyancy): the
+    steady profile is linear, T = Th + (Tl - Th)(x + 1/2)/nx with half-way walls, so the
+    wall numbers are exactly 1.  Returns (max |T - exact|, max |C - exact|, Nu, Sh)."""
+    p = dict(nx=nx, ny=ny, sides=("hot", "cold", "adiabatic", "adiabatic"), sigma=sigma, phi=phi,
+             nu=0.1, alpha_e=0.2, D_e=0.1, K=1e30, **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    x = np.arange(nx)
+    exact = 1.0 - (x + 0.5) / nx
+    ob = s.observables()
+    return (np.abs(F["T"] - exact[None, :]).max(), np.abs(F["C"] - exact[None, :]).max(),
+            ob["Nu"][:2], ob["Sh"][:2])
+
+
+def brinkman_poiseuille(make, nx, J=2.0, nu=0.05, K16=50.0, phi=0.7, G=1e-5, steps=None, **extra):
+    """Flow between no-slip walls at x = -1/2 and nx - 1/2, periodic in y, driven by a
+    constant body acceleration G in y, without inertia (F_phi = 0).  Steady Brinkman
+    equation nu_e u'' - (phi nu/K) u + phi G = 0 has the closed form
+    u = (G K/nu) [1 - cosh(r (x - xc))/cosh(r nx/2)], r = sqrt(phi nu/(nu_e K)).
+    K is scaled with nx^2 so that the profile shape is fixed.  Returns the relative L2
+    error of u_y."""
+    K = K16 * (nx / 16.0) ** 2
+    p = dict(nx=nx, ny=3, sides=("adiabatic", "adiabatic", "periodic", "periodic"), J=J, phi=phi,
+             nu=nu, alpha_e=0.1, D_e=0.1, K=K, g_ext=(0.0, G), **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps or int(20 * nx * nx / (J * nu)))
+    u = s.fields()["uy"][1]
+    x = np.arange(nx)
+    r = np.sqrt(phi * nu / (J * nu * K))
+    ua = (G * K / nu) * (1.0 - np.cosh(r * (x - (nx - 1) / 2.0)) / np.cosh(r * nx / 2.0))
+    return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
+
+
+def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G=(6e-4, 2e-3), **extra):
+    """A fully periodic, spatially uniform state under a constant acceleration G.  Then
+    streaming is the identity and the momentum obeys the trapezoidal recurrence
+    u^{n+1} - F(u^{n+1})/2 = u^n + F(u^n)/2 with F(u) = -a u - b|u|u + phi G, a = phi nu/K,
+    b = phi F_phi/sqrt(K) (Eq. 5); u^0 solves u - F(u)/2 = 0.  The recurrence is solved here
+    by Newton's method.  Its fixed point F = 0 is the Darcy-Forchheimer velocity
+    |u| = (-a + sqrt(a^2 + 4 b phi|G|))/(2b).
+    Returns (max recurrence error over ``steps`` steps, |u| after 20000 more steps, the
+    closed-form |u|)."""
+    p = dict(nx=3, ny=3, sides=PERIODIC, direct=1, nu=nu, alpha_e=0.1, D_e=0.1, K=K, gbT=0.0,
+             gbC=0.0, Fphi=Fphi, phi=phi, g_ext=tuple(G))
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    a = phi * nu / K
+    b = phi * Fphi / np.sqrt(K)
+    Gv = np.array(G, dtype=float)
+
+    def force(u):
+        return -a * u - b * np.hypot(*u) * u + phi * Gv
+
+    def solve(rhs):
+        x = rhs.copy()
+        for _ in range(60):
+            r = x - force(x) / 2 - rhs
+            n = np.hypot(*x)
+            # Jacobian of x - F(x)/2
+            Jm = np.eye(2) * (1 + a / 2 + b * n / 2)
+            if n > 0:
+                Jm += (b / 2) * np.outer(x, x) / n
+            dx = np.linalg.solve(Jm, -r)
+            x = x + dx
+            if np.abs(dx).max() < 1e-19:
+                break
+        return x
+
+    u = solve(np.zeros(2))
+    err = 0.0
+    for _ in range(steps):
+        F = s.fields()
+        got = np.array([F["ux"][1, 1], F["uy"][1, 1]])
+        err = max(err, float(np.abs(got - u).max()))
+        s.step(1)
+        u = solve(u + force(u) / 2)
+    s.step(20000)
+    F = s.fields()
+    got = float(np.hypot(F["ux"][1, 1], F["uy"][1, 1]))
+    g = phi * np.hypot(*Gv)
+    closed = (-a + np.sqrt(a * a + 4 * b * g)) / (2 * b) if b > 0 else g / a
+    return err, got, float(closed)
+
+
+def sine_decay(make, nx=64, sigma=1.0, phi=1.0, alpha=0.05, u0=0.0, which="T", t1=300, steps=2000, **extra):
+    """A sine mode of T (or C) in a fully periodic domain, at rest or carried by a uniform
+    flow u0 (no porous drag, no buoyancy).  Eqs. (3)-(4) give the amplitude decay rate
+    alpha_e k^2/sigma (D_e k^2/phi) per step and the phase speed u0/sigma (u0/phi).
+    Returns the relative error of the measured rate between steps t1 and t1 + steps."""
+    p = dict(nx=nx, ny=3, sides=PERIODIC, nu=0.05, alpha_e=alpha, D_e=alpha, K=1e30, sigma=sigma,
+             phi=phi, varpi=0.4, **NO_FLOW)
+    p.update(extra)
+    k = 2 * np.pi / nx
+    x = np.arange(nx)
+    prof = 0.5 + 0.1 * np.sin(k * x)[None, :].repeat(3, 0)
+    s = make(p, T=prof, C=prof, ux=u0)
+    key = "T" if which == "T" else "C"
+    cap = sigma if which == "T" else phi
+
+    def amp():
+        return np.abs(np.fft.fft(s.fields()[key][1] - 0.5)[1])
+
+    s.step(t1)
+    a0 = amp()
+    s.step(steps)
+    a1 = amp()
+    rate = -np.log(a1 / a0) / steps
+    return float(rate / (alpha * k * k / cap) - 1.0)
+
+
+def sine_phase_speed(make, nx=128, sigma=2.0, u0=0.05, steps=400, **extra):
+    """Phase speed of an advected sine mode of T relative to u0/sigma (Eq. 3)."""
+    p = dict(nx=nx, ny=3, sides=PERIODIC, nu=0.05, alpha_e=0.05, D_e=0.05, K=1e30, sigma=sigma,
+             phi=1.0, varpi=0.4, **NO_FLOW)
+    p.update(extra)
+    k = 2 * np.pi / nx
+    x = np.arange(nx)
+    prof = 0.5 + 0.1 * np.sin(k * x)[None, :].repeat(3, 0)
+    s = make(p, T=prof, C=prof, ux=u0)
+    s.step(100)
+    ph0 = np.angle(np.fft.fft(s.fields()["T"][1] - 0.5)[1])
+    s.step(steps)
+    ph1 = np.angle(np.fft.fft(s.fields()["T"][1] - 0.5)[1])
+    dph = (ph0 - ph1) % (2 * np.pi)
+    return float((dph / k / steps) / (u0 / sigma) - 1.0)
+
+
+def closed_box(make, nx=24, ny=20, steps=2000, seed=5, **extra):
+    """All four sides adiabatic and no-slip, random porosity and initial T, C, buoyancy
+    on.  Mass, heat and solute (sum rho, sum sigma T, sum phi C) are invariant.
+    Returns the relative drifts."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.45, 0.9, size=(ny, nx))
+    T = rng.uniform(0.0, 1.0, size=(ny, nx))
+    C = rng.uniform(0.0, 1.0, size=(ny, nx))
+    p = dict(nx=nx, ny=ny, sides=("adiabatic",) * 4, Ra=1e5, Da=1e-2, Le=3.0, N=0.7, sigma=1.3,
+             phi=0.6)
+    p.update(extra)
+    s = make(p, phi=phi, T=T, C=C)
+    o0 = s.observables()
+    s.step(steps)
+    o1 = s.observables()
+    return tuple(abs(o1[k] - o0[k]) / abs(o0[k]) for k in ("mass", "heat", "solute")), o1
+
+
+def rest_state(make, nx=12, ny=10, steps=300, **extra):
+    """u = 0 and T = C = 0.5 everywhere, walls held at the same values: the state must not
+    move.  Returns max |field - initial| over (rho - rho0, u, T, C)."""
+    p = dict(nx=nx, ny=ny, sides=("hot", "cold", "adiabatic", "adiabatic"), Th=0.5, Tl=0.5,
+             Ch=0.5, Cl=0.5, direct=1, nu=0.05, alpha_e=0.05, D_e=0.03, K=30.0, gbT=1e-3,
+             gbC=-2e-4, Fphi=-1.0, phi=0.55)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    return max(float(np.abs(F["rho"] - 1.0).max()), float(np.abs(F["ux"]).max()),
+               float(np.abs(F["uy"]).max()), float(np.abs(F["T"] - 0.5).max()),
+               float(np.abs(F["C"] - 0.5).max()))
+
+
+def cavity_symmetry(make, nx=32, ny=24, steps=2000, **extra):
+    """A noise-free cavity with uniform porosity, hot left and cold right walls and
+    scalars centred on zero (walls at +-1/2, initial T = C = 0): rotating the domain by
+    pi maps the discrete problem onto itself with T -> -T, C -> -C, u -> -u, because the
+    D2Q5 equilibria, the source term and the buoyancy are all linear in the scalars.
+    (A shifted scalar, T -> 1 - T, is not an exact symmetry of the lattice scheme: the
+    equilibrium flux u T transports a constant only where the lattice divergence of u
+    vanishes.)  Returns the largest violation."""
+    p = dict(nx=nx, ny=ny, Ra=5e4, Da=1e-2, Le=2.0, N=0.5, phi=0.6, Th=0.5, Tl=-0.5, Ch=0.5, Cl=-0.5)
+    p.update(extra)
+    s = make(p, T=0.0, C=0.0)
+    s.step(steps)
+    F = s.fields()
+    rot = lambda a: a[::-1, ::-1]
+    scale = max(np.abs(F["ux"]).max(), np.abs(F["uy"]).max())
+    return max(float(np.abs(F["T"] + rot(F["T"])).max()), float(np.abs(F["C"] + rot(F["C"])).max()),
+               float(np.abs(F["ux"] + rot(F["ux"])).max() / scale),
+               float(np.abs(F["uy"] + rot(F["uy"])).max() / scale),
+               float(np.abs(F["rho"] - rot(F["rho"])).max()))
+
+
+def hot_fluid_rises(make, nx=32, ny=32, steps=1500, **extra):
+    """Eq. (6) with j pointing up: next to the hot left wall the fluid rises (u_y > 0)
+    and next to the cold right wall it sinks.  Returns (mean u_y of the first column,
+    mean u_y of the last column)."""
+    p = dict(nx=nx, ny=ny, Ra=1e5, Da=1e-1, Le=1.0, N=0.0, phi=0.8)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    return float(F["uy"][:, 0].mean()), float(F["uy"][:, -1].mean())
+
+
+def le1_decoupling(make, n=24, steps=40000, sigma=2.0, phi=0.6, model=0, **extra):
+    """Le = 1 with identical walls and initial fields for T and C and sigma != phi: the
+    present model's steady state has T = C, hence Nu = Sh (section 3.2 and Tables 3 and
+    5); Model-A's does not.  Returns (max |T - C|, Nu - Sh, r_u)."""
+    p = dict(nx=n, ny=n, Ra=1e3, Pr=1.0, Le=1.0, Da=1e-2, N=1.0, sigma=sigma, phi=phi, model=model)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps - 1000)
+    s.observables()
+    s.step(1000)
+    ob = s.observables()
+    F = s.fields()
+    return float(np.abs(F["T"] - F["C"]).max()), ob["Nu"][0] - ob["Sh"][0], ob["r_u"]
+
+
+def buoyancy_cancellation(make, n=20, steps=1500, seed=9, **extra):
+    """Le = 1, N = -1, sigma = phi and T, C started from the same noisy field: T and C
+    evolve identically, so the buoyancy of Eq. (6) vanishes and the fluid never moves.
+    Returns (max |u|, max |T - C|, Nu, Sh at the hot wall)."""
+    rng = np.random.default_rng(seed)
+    T = 0.5 + rng.uniform(-1e-2, 1e-2, size=(n, n))
+    p = dict(nx=n, ny=n, Ra=1e5, Pr=1.0, Le=1.0, Da=1e-1, N=-1.0, sigma=0.7, phi=0.7)
+    p.update(extra)
+    s = make(p, T=T, C=T.copy())
+    s.step(steps)
+    F = s.fields()
+    ob = s.observables()
+    return (float(max(np.abs(F["ux"]).max(), np.abs(F["uy"]).max())), float(np.abs(F["T"] - F["C"]).max()),
+            ob["Nu"][0], ob["Sh"][0])
