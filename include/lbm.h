@@ -1,0 +1,205 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the multiple-relaxation-time lattice
+ * Boltzmann model of double-diffusive convection in fluid-saturated porous media of
+ * Liu & He (arXiv 1708.07525).
+ *
+ * One time step advances, in a single fused stream-and-collide pass over every node:
+ *   - the D2Q9 flow distribution f: moment-space collision (Eq. 10) with the porous
+ *     equilibrium moments (Eq. 14, alpha1 = 1, alpha2 = -3), the forcing moments (Eq. 15)
+ *     of the total force of Eq. (5) (Darcy, Forchheimer, buoyancy of Eq. 6), density and
+ *     the explicit velocity of Eqs. (16)-(19);
+ *   - the D2Q5 temperature and concentration distributions g and h: moment-space
+ *     collisions (Eqs. 21-23) with the modified equilibrium moments (Eqs. 24-25) and the
+ *     source term of Eq. (27) with its time derivative taken as a one-step backward
+ *     difference (section 3.2);
+ *   - streaming (Eq. 11) as a pull from the upstream node, with half-way bounce-back for
+ *     f, anti-bounce-back for g/h at a side held at fixed T/C and bounce-back at a zero-flux
+ *     side (the constant follows from Eq. 28).
+ * Parameters follow the problem statement of section 2 (Ra, Pr, Le, Da, N, J, sigma,
+ * porosity) and the lattice choices of section 4 (rho0, varpi, free relaxation rates,
+ * Ma = U/c_s with U = sqrt(g beta_T dT L), L = nx).
+ *
+ * Conventions
+ *   - Host field arrays are double, ny rows of nx values, x fastest (index y*nx + x);
+ *     they are borrowed for the duration of a call and copied.
+ *   - Device memory belongs to the context, or to a caller arena (params.arena) that must
+ *     outlive the context.
+ *   - Every call returns an lbm_status; no exception crosses the ABI.  On error the
+ *     context (if any) keeps a message readable with lbm_last_error().
+ *   - A context is used by one host thread at a time.  Work is ordered on the context's
+ *     HIP stream (params.stream, NULL = the null stream); lbm_step is asynchronous,
+ *     lbm_observables and the state/field copies synchronise the stream.
+ *   - Only gfx950 code is built; a context on any other device fails with LBM_EDEVICE.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument or parameter                         */
+  LBM_ENOMEM = -2,     /* device or host allocation failed, or the arena is too small */
+  LBM_EDEVICE = -3,    /* HIP runtime error, or no gfx950 device                 */
+  LBM_ESTATE = -4,     /* call out of order (e.g. step before set_fields)        */
+  LBM_EUNSTABLE = -5   /* a non-finite value was found in the fields             */
+} lbm_status;
+
+/* Storage of the populations.  Arithmetic is FP64 for LBM_FP64 and FP32 otherwise.
+ * Populations are stored as deviations from the rest state at (rho0, T0, C0): f_i - w_i rho0,
+ * g_i - g_i^eq(T0, 0), h_i - h_i^eq(C0, 0).  LBM_FP16S stores them in IEEE binary16 with a
+ * power-of-two pre-scale (round to nearest even); the previous-step fields (T, C, u) used by
+ * the source term of Eq. (27) stay FP32. */
+typedef enum lbm_precision { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
+
+/* Kind of a side of the rectangle.  HOT holds T = Th and C = Ch, COLD holds T = Tl and
+ * C = Cl (anti-bounce-back for g, h); ADIABATIC is zero flux for T and C (bounce-back).  All
+ * three are impermeable no-slip walls for f (half-way bounce-back, moving with wall_u).
+ * PERIODIC must be set on both left and right, or on both bottom and top. */
+typedef enum lbm_side {
+  LBM_SIDE_HOT = 0,
+  LBM_SIDE_COLD = 1,
+  LBM_SIDE_ADIABATIC = 2,
+  LBM_SIDE_PERIODIC = 3
+} lbm_side;
+
+enum { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
+
+typedef struct lbm_params {
+  int32_t nx, ny;        /* lattice nodes; walls lie half a spacing outside; L = nx      */
+  int32_t precision;     /* lbm_precision                                               */
+  int32_t model;         /* 0: present model (Eqs. 24-25, 29); 1: Model-A (Eqs. 30-32)    */
+  int32_t side[4];       /* lbm_side of left, right, bottom, top                         */
+  double Ra, Pr, Le, Da, N;   /* thermal Rayleigh, Prandtl, Lewis, Darcy, buoyancy ratio  */
+  double J, sigma, phi;       /* viscosity ratio nu_e/nu, heat-capacity ratio, uniform porosity
+                                 (used when lbm_set_fields gets phi == NULL)              */
+  double Ma, varpi, rho0;     /* Mach number U/c_s; model parameter of Eq. (24) (<= 0:
+                                 min(2/5, smallest porosity)); reference density          */
+  double s_rho, s_e, s_eps, s_j, s_q;                  /* D2Q9 free rates                */
+  double zeta0, zeta_e, zeta_eps, eta0, eta_e, eta_eps;  /* D2Q5 free rates              */
+  double Th, Tl, Ch, Cl;      /* hot/cold T and C; dT = Th - Tl, T0 = (Th + Tl)/2, same for C */
+  double Fphi;                /* < 0: Ergun, Eq. (7); >= 0: this Forchheimer coefficient  */
+  double g_ext[2];            /* constant acceleration added to G of Eq. (6)              */
+  double wall_u[4];           /* tangential velocity of each side (moving lid)           */
+  int32_t direct;             /* 1: take nu, alpha_e, D_e, K, gbT, gbC below as lattice values
+                                 instead of mapping Ra, Pr, Le, Da, N, Ma                 */
+  double nu, alpha_e, D_e, K, gbT, gbC;
+  void *stream;               /* hipStream_t for all work of the context (NULL: null stream) */
+  void *arena;                /* optional device memory for every buffer of the context   */
+  uint64_t arena_bytes;       /* size of arena; must be >= lbm_footprint_bytes()          */
+} lbm_params;
+
+/* Fills the constants of section 4: rho0 = J = sigma = 1, Ma = 0.1, varpi automatic,
+ * s_rho = s_j = 1, s_e = s_eps = 1.1, s_q = 1.2, zeta0 = eta0 = 1, the other D2Q5 rates 1.5,
+ * Th = Ch = 1, Tl = Cl = 0, left HOT, right COLD, bottom/top ADIABATIC, FP32, Ergun F_phi,
+ * and the 64x64 porous-cavity groups nx = ny = 64, Ra = 1e4, Pr = 1, Le = 2, Da = 1e-2, N = 1,
+ * phi = 0.6. */
+void lbm_params_default(lbm_params *p);
+
+/* Bytes of device memory a context with these parameters needs (for an arena). */
+uint64_t lbm_footprint_bytes(const lbm_params *p);
+
+/* Validates p, maps it to lattice units (section 4.1, Eq. 29) and allocates the device
+ * buffers.  LBM_EINVAL: nx or ny < 3, a non-positive group, phi outside (0, 1], a free rate
+ * outside (0, 2), a derived s_v, zeta_alpha or eta_D outside (0, 2), inconsistent periodic
+ * sides.  *out is set only on LBM_OK. */
+lbm_status lbm_create(const lbm_params *p, struct lbm_ctx **out);
+
+/* Initial state from host fields (each nx*ny doubles): porosity (NULL: uniform p.phi; a
+ * field must lie in (0, 1) and sets K(x) by the Kozeny-Carman form of Eq. (7) scaled to
+ * mean Da L^2), T and C (NULL: T0, C0), ux and uy (NULL: 0).  The populations start at the
+ * equilibria of Eqs. (20) and (28) with rho = rho0; the previous-step fields of the source
+ * term start at the given T, C, u.  Resolves the automatic varpi.  Then one collision is
+ * applied, so that the stored state is the post-collision populations of level 0. */
+lbm_status lbm_set_fields(struct lbm_ctx *c, const double *phi, const double *T, const double *C,
+                          const double *ux, const double *uy);
+
+/* Advances nsteps >= 0 time steps (asynchronous, stream-ordered).  LBM_ESTATE before
+ * lbm_set_fields or while the context is attached to a batch. */
+lbm_status lbm_step(struct lbm_ctx *c, int64_t nsteps);
+
+typedef struct lbm_obs {
+  int64_t step;              /* time level n of the fields                               */
+  double Nu[4], Sh[4];       /* mean Nusselt / Sherwood number of Eq. (38) at each side held
+                                at fixed T/C (0 elsewhere); heat flowing from hot to cold is
+                                positive; second-order one-sided wall gradient           */
+  double mass, heat, solute; /* sum rho, sum sigma T, sum phi C over all nodes            */
+  double max_ux, max_uy;     /* largest |u_x|, |u_y|                                      */
+  double r_u, r_T, r_C;      /* |X(n) - X(m)|_2 / ((n - m) max(|X(n)|_2, 1e-30)) against the
+                                level m of the previous lbm_observables call (or level 0) */
+  int32_t nonfinite;         /* 1 if any rho, u, T or C is NaN or infinite                */
+} lbm_obs;
+
+/* Reductions over the current level (FP64 accumulation, fixed order: the result does not
+ * depend on launch shapes), optional export of the FP64 fields rho, ux, uy, T, C (5*nx*ny
+ * doubles, in that order) into fields, and the residual snapshot update.  Synchronises.
+ * Returns LBM_EUNSTABLE (after filling *out) when a value is not finite. */
+lbm_status lbm_observables(struct lbm_ctx *c, lbm_obs *out, double *fields);
+
+/* Export of the FP64 fields rho, ux, uy, T, C of the current level (5*nx*ny doubles, in that
+ * order, each ny rows of nx) without touching the residual snapshot.  Synchronises. */
+lbm_status lbm_get_fields(struct lbm_ctx *c, double *fields);
+
+/* Lattice values derived from the parameters (valid after lbm_set_fields). */
+typedef struct lbm_derived {
+  double L, U, nu, nu_e, alpha_e, D_e, s_v, zeta_a, eta_D, varpi, csT2;
+  double gbT, gbC, T0, C0, dT, dC, K_mean, phi_min, fp16_scale;
+} lbm_derived;
+lbm_status lbm_get_derived(const struct lbm_ctx *c, lbm_derived *out);
+
+/* Checkpoint: the complete state (populations, previous-step fields, residual snapshot,
+ * step counter).  lbm_state_bytes gives the size; lbm_get_state copies it to host memory,
+ * lbm_set_state restores it into a context created with the same parameters. */
+uint64_t lbm_state_bytes(const struct lbm_ctx *c);
+lbm_status lbm_get_state(struct lbm_ctx *c, void *host, uint64_t bytes);
+lbm_status lbm_set_state(struct lbm_ctx *c, const void *host, uint64_t bytes);
+
+/* Launch shape of the step kernel: tile_x nodes along x (64, 128 or 256) by tile_y rows
+ * (1, 2, 4 or 8) per work-group.  Results do not depend on it.  0, 0 restores the default. */
+lbm_status lbm_set_tile(struct lbm_ctx *c, int32_t tile_x, int32_t tile_y);
+lbm_status lbm_get_tile(const struct lbm_ctx *c, int32_t *tile_x, int32_t *tile_y);
+
+/* Times every supported launch shape on this context for `steps` steps each (HIP events),
+ * keeps the fastest, restores the state it started from, and reports the choice and its
+ * time per step.  Synchronises. */
+lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32_t *tile_y,
+                        double *ms_per_step);
+
+/* Text of the last error on this context ("" if none); a static text for c == NULL. */
+const char *lbm_last_error(const struct lbm_ctx *c);
+
+/* Frees the context and its device memory.  NULL is a no-op. */
+void lbm_destroy(struct lbm_ctx *c);
+
+/* ---- batched stepping of many independent cavities --------------------------------
+ * A batch advances every attached context (any size, parameters and precision) with one
+ * kernel launch per precision per time step.  The launches use a fixed grid that walks a
+ * device-side table of (cavity, tile) work items, and are replayed from a captured HIP
+ * graph of `chunk` steps, so that attaching or detaching contexts only rewrites the table
+ * between replays.  Per-node arithmetic is the same code as lbm_step: a cavity's state
+ * after n batched steps is bitwise the state after lbm_step(c, n). */
+typedef struct lbm_batch lbm_batch;
+
+/* max_cavities: capacity of the table; chunk: steps per graph replay (even, >= 2);
+ * stream: hipStream_t the batch runs on (NULL: null stream). */
+lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *stream, lbm_batch **out);
+/* The context must be initialised (lbm_set_fields), on the batch's device and not in
+ * another batch; its work moves to the batch's stream until detached. */
+lbm_status lbm_batch_attach(lbm_batch *b, struct lbm_ctx *c);
+lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
+/* Advances every attached context by nsteps (asynchronous). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+int32_t lbm_batch_size(const lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

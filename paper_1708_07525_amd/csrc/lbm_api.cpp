@@ -1,0 +1,952 @@
+// lbm_api.cpp -- host runtime behind the C ABI of include/lbm.h: parameter mapping and
+// validation (sections 2 and 4.1, Eq. 29), device buffers, launch bookkeeping, HIP graph
+// replay of step chunks, reductions, checkpoints, the autotuner and the batch table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#define LBM_API extern "C" __attribute__((visibility("default")))
+
+using namespace lbmk;
+
+namespace {
+
+constexpr int kGraphChunk = 64;     // steps per captured graph in lbm_step (even)
+constexpr double kCs2 = 1.0 / 3.0;  // D2Q9 sound speed squared
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// element sizes
+size_t store_size(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
+size_t real_size(int prec) { return prec == PREC_FP64 ? 8 : 4; }
+
+struct Layout {
+  int pitch;
+  long long plane;
+  size_t off_pop0, off_pop1, off_d4, off_phi, off_snap, off_small, total;
+  int nblocks_obs;
+};
+
+// Planes of ny rows of `pitch` elements; the plane stride is padded by 256 elements past a
+// 1024-element boundary so that the 19 + 4 concurrent streams do not start on the same
+// HBM channel.
+Layout plan_layout(int nx, int ny, int prec) {
+  Layout L{};
+  const size_t es = store_size(prec), rs = real_size(prec);
+  L.pitch = (int)round_up((size_t)nx, 64);
+  L.plane = (long long)round_up((size_t)L.pitch * ny, 1024) + 256;
+  L.nblocks_obs = observables_blocks(ny);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = round_up(off + bytes, 4096);
+    return o;
+  };
+  L.off_pop0 = take((size_t)NPOP * L.plane * es);
+  L.off_pop1 = take((size_t)NPOP * L.plane * es);
+  L.off_d4 = take((size_t)ND4 * L.plane * rs);
+  L.off_phi = take((size_t)L.plane * rs);
+  L.off_snap = take((size_t)ND4 * L.plane * rs);
+  // small: wall T (4), wall C (4), obs out (32), partials
+  L.off_small = take((8 + 32 + (size_t)L.nblocks_obs * 12) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  Layout lay{};
+  int prec = PREC_FP32;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *base = nullptr;      // device memory (arena or owned)
+  bool owned = false;
+  bool ready = false;
+  bool in_batch = false;
+  int cur = 0;               // buffer holding the post-collision state of the current level
+  int64_t step = 0;
+  int64_t snap_step = 0;
+  Tile tile{256, 1};
+  lbm_derived dv{};
+  bool phi_field = false;
+  Desc<double> d64{};
+  Desc<float> d32{};
+  double wallT[4]{}, wallC[4]{};
+  std::string err;
+  // graph of kGraphChunk steps, valid for `graph_cur` and `graph_tile`
+  hipGraphExec_t graph = nullptr;
+  int graph_cur = -1;
+  Tile graph_tile{0, 0};
+
+  void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
+  void *d4() const { return base + lay.off_d4; }
+  void *phi() const { return base + lay.off_phi; }
+  void *snap() const { return base + lay.off_snap; }
+  double *wall_dev() const { return (double *)(base + lay.off_small); }
+  double *obs_out() const { return wall_dev() + 8; }
+  double *partials() const { return wall_dev() + 40; }
+  const void *desc() const { return prec == PREC_FP64 ? (const void *)&d64 : (const void *)&d32; }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx *c, lbm_status s, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
+  return fail(c, LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_CHECK(ctx, expr, what)                 \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
+
+// Validation of everything that does not need the porosity field.
+lbm_status validate(const lbm_params *p, std::string &msg) {
+  auto bad = [&](const char *m) {
+    msg = m;
+    return LBM_EINVAL;
+  };
+  if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return bad("lattice too large");
+  if (p->precision < 0 || p->precision > 2) return bad("unknown precision");
+  if (p->model != 0 && p->model != 1) return bad("model must be 0 (present) or 1 (Model-A)");
+  for (int s = 0; s < 4; ++s)
+    if (p->side[s] < 0 || p->side[s] > 3) return bad("unknown side kind");
+  if ((p->side[LEFT] == SIDE_PERIODIC) != (p->side[RIGHT] == SIDE_PERIODIC) ||
+      (p->side[BOTTOM] == SIDE_PERIODIC) != (p->side[TOP] == SIDE_PERIODIC))
+    return bad("periodic sides must come in opposite pairs");
+  if (!(p->phi > 0.0 && p->phi <= 1.0)) return bad("porosity must lie in (0, 1]");
+  if (!(p->sigma > 0.0) || !(p->J > 0.0) || !(p->rho0 > 0.0)) return bad("sigma, J and rho0 must be positive");
+  if (p->varpi >= 1.0) return bad("varpi must lie in (0, 1)");
+  const double rates[] = {p->s_rho, p->s_e, p->s_eps, p->s_j, p->s_q, p->zeta0, p->zeta_e, p->zeta_eps,
+                          p->eta0, p->eta_e, p->eta_eps};
+  for (double r : rates)
+    if (!rate_ok(r)) return bad("free relaxation rates must lie in (0, 2)");
+  if (p->direct) {
+    if (!(p->nu > 0) || !(p->alpha_e > 0) || !(p->D_e > 0) || !(p->K > 0))
+      return bad("direct lattice values nu, alpha_e, D_e, K must be positive");
+  } else {
+    if (!(p->Ra > 0) || !(p->Pr > 0) || !(p->Le > 0) || !(p->Da > 0) || !(p->Ma > 0))
+      return bad("Ra, Pr, Le, Da and Ma must be positive");
+    if (!(p->Th - p->Tl > 0) || !(p->Ch - p->Cl > 0)) return bad("Th > Tl and Ch > Cl are required");
+  }
+  return LBM_OK;
+}
+
+// Lattice values of sections 2 and 4.1 (nothing that needs the porosity field).
+void map_params(const lbm_params *p, lbm_derived &d) {
+  d.L = p->nx;
+  d.dT = p->Th - p->Tl;
+  d.T0 = 0.5 * (p->Th + p->Tl);
+  d.dC = p->Ch - p->Cl;
+  d.C0 = 0.5 * (p->Ch + p->Cl);
+  if (p->direct) {
+    d.nu = p->nu;
+    d.alpha_e = p->alpha_e;
+    d.D_e = p->D_e;
+    d.K_mean = p->K;
+    d.gbT = p->gbT;
+    d.gbC = p->gbC;
+    d.U = std::sqrt(std::fabs(d.gbT * d.dT * d.L));
+  } else {
+    // Ma = U/c_s; U^2 = g beta_T dT L; Ra = g beta_T dT L^3/(nu alpha_e); Pr = nu/alpha_e
+    d.U = p->Ma * std::sqrt(kCs2);
+    d.nu = d.U * d.L * std::sqrt(p->Pr / p->Ra);
+    d.alpha_e = d.nu / p->Pr;
+    d.D_e = d.alpha_e / p->Le;
+    d.K_mean = p->Da * d.L * d.L;
+    d.gbT = d.U * d.U / (d.L * d.dT);
+    d.gbC = p->N * d.gbT * d.dT / d.dC;
+  }
+  d.nu_e = p->J * d.nu;
+  d.s_v = 1.0 / (0.5 + d.nu_e / kCs2);
+}
+
+// Everything that needs varpi (known once the porosity field is).
+lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
+  const lbm_params *p = &c->p;
+  lbm_derived &d = c->dv;
+  d.phi_min = phi_min;
+  d.varpi = p->varpi > 0 ? p->varpi : std::min(0.4, phi_min);
+  d.csT2 = 0.5 * d.varpi;
+  if (p->model == 0) {
+    d.zeta_a = 1.0 / (0.5 + d.alpha_e / d.csT2);  // Eq. (29)
+    d.eta_D = 1.0 / (0.5 + d.D_e / d.csT2);
+  } else {
+    d.zeta_a = 1.0 / (0.5 + d.alpha_e / (p->sigma * d.csT2));  // Eq. (32)
+    d.eta_D = 1.0 / (0.5 + d.D_e / (p->phi * d.csT2));
+  }
+  if (!rate_ok(d.s_v)) return fail(c, LBM_EINVAL, "derived s_v = %g outside (0, 2)", d.s_v);
+  if (!rate_ok(d.zeta_a)) return fail(c, LBM_EINVAL, "derived zeta_alpha = %g outside (0, 2)", d.zeta_a);
+  if (!rate_ok(d.eta_D)) return fail(c, LBM_EINVAL, "derived eta_D = %g outside (0, 2)", d.eta_D);
+  if (p->varpi > phi_min)
+    c->err = "note: varpi exceeds the smallest porosity; the concentration scheme may be unstable";
+
+  // FP16 pre-scale: a power of two that keeps deviations of size up to 16x the wall
+  // contrast inside the binary16 range
+  double B = 0.5;
+  B = std::max(B, std::max(p->sigma, 1.0) * std::max(std::fabs(p->Th - d.T0), std::fabs(p->Tl - d.T0)));
+  B = std::max(B, std::max(std::fabs(p->Ch - d.C0), std::fabs(p->Cl - d.C0)));
+  d.fp16_scale = c->prec == PREC_FP16S ? std::ldexp(1.0, (int)std::floor(std::log2(4096.0 / B))) : 1.0;
+
+  // fill both descriptor types from FP64 values
+  auto fill = [&](auto &D) {
+    using R = std::remove_reference_t<decltype(D.rho0)>;
+    D = {};
+    D.nx = p->nx;
+    D.ny = p->ny;
+    D.pitch = c->lay.pitch;
+    D.plane = c->lay.plane;
+    D.perx = p->side[LEFT] == SIDE_PERIODIC;
+    D.pery = p->side[BOTTOM] == SIDE_PERIODIC;
+    D.phi_field = c->phi_field;
+    D.ergun = p->Fphi < 0;
+    D.model = p->model;
+    for (int s = 0; s < 4; ++s) D.kind[s] = p->side[s];
+    D.base_parity = 0;
+    D.pop0 = c->pop(0);
+    D.pop1 = c->pop(1);
+    D.d4 = c->d4();
+    D.phi = c->phi();
+    D.rho0 = (R)p->rho0;
+    D.inv_rho0 = (R)(1.0 / p->rho0);
+    D.sigma = (R)p->sigma;
+    D.inv_sigma = (R)(1.0 / p->sigma);
+    D.varpi = (R)d.varpi;
+    D.T0 = (R)d.T0;
+    D.C0 = (R)d.C0;
+    D.s_e = (R)p->s_e;
+    D.s_eps = (R)p->s_eps;
+    D.s_j = (R)p->s_j;
+    D.s_q = (R)p->s_q;
+    D.s_v = (R)d.s_v;
+    D.z_a = (R)d.zeta_a;
+    D.z_e = (R)p->zeta_e;
+    D.z_eps = (R)p->zeta_eps;
+    D.e_D = (R)d.eta_D;
+    D.e_e = (R)p->eta_e;
+    D.e_eps = (R)p->eta_eps;
+    D.gbT = (R)d.gbT;
+    D.gbC = (R)d.gbC;
+    D.gx = (R)p->g_ext[0];
+    D.gy = (R)p->g_ext[1];
+    // uniform porosity: a = phi nu/K, b = phi F_phi/sqrt(K) (Eq. 5), K = Da L^2
+    const double phi = p->phi;
+    const double F = p->Fphi >= 0 ? p->Fphi : 1.75 / std::sqrt(150.0 * phi * phi * phi);  // Eq. (7)
+    D.phi_u = (R)phi;
+    D.a_u = (R)(phi * d.nu / d.K_mean);
+    D.b_u = (R)(phi * F / std::sqrt(d.K_mean));
+    // porosity field: K(x) = Ks phi^3/(1-phi)^2 with Ks = K_mean / mean(phi^3/(1-phi)^2)
+    const double Ks = mean_kc > 0 ? d.K_mean / mean_kc : d.K_mean;
+    D.ca = (R)(d.nu / Ks);
+    D.cb = (R)(p->Fphi < 0 ? 1.75 / std::sqrt(150.0 * Ks) : p->Fphi / std::sqrt(Ks));
+    D.kg3 = (R)(p->model == 0 ? 5.0 * d.varpi - 4.0 * p->sigma : (5.0 * d.varpi - 4.0) * p->sigma);
+    D.c5v = (R)(5.0 * d.varpi);
+    const double capT = p->model == 0 ? 1.0 : p->sigma;
+    const double capC = p->model == 0 ? 1.0 : p->phi;
+    for (int s = 0; s < 4; ++s) {
+      const double Tw = p->side[s] == SIDE_HOT ? p->Th : p->Tl;
+      const double Cw = p->side[s] == SIDE_HOT ? p->Ch : p->Cl;
+      // anti-bounce-back: g_i = -g*_opp + g^eq_i(w) + g^eq_opp(w) = -g*_opp + (varpi/2) cap T_w,
+      // in deviation form -gd*_opp + (varpi/2) cap (T_w - T0)
+      D.wT[s] = (R)(0.5 * d.varpi * capT * (Tw - d.T0));
+      D.wC[s] = (R)(0.5 * d.varpi * capC * (Cw - d.C0));
+      D.uw[s] = (R)(6.0 * p->rho0 * p->wall_u[s]);
+    }
+    D.scale = (R)d.fp16_scale;
+    D.inv_scale = (R)(1.0 / d.fp16_scale);
+  };
+  fill(c->d64);
+  fill(c->d32);
+  for (int s = 0; s < 4; ++s) {
+    c->wallT[s] = p->side[s] == SIDE_HOT ? p->Th : p->Tl;
+    c->wallC[s] = p->side[s] == SIDE_HOT ? p->Ch : p->Cl;
+  }
+  return LBM_OK;
+}
+
+void set_parity(lbm_ctx *c, int cur) {
+  c->d64.base_parity = cur;
+  c->d32.base_parity = cur;
+}
+
+bool arch_ok(int dev, std::string &name) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  name = prop.gcnArchName;
+  return name.rfind("gfx950", 0) == 0;
+}
+
+void drop_graph(lbm_ctx *c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_cur = -1;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+LBM_API void lbm_params_default(lbm_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->nx = p->ny = 64;
+  p->precision = LBM_FP32;
+  p->model = 0;
+  p->side[LEFT] = LBM_SIDE_HOT;
+  p->side[RIGHT] = LBM_SIDE_COLD;
+  p->side[BOTTOM] = LBM_SIDE_ADIABATIC;
+  p->side[TOP] = LBM_SIDE_ADIABATIC;
+  p->Ra = 1e4;
+  p->Pr = 1.0;
+  p->Le = 2.0;
+  p->Da = 1e-2;
+  p->N = 1.0;
+  p->J = 1.0;
+  p->sigma = 1.0;
+  p->phi = 0.6;
+  p->Ma = 0.1;
+  p->varpi = 0.0;
+  p->rho0 = 1.0;
+  p->s_rho = 1.0;
+  p->s_e = 1.1;
+  p->s_eps = 1.1;
+  p->s_j = 1.0;
+  p->s_q = 1.2;
+  p->zeta0 = p->eta0 = 1.0;
+  p->zeta_e = p->zeta_eps = p->eta_e = p->eta_eps = 1.5;
+  p->Th = 1.0;
+  p->Tl = 0.0;
+  p->Ch = 1.0;
+  p->Cl = 0.0;
+  p->Fphi = -1.0;
+}
+
+LBM_API uint64_t lbm_footprint_bytes(const lbm_params *p) {
+  if (!p || p->nx < 3 || p->ny < 3 || p->precision < 0 || p->precision > 2) return 0;
+  return plan_layout(p->nx, p->ny, p->precision).total;
+}
+
+LBM_API lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
+  if (!p || !out) return LBM_EINVAL;
+  std::string msg;
+  lbm_status s = validate(p, msg);
+  if (s != LBM_OK) return s;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->p = *p;
+  c->prec = p->precision;
+  c->stream = (hipStream_t)p->stream;
+  c->lay = plan_layout(p->nx, p->ny, p->precision);
+  map_params(p, c->dv);
+  std::string arch;
+  if (hipGetDevice(&c->device) != hipSuccess || !arch_ok(c->device, arch)) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  if (p->arena) {
+    if (p->arena_bytes < c->lay.total || ((uintptr_t)p->arena & 255)) {
+      delete c;
+      return LBM_ENOMEM;
+    }
+    c->base = (char *)p->arena;
+  } else {
+    if (hipMalloc((void **)&c->base, c->lay.total) != hipSuccess) {
+      delete c;
+      return LBM_ENOMEM;
+    }
+    c->owned = true;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+LBM_API void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  drop_graph(c);
+  if (c->owned && c->base) (void)hipFree(c->base);
+  delete c;
+}
+
+LBM_API const char *lbm_last_error(const lbm_ctx *c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T, const double *C,
+                                  const double *ux, const double *uy) {
+  if (!c) return LBM_EINVAL;
+  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  c->err.clear();
+  const lbm_params *p = &c->p;
+  const size_t n = (size_t)p->nx * p->ny;
+  // porosity: validation, smallest value and the Kozeny-Carman mean
+  double phi_min = p->phi, mean_kc = 0.0;
+  c->phi_field = phi != nullptr;
+  if (phi) {
+    if (p->model == 1) return fail(c, LBM_EINVAL, "Model-A needs a uniform porosity");
+    phi_min = 1e300;
+    double s = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+      const double q = phi[k];
+      if (!(q > 0.0 && q < 1.0)) return fail(c, LBM_EINVAL, "porosity field values must lie in (0, 1)");
+      phi_min = std::min(phi_min, q);
+      s += q * q * q / ((1.0 - q) * (1.0 - q));
+    }
+    mean_kc = s / (double)n;
+  }
+  lbm_status st = finish_mapping(c, phi_min, mean_kc);
+  if (st != LBM_OK) return st;
+  drop_graph(c);
+  c->cur = 0;
+  set_parity(c, 0);
+  // stage the inputs (FP64) on the device
+  const size_t plane_bytes = (size_t)c->lay.plane * real_size(c->prec);
+  double *stage = nullptr;
+  HIP_CHECK(c, hipMalloc((void **)&stage, 4 * n * sizeof(double)), "hipMalloc staging");
+  std::vector<double> fill;
+  auto put = [&](const double *src, double def, int slot) -> hipError_t {
+    if (!src) {
+      fill.assign(n, def);
+      src = fill.data();
+    }
+    return hipMemcpyAsync(stage + slot * n, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  };
+  hipError_t e = put(T, c->dv.T0, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = put(C, c->dv.C0, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = put(ux, 0.0, 2);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = put(uy, 0.0, 3);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->phi(), 0, plane_bytes, c->stream);
+  if (e == hipSuccess && phi) {
+    // porosity plane in the arithmetic type, row pitch applied
+    const size_t rs = real_size(c->prec);
+    std::vector<char> rows((size_t)c->lay.pitch * p->ny * rs, 0);
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const double q = phi[(size_t)y * p->nx + x];
+        char *dst = rows.data() + ((size_t)y * c->lay.pitch + x) * rs;
+        if (rs == 8) std::memcpy(dst, &q, 8);
+        else { float f = (float)q; std::memcpy(dst, &f, 4); }
+      }
+    e = hipMemcpyAsync(c->phi(), rows.data(), rows.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e == hipSuccess) e = (hipError_t)launch_init(c->prec, c->desc(), stage, stage + n, stage + 2 * n, stage + 3 * n, c->stream);
+  // the residual snapshot starts at level 0
+  if (e == hipSuccess) e = hipMemcpyAsync(c->snap(), c->d4(), 4 * plane_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->wall_dev(), c->wallT, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->wall_dev() + 4, c->wallC, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(stage);
+  if (e != hipSuccess) return hip_fail(c, e, "lbm_set_fields");
+  c->step = 0;
+  c->snap_step = 0;
+  c->ready = true;
+  return LBM_OK;
+}
+
+static lbm_status step_plain(lbm_ctx *c, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    set_parity(c, c->cur);
+    int e = launch_step(c->prec, c->desc(), c->tile, 0, c->stream);
+    if (e) return hip_fail(c, (hipError_t)e, "step kernel launch");
+    c->cur ^= 1;
+  }
+  return LBM_OK;
+}
+
+static lbm_status ensure_graph(lbm_ctx *c) {
+  if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty)
+    return LBM_OK;
+  drop_graph(c);
+  hipStream_t cs;
+  HIP_CHECK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  const int start = c->cur;
+  if (e == hipSuccess) {
+    int cur = start;
+    for (int k = 0; k < kGraphChunk && e == hipSuccess; ++k) {
+      set_parity(c, cur);
+      e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, 0, cs);
+      cur ^= 1;
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+  }
+  set_parity(c, start);
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return hip_fail(c, e, "step graph capture");
+  }
+  c->graph_cur = start;
+  c->graph_tile = c->tile;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
+  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  int64_t left = nsteps;
+  if (left >= kGraphChunk) {
+    lbm_status s = ensure_graph(c);
+    if (s != LBM_OK) return s;
+    while (left >= kGraphChunk) {
+      HIP_CHECK(c, hipGraphLaunch(c->graph, c->stream), "hipGraphLaunch");
+      left -= kGraphChunk;   // kGraphChunk is even: the current buffer is unchanged
+    }
+  }
+  lbm_status s = step_plain(c, left);
+  if (s != LBM_OK) return s;
+  c->step += nsteps;
+  return LBM_OK;
+}
+
+static lbm_status export_fields(lbm_ctx *c, double *fields) {
+  set_parity(c, c->cur);
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  double *stage = nullptr;
+  HIP_CHECK(c, hipMalloc((void **)&stage, 5 * n * sizeof(double)), "hipMalloc export");
+  hipError_t he = (hipError_t)launch_export(c->prec, c->desc(), 0, stage, c->stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(fields, stage, 5 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  (void)hipFree(stage);
+  if (he != hipSuccess) return hip_fail(c, he, "field export");
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_fields(lbm_ctx *c, double *fields) {
+  if (!c || !fields) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_get_fields before lbm_set_fields");
+  return export_fields(c, fields);
+}
+
+LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables before lbm_set_fields");
+  set_parity(c, c->cur);
+  const int nb = c->lay.nblocks_obs;
+  int e = launch_observables(c->prec, c->desc(), 0, c->snap(), c->partials(), nb, c->obs_out(), c->wall_dev(),
+                             c->wall_dev() + 4, c->dv.dT != 0 ? c->dv.L / c->dv.dT : 0.0,
+                             c->dv.dC != 0 ? c->dv.L / c->dv.dC : 0.0, c->stream);
+  if (e) return hip_fail(c, (hipError_t)e, "observables launch");
+  double r[20];
+  HIP_CHECK(c, hipMemcpyAsync(r, c->obs_out(), sizeof r, hipMemcpyDeviceToHost, c->stream), "observables copy");
+  if (fields) {
+    lbm_status fs = export_fields(c, fields);
+    if (fs != LBM_OK) return fs;
+  }
+  HIP_CHECK(c, hipStreamSynchronize(c->stream), "observables sync");
+  std::memset(out, 0, sizeof *out);
+  out->step = c->step;
+  out->mass = r[0];
+  out->heat = r[1];
+  out->solute = r[2];
+  const double dn = (double)(c->step - c->snap_step);
+  if (dn > 0) {
+    out->r_u = std::sqrt(r[3]) / (dn * std::max(std::sqrt(r[4]), 1e-30));
+    out->r_T = std::sqrt(r[5]) / (dn * std::max(std::sqrt(r[6]), 1e-30));
+    out->r_C = std::sqrt(r[7]) / (dn * std::max(std::sqrt(r[8]), 1e-30));
+  }
+  out->max_ux = r[9];
+  out->max_uy = r[10];
+  out->nonfinite = r[11] > 0 || !std::isfinite(r[0]) || !std::isfinite(r[3]);
+  for (int s = 0; s < 4; ++s) {
+    out->Nu[s] = r[12 + s];
+    out->Sh[s] = r[16 + s];
+  }
+  c->snap_step = c->step;
+  if (out->nonfinite) return fail(c, LBM_EUNSTABLE, "non-finite value in the fields at step %lld", (long long)c->step);
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_derived(const lbm_ctx *c, lbm_derived *out) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->ready) return LBM_ESTATE;
+  *out = c->dv;
+  return LBM_OK;
+}
+
+// ---- checkpoints ---------------------------------------------------------------------
+namespace {
+struct StateHeader {
+  char magic[8];
+  int32_t nx, ny, precision, pad;
+  int64_t step, snap_step;
+  uint64_t pop_bytes, d4_bytes;
+};
+}  // namespace
+
+LBM_API uint64_t lbm_state_bytes(const lbm_ctx *c) {
+  if (!c) return 0;
+  const size_t es = store_size(c->prec), rs = real_size(c->prec);
+  return sizeof(StateHeader) + (uint64_t)NPOP * c->lay.plane * es + 2ull * ND4 * c->lay.plane * rs;
+}
+
+LBM_API lbm_status lbm_get_state(lbm_ctx *c, void *host, uint64_t bytes) {
+  if (!c || !host) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "no state before lbm_set_fields");
+  if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
+  StateHeader h{};
+  std::memcpy(h.magic, "LBMDDPS1", 8);
+  h.nx = c->p.nx;
+  h.ny = c->p.ny;
+  h.precision = c->prec;
+  h.step = c->step;
+  h.snap_step = c->snap_step;
+  h.pop_bytes = (uint64_t)NPOP * c->lay.plane * store_size(c->prec);
+  h.d4_bytes = (uint64_t)ND4 * c->lay.plane * real_size(c->prec);
+  char *dst = (char *)host;
+  std::memcpy(dst, &h, sizeof h);
+  dst += sizeof h;
+  HIP_CHECK(c, hipMemcpyAsync(dst, c->pop(c->cur), h.pop_bytes, hipMemcpyDeviceToHost, c->stream), "state copy");
+  HIP_CHECK(c, hipMemcpyAsync(dst + h.pop_bytes, c->d4(), h.d4_bytes, hipMemcpyDeviceToHost, c->stream), "state copy");
+  HIP_CHECK(c, hipMemcpyAsync(dst + h.pop_bytes + h.d4_bytes, c->snap(), h.d4_bytes, hipMemcpyDeviceToHost, c->stream),
+            "state copy");
+  HIP_CHECK(c, hipStreamSynchronize(c->stream), "state sync");
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
+  if (!c || !host) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_set_fields must run first (it fixes the porosity)");
+  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
+  StateHeader h;
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, "LBMDDPS1", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
+    return fail(c, LBM_EINVAL, "state does not match this context");
+  const char *src = (const char *)host + sizeof h;
+  drop_graph(c);
+  c->cur = 0;
+  set_parity(c, 0);
+  HIP_CHECK(c, hipMemcpyAsync(c->pop(0), src, h.pop_bytes, hipMemcpyHostToDevice, c->stream), "state copy");
+  HIP_CHECK(c, hipMemcpyAsync(c->d4(), src + h.pop_bytes, h.d4_bytes, hipMemcpyHostToDevice, c->stream), "state copy");
+  HIP_CHECK(c, hipMemcpyAsync(c->snap(), src + h.pop_bytes + h.d4_bytes, h.d4_bytes, hipMemcpyHostToDevice, c->stream),
+            "state copy");
+  HIP_CHECK(c, hipStreamSynchronize(c->stream), "state sync");
+  c->step = h.step;
+  c->snap_step = h.snap_step;
+  return LBM_OK;
+}
+
+// ---- launch shape and autotuning ---------------------------------------------------------
+static bool tile_supported(int tx, int ty) {
+  return (tx == 64 || tx == 128 || tx == 256) && (ty == 1 || ty == 2 || ty == 4 || ty == 8);
+}
+
+LBM_API lbm_status lbm_set_tile(lbm_ctx *c, int32_t tx, int32_t ty) {
+  if (!c) return LBM_EINVAL;
+  if (tx == 0 && ty == 0) {
+    tx = 256;
+    ty = 1;
+  }
+  if (!tile_supported(tx, ty)) return fail(c, LBM_EINVAL, "unsupported tile %dx%d", tx, ty);
+  c->tile = Tile{tx, ty};
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_tile(const lbm_ctx *c, int32_t *tx, int32_t *ty) {
+  if (!c || !tx || !ty) return LBM_EINVAL;
+  *tx = c->tile.tx;
+  *ty = c->tile.ty;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int32_t *ty_out, double *ms_out) {
+  if (!c || steps < 2) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_set_fields");
+  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  // save the state on the device, try each shape, restore
+  const size_t pop_bytes = (size_t)NPOP * c->lay.plane * store_size(c->prec);
+  const size_t d4_bytes = (size_t)ND4 * c->lay.plane * real_size(c->prec);
+  char *save = nullptr;
+  HIP_CHECK(c, hipMalloc((void **)&save, pop_bytes + d4_bytes), "hipMalloc autotune");
+  const int cur0 = c->cur;
+  const int64_t step0 = c->step;
+  const Tile tile0 = c->tile;
+  hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  double best = 1e300;
+  Tile best_tile = tile0;
+  const int txs[] = {64, 128, 256};
+  const int tys[] = {1, 2, 4, 8};
+  for (int tx : txs)
+    for (int ty : tys) {
+      if (e != hipSuccess) break;
+      c->tile = Tile{tx, ty};
+      if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
+      e = hipEventRecord(t0, c->stream);
+      if (e == hipSuccess && step_plain(c, steps) != LBM_OK) e = hipErrorUnknown;
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && ms / steps < best) {
+        best = ms / steps;
+        best_tile = c->tile;
+      }
+    }
+  // restore
+  c->cur = cur0;
+  set_parity(c, cur0);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->pop(cur0), save, pop_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d4(), save + pop_bytes, d4_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(save);
+  c->step = step0;
+  if (e != hipSuccess) {
+    c->tile = tile0;
+    return hip_fail(c, e, "autotune");
+  }
+  c->tile = best_tile;
+  drop_graph(c);
+  if (tx_out) *tx_out = best_tile.tx;
+  if (ty_out) *ty_out = best_tile.ty;
+  if (ms_out) *ms_out = best;
+  return LBM_OK;
+}
+
+// ================================================================== batch
+struct lbm_batch {
+  int cap = 0;
+  int chunk = 2;
+  hipStream_t stream = nullptr;
+  std::vector<lbm_ctx *> ctx;
+  // per precision: descriptor table, item table, item count (device)
+  void *descs[3] = {nullptr, nullptr, nullptr};
+  Item *items[3] = {nullptr, nullptr, nullptr};
+  int *nitems[3] = {nullptr, nullptr, nullptr};
+  int item_cap[3] = {0, 0, 0};
+  int grid = 2048;
+  int tile_y = 1;
+  hipGraphExec_t graph = nullptr;
+  unsigned graph_mask = 0;   // precisions present when the graph was captured
+  bool dirty = true;
+};
+
+namespace {
+
+lbm_status batch_upload(lbm_batch *b) {
+  for (int prec = 0; prec < 3; ++prec) {
+    std::vector<Item> items;
+    std::vector<Desc<double>> d64;
+    std::vector<Desc<float>> d32;
+    for (lbm_ctx *c : b->ctx) {
+      if (c->prec != prec) continue;
+      const int idx = prec == PREC_FP64 ? (int)d64.size() : (int)d32.size();
+      set_parity(c, c->cur);
+      if (prec == PREC_FP64) d64.push_back(c->d64);
+      else d32.push_back(c->d32);
+      const int ntx = (c->p.nx + 255) / 256, nty = (c->p.ny + b->tile_y - 1) / b->tile_y;
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * 256, ty * b->tile_y, 0});
+    }
+    const int n = (int)items.size();
+    if (n > b->item_cap[prec]) {
+      // grow the item table; the graph references the old pointer, so drop it
+      if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+      }
+      if (b->items[prec]) (void)hipFree(b->items[prec]);
+      int cap = std::max(n, 2 * b->item_cap[prec]);
+      if (hipMalloc((void **)&b->items[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
+      b->item_cap[prec] = cap;
+    }
+    if (n) {
+      if (hipMemcpyAsync(b->items[prec], items.data(), n * sizeof(Item), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return LBM_EDEVICE;
+      const void *src = prec == PREC_FP64 ? (const void *)d64.data() : (const void *)d32.data();
+      const size_t bytes = prec == PREC_FP64 ? d64.size() * sizeof(Desc<double>) : d32.size() * sizeof(Desc<float>);
+      if (hipMemcpyAsync(b->descs[prec], src, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    }
+    if (hipMemcpyAsync(b->nitems[prec], &n, sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      return LBM_EDEVICE;
+  }
+  // the host copies above read host vectors that die here: wait for them
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
+  b->dirty = false;
+  return LBM_OK;
+}
+
+unsigned batch_mask(const lbm_batch *b) {
+  unsigned m = 0;
+  for (lbm_ctx *c : b->ctx) m |= 1u << c->prec;
+  return m;
+}
+
+hipError_t batch_launch_step(lbm_batch *b, unsigned mask, int parity, hipStream_t s) {
+  for (int prec = 0; prec < 3; ++prec) {
+    if (!(mask & (1u << prec))) continue;
+    int e = launch_step_batch(prec, b->descs[prec], b->items[prec], b->nitems[prec], b->grid, 256, b->tile_y,
+                              parity, s);
+    if (e) return (hipError_t)e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *stream, lbm_batch **out) {
+  if (!out || max_cavities < 1 || chunk < 2 || (chunk & 1)) return LBM_EINVAL;
+  lbm_batch *b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->cap = max_cavities;
+  b->chunk = chunk;
+  b->stream = (hipStream_t)stream;
+  int dev = 0;
+  std::string arch;
+  if (hipGetDevice(&dev) != hipSuccess || !arch_ok(dev, arch)) {
+    delete b;
+    return LBM_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b->grid = prop.multiProcessorCount * 8;
+  bool ok = true;
+  for (int prec = 0; prec < 3 && ok; ++prec) {
+    const size_t dsz = prec == PREC_FP64 ? sizeof(Desc<double>) : sizeof(Desc<float>);
+    ok = hipMalloc(&b->descs[prec], dsz * max_cavities) == hipSuccess &&
+         hipMalloc((void **)&b->nitems[prec], sizeof(int)) == hipSuccess;
+  }
+  if (!ok) {
+    lbm_batch_destroy(b);
+    return LBM_ENOMEM;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+LBM_API void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  for (lbm_ctx *c : b->ctx) {
+    c->in_batch = false;
+    c->stream = (hipStream_t)c->p.stream;
+  }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (int prec = 0; prec < 3; ++prec) {
+    if (b->descs[prec]) (void)hipFree(b->descs[prec]);
+    if (b->items[prec]) (void)hipFree(b->items[prec]);
+    if (b->nitems[prec]) (void)hipFree(b->nitems[prec]);
+  }
+  delete b;
+}
+
+LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
+  if (!b || !c) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "attach before lbm_set_fields");
+  if (c->in_batch) return fail(c, LBM_ESTATE, "context already in a batch");
+  if ((int)b->ctx.size() >= b->cap) return fail(c, LBM_ENOMEM, "batch is full");
+  // make prior work of the context visible to the batch stream
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before attach");
+  c->in_batch = true;
+  c->stream = b->stream;
+  drop_graph(c);
+  b->ctx.push_back(c);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_batch_detach(lbm_batch *b, lbm_ctx *c) {
+  if (!b || !c) return LBM_EINVAL;
+  auto it = std::find(b->ctx.begin(), b->ctx.end(), c);
+  if (it == b->ctx.end()) return fail(c, LBM_EINVAL, "context is not in this batch");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before detach");
+  b->ctx.erase(it);
+  c->in_batch = false;
+  c->stream = (hipStream_t)c->p.stream;
+  b->dirty = true;
+  return LBM_OK;
+}
+
+LBM_API int32_t lbm_batch_size(const lbm_batch *b) { return b ? (int32_t)b->ctx.size() : 0; }
+
+LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  if (b->ctx.empty() || nsteps == 0) return LBM_OK;
+  if (b->dirty) {
+    lbm_status s = batch_upload(b);
+    if (s != LBM_OK) return s;
+  }
+  const unsigned mask = batch_mask(b);
+  int64_t left = nsteps;
+  if (left >= b->chunk) {
+    if (!b->graph || b->graph_mask != mask) {
+      if (b->graph) (void)hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+      hipStream_t cs;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LBM_EDEVICE;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      for (int k = 0; k < b->chunk && e == hipSuccess; ++k) e = batch_launch_step(b, mask, k & 1, cs);
+      hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return LBM_EDEVICE;
+      }
+      b->graph_mask = mask;
+    }
+    while (left >= b->chunk) {
+      if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return LBM_EDEVICE;
+      left -= b->chunk;   // even chunk: every cavity's current buffer is unchanged
+    }
+  }
+  for (int64_t k = 0; k < left; ++k)
+    if (batch_launch_step(b, mask, (int)(k & 1), b->stream) != hipSuccess) return LBM_EDEVICE;
+  for (lbm_ctx *c : b->ctx) {
+    c->step += nsteps;
+    if (left & 1) c->cur ^= 1;
+  }
+  if (left & 1) b->dirty = true;   // base parities in the table changed
+  return LBM_OK;
+}

@@ -1,0 +1,73 @@
+// lbm_internal.h -- structures shared by the host runtime and the gfx950 kernels.
+//
+// Data layout in HBM (one cavity):
+//   pop[2]  two population buffers (pull scheme: read one, write the other), each 19
+//           planes: f0..f8, g0..g4, h0..h4.  A plane holds ny rows of `pitch` elements
+//           (pitch >= nx, a multiple of 64), planes are `plane` elements apart
+//           (plane >= ny*pitch, padded so that planes do not alias on the same HBM
+//           channels).  Element (x, y) of plane i is at i*plane + y*pitch + x.
+//   d4      4 planes of the fields of the previous step: T, C, ux, uy (FP64 for FP64
+//           storage, FP32 otherwise).  Read and rewritten in place by the node itself.
+//   phi     1 plane of porosity (only when the porosity is a field).
+//   snap    4 planes: residual snapshot of ux, uy, T, C.
+//   Populations are stored as deviations from the rest state (rho0, T0, C0).
+#pragma once
+#include <stdint.h>
+
+namespace lbmk {
+
+enum { SIDE_HOT = 0, SIDE_COLD = 1, SIDE_ADIABATIC = 2, SIDE_PERIODIC = 3 };
+enum { LEFT = 0, RIGHT = 1, BOTTOM = 2, TOP = 3 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
+constexpr int NPOP = 19;       // 9 + 5 + 5 planes
+constexpr int ND4 = 4;
+
+// Per-cavity constants in the arithmetic type R of the kernel (double or float).
+template <typename R>
+struct Desc {
+  int nx, ny, pitch, phi_field;
+  long long plane;
+  int perx, pery, ergun, model;
+  int kind[4];
+  int base_parity, pad_[3];
+  void *pop0, *pop1;       // population buffers (storage type)
+  void *d4;                // previous-step fields (type R)
+  void *phi;               // porosity plane (type R), when phi_field
+  R rho0, inv_rho0, sigma, inv_sigma, varpi, T0, C0;
+  R s_e, s_eps, s_j, s_q, s_v;
+  R z_a, z_e, z_eps, e_D, e_e, e_eps;
+  R gbT, gbC, gx, gy;
+  R phi_u, a_u, b_u;       // uniform porosity: phi, Darcy a = phi nu/K, Forchheimer b = phi F/sqrt(K)
+  R ca, cb;                // porosity field: a = ca (1-phi)^2/phi^2; b = cb (1-phi)/phi^2 (Ergun)
+                           // or cb (1-phi)/sqrt(phi) (fixed F_phi)
+  R kg3, c5v;              // n3eq - n3ref = kg3 (T - T0) for g; c5v = 5 varpi
+  R wT[4], wC[4];          // anti-bounce-back constants (deviation form) per side
+  R uw[4];                 // 6 rho0 u_wall per side (moving-wall term of the bounce-back)
+  R scale, inv_scale;      // FP16 pre-scale (1 for FP32/FP64)
+};
+
+struct Item {              // one tile of one cavity, for the batched kernel
+  int cavity, x0, y0, _pad;
+};
+
+// Launch shape of the step kernel
+struct Tile {
+  int tx, ty;
+};
+
+// ---- launchers (defined in lbm_kernels.hip) ---------------------------------------------
+// All take a hipStream_t as void*; return a hipError_t as int.
+int launch_init(int prec, const void *desc, const double *T, const double *C, const double *ux,
+                const double *uy, void *stream);
+int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream);
+int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems,
+                      int grid, int block, int tile_y, int parity, void *stream);
+// observables: partial sums per block, then a final fixed-order reduction.
+// out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)
+int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials,
+                       int nblocks, double *out, const double *wall_T, const double *wall_C,
+                       double L_over_dT, double L_over_dC, void *stream);
+int launch_export(int prec, const void *desc, int parity, double *fields, void *stream);
+int observables_blocks(int ny);
+
+}  // namespace lbmk

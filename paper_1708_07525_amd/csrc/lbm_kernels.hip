@@ -1,0 +1,672 @@
+// lbm_kernels.hip -- gfx950 kernels of the fused stream-and-collide step of the porous
+// double-diffusive MRT lattice Boltzmann model (Liu & He, arXiv 1708.07525).
+//
+// One thread updates one lattice node per row of its tile:
+//   pull the 9 + 5 + 5 post-collision populations of the previous level from the
+//   upstream nodes (Eq. 11; walls: half-way bounce-back for f, anti-bounce-back /
+//   bounce-back for g, h), form rho, T, C (Eqs. 16, 26), the buoyancy (Eq. 6), the
+//   explicit velocity (Eqs. 18-19) and the total force (Eq. 5), collide f in moment
+//   space (Eqs. 10, 13-15), collide g and h in moment space (Eqs. 21-25) with the source
+//   term of Eq. (27) (time derivative: one-step backward difference), and store.
+// The 9x9 and 5x5 transforms are written out as sums with the integer / rational
+// coefficients of M, N and their inverses (the inverse of an orthogonal-row matrix is its
+// transpose over the squared row norms 9, 36, 36, 6, 12, 6, 12, 4, 4 and 5, 2, 2, 20, 4).
+// Populations are deviations from the rest state (rho0, T0, C0); all three storage
+// types share this one node function, so results do not depend on the launch shape.
+//
+// The path is bound by HBM bandwidth (19 population loads + 19 stores + 4 + 4 previous-step
+// field accesses + 1 porosity load per node, against ~350 flops), so there is no MFMA and
+// no LDS staging: each population element is read exactly once, by the one node that pulls
+// it, and the +-1 shifted reads of neighbouring tiles hit in L2.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+
+// ---------------------------------------------------------------- storage traits
+template <typename S>
+struct St;
+template <>
+struct St<double> {
+  using R = double;
+  static __device__ __forceinline__ R ld(const double *p, R) { return *p; }
+  static __device__ __forceinline__ void st(double *p, R v, R) { *p = v; }
+};
+template <>
+struct St<float> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const float *p, R) { return *p; }
+  static __device__ __forceinline__ void st(float *p, R v, R) { *p = v; }
+};
+template <>
+struct St<_Float16> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const _Float16 *p, R inv_scale) { return (float)(*p) * inv_scale; }
+  static __device__ __forceinline__ void st(_Float16 *p, R v, R scale) { *p = (_Float16)(v * scale); }
+};
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_(R v);
+template <>
+__device__ __forceinline__ double rsqrt_(double v) { return 1.0 / sqrt(v); }
+template <>
+__device__ __forceinline__ float rsqrt_(float v) { return 1.0f / sqrtf(v); }
+
+template <typename R>
+__device__ __forceinline__ R sqrt_(R v);
+template <>
+__device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
+template <>
+__device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
+
+// ---------------------------------------------------------------- collision of one node
+// Inputs: the pulled deviations fd[9], gd[5], hd[5]; node porosity; the previous-step
+// fields (T, C, ux, uy) in prev[4].  Outputs: post-collision deviations (in place) and the
+// fields of this level in prev[4].
+template <typename R>
+__device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd, R *gd, R *hd, R *prev) {
+  const R one = R(1), half = R(0.5);
+  // density, momentum and scalars (Eqs. 16, 17, 26), deviation form
+  const R sA = fd[1] + fd[2] + fd[3] + fd[4];
+  const R sD = fd[5] + fd[6] + fd[7] + fd[8];
+  const R drho = fd[0] + sA + sD;
+  const R jx = (fd[1] - fd[3]) + (fd[5] - fd[6]) - (fd[7] - fd[8]);
+  const R jy = (fd[2] - fd[4]) + (fd[5] + fd[6]) - (fd[7] + fd[8]);
+  const R sg = gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
+  const R sh = hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
+  const R inv_phi = one / phi;
+  const R dT = sg * d.inv_sigma;          // T - T0
+  const R dC = sh * inv_phi;              // C - C0
+  const R T = d.T0 + dT, C = d.C0 + dC;
+  // buoyancy (Eq. 6) plus any constant acceleration
+  const R Gx = d.gx;
+  const R Gy = d.gy + d.gbT * dT + d.gbC * dC;
+  // explicit velocity (Eqs. 18-19), delta_t = 1
+  const R vx = jx * d.inv_rho0 + half * phi * Gx;
+  const R vy = jy * d.inv_rho0 + half * phi * Gy;
+  const R l0 = half + R(0.25) * a;
+  const R l1 = half * b;
+  const R vn = sqrt_(vx * vx + vy * vy);
+  const R inv_den = one / (l0 + sqrt_(l0 * l0 + l1 * vn));
+  const R ux = vx * inv_den, uy = vy * inv_den;
+  const R u2 = ux * ux + uy * uy;
+  const R un = sqrt_(u2);
+  // total force (Eq. 5)
+  const R drag = a + b * un;
+  const R Fx = phi * Gx - drag * ux;
+  const R Fy = phi * Gy - drag * uy;
+
+  // ---- D2Q9: moments m = M f (Eq. 13) of the deviations
+  const R m1 = R(-4) * fd[0] - sA + R(2) * sD;
+  const R m2 = R(4) * fd[0] - R(2) * sA + sD;
+  const R m4 = R(-2) * (fd[1] - fd[3]) + (fd[5] - fd[6]) - (fd[7] - fd[8]);
+  const R m6 = R(-2) * (fd[2] - fd[4]) + (fd[5] + fd[6]) - (fd[7] + fd[8]);
+  const R m7 = (fd[1] + fd[3]) - (fd[2] + fd[4]);
+  const R m8 = (fd[5] + fd[7]) - (fd[6] + fd[8]);
+  // equilibrium moments (Eq. 14, alpha1 = 1, alpha2 = -3) minus those of the rest state
+  const R r0 = d.rho0;
+  const R r0p = r0 * inv_phi;
+  const R e1 = R(-2) * drho + R(3) * r0p * u2;
+  const R e2 = drho - R(3) * r0p * u2;
+  const R jxe = r0 * ux, jye = r0 * uy;
+  const R e7 = r0p * (ux * ux - uy * uy);
+  const R e8 = r0p * ux * uy;
+  // forcing moments (Eq. 15)
+  const R S1 = R(6) * r0p * (ux * Fx + uy * Fy);
+  const R S3 = r0 * Fx, S5 = r0 * Fy;
+  const R S7 = R(2) * r0p * (ux * Fx - uy * Fy);
+  const R S8 = r0p * (ux * Fy + uy * Fx);
+  // relaxation (Eq. 10): m* = m - s (m - meq) + (1 - s/2) S
+  const R p0 = drho;
+  const R p1 = m1 - d.s_e * (m1 - e1) + (one - half * d.s_e) * S1;
+  const R p2 = m2 - d.s_eps * (m2 - e2) - (one - half * d.s_eps) * S1;
+  const R p3 = jx - d.s_j * (jx - jxe) + (one - half * d.s_j) * S3;
+  const R p4 = m4 - d.s_q * (m4 + jxe) - (one - half * d.s_q) * S3;
+  const R p5 = jy - d.s_j * (jy - jye) + (one - half * d.s_j) * S5;
+  const R p6 = m6 - d.s_q * (m6 + jye) - (one - half * d.s_q) * S5;
+  const R p7 = m7 - d.s_v * (m7 - e7) + (one - half * d.s_v) * S7;
+  const R p8 = m8 - d.s_v * (m8 - e8) + (one - half * d.s_v) * S8;
+  // f* = M^-1 m*
+  const R a0 = p0 * R(1.0 / 9.0);
+  const R a1 = p1 * R(1.0 / 36.0);
+  const R a2 = p2 * R(1.0 / 36.0);
+  const R a3 = p3 * R(1.0 / 6.0);
+  const R a4 = p4 * R(1.0 / 12.0);
+  const R a5 = p5 * R(1.0 / 6.0);
+  const R a6 = p6 * R(1.0 / 12.0);
+  const R a7 = p7 * R(0.25);
+  const R a8 = p8 * R(0.25);
+  const R axis = a0 - a1 - R(2) * a2;
+  const R diag = a0 + R(2) * a1 + a2;
+  fd[0] = a0 - R(4) * a1 + R(4) * a2;
+  fd[1] = axis + a3 - R(2) * a4 + a7;
+  fd[2] = axis + a5 - R(2) * a6 - a7;
+  fd[3] = axis - a3 + R(2) * a4 + a7;
+  fd[4] = axis - a5 + R(2) * a6 - a7;
+  fd[5] = diag + a3 + a4 + a5 + a6 + a8;
+  fd[6] = diag - a3 - a4 + a5 + a6 - a8;
+  fd[7] = diag - a3 - a4 - a5 - a6 + a8;
+  fd[8] = diag + a3 + a4 - a5 - a6 - a8;
+
+  // ---- D2Q5 for T (Eq. 21) and C (Eq. 22)
+  // source moments N S~ = (0, d(T ux)/dt, d(T uy)/dt, 0, 0) from Eq. (27)
+  const R TuX = T * ux, TuY = T * uy, CuX = C * ux, CuY = C * uy;
+  const R STx = TuX - prev[0] * prev[2], STy = TuY - prev[0] * prev[3];
+  const R SCx = CuX - prev[1] * prev[2], SCy = CuY - prev[1] * prev[3];
+  const R kh3 = d.model == 0 ? (d.c5v - R(4) * phi) : (d.c5v - R(4)) * phi;
+  {
+    const R n0 = sg;
+    const R n1 = gd[1] - gd[3], n2 = gd[2] - gd[4];
+    const R n3 = R(-4) * gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
+    const R n4 = gd[1] - gd[2] + gd[3] - gd[4];
+    const R q1 = n1 - d.z_a * (n1 - TuX) + (one - half * d.z_a) * STx;
+    const R q2 = n2 - d.z_a * (n2 - TuY) + (one - half * d.z_a) * STy;
+    const R q3 = n3 - d.z_e * (n3 - d.kg3 * dT);
+    const R q4 = n4 - d.z_eps * n4;
+    const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
+    gd[0] = b0 - R(4) * b3;
+    gd[1] = b0 + b1 + b3 + b4;
+    gd[2] = b0 + b2 + b3 - b4;
+    gd[3] = b0 - b1 + b3 + b4;
+    gd[4] = b0 - b2 + b3 - b4;
+  }
+  {
+    const R eD = d.e_D;
+    const R n0 = sh;
+    const R n1 = hd[1] - hd[3], n2 = hd[2] - hd[4];
+    const R n3 = R(-4) * hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
+    const R n4 = hd[1] - hd[2] + hd[3] - hd[4];
+    const R q1 = n1 - eD * (n1 - CuX) + (one - half * eD) * SCx;
+    const R q2 = n2 - eD * (n2 - CuY) + (one - half * eD) * SCy;
+    const R q3 = n3 - d.e_e * (n3 - kh3 * dC);
+    const R q4 = n4 - d.e_eps * n4;
+    const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
+    hd[0] = b0 - R(4) * b3;
+    hd[1] = b0 + b1 + b3 + b4;
+    hd[2] = b0 + b2 + b3 - b4;
+    hd[3] = b0 - b1 + b3 + b4;
+    hd[4] = b0 - b2 + b3 - b4;
+  }
+  prev[0] = T;
+  prev[1] = C;
+  prev[2] = ux;
+  prev[3] = uy;
+}
+
+// Darcy and Forchheimer coefficients of Eq. (5) at a node
+template <typename R>
+__device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &b) {
+  if (!d.phi_field) {
+    a = d.a_u;
+    b = d.b_u;
+    return;
+  }
+  // K = Kscale phi^3/(1-phi)^2 (Kozeny-Carman shape of Eq. 7);
+  // a = phi nu/K = ca (1-phi)^2/phi^2;  Ergun F = 1.75/sqrt(150 phi^3):
+  // b = phi F/sqrt(K) = cb (1-phi)/phi^2;  fixed F: b = cb (1-phi)/sqrt(phi)
+  const R q = R(1) - phi;
+  const R ip = R(1) / phi;
+  a = d.ca * q * q * ip * ip;
+  b = d.ergun ? d.cb * q * ip * ip : d.cb * q * rsqrt_(phi);
+}
+
+// ---------------------------------------------------------------- one node of a step
+template <typename S>
+__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const S *__restrict__ src,
+                                          S *__restrict__ dst, int x, int y) {
+  using R = typename St<S>::R;
+  const long long P = d.plane;
+  const int pitch = d.pitch, nx = d.nx, ny = d.ny;
+  const long long c = (long long)y * pitch + x;
+  // upstream coordinates, periodic wrap, and whether they lie inside
+  const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
+  const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
+  const int xm = x > 0 ? x - 1 : nx - 1, xp = x < nx - 1 ? x + 1 : 0;
+  const long long rm = (long long)(y > 0 ? y - 1 : ny - 1) * pitch;
+  const long long rp = (long long)(y < ny - 1 ? y + 1 : 0) * pitch;
+  const long long r0 = (long long)y * pitch;
+  const R is = d.inv_scale;
+  // source index of each direction (own index when the link crosses a wall)
+  const long long i1 = okxm ? r0 + xm : c;
+  const long long i2 = okym ? rm + x : c;
+  const long long i3 = okxp ? r0 + xp : c;
+  const long long i4 = okyp ? rp + x : c;
+  const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+  const long long i5 = ok5 ? rm + xm : c;
+  const long long i6 = ok6 ? rm + xp : c;
+  const long long i7 = ok7 ? rp + xp : c;
+  const long long i8 = ok8 ? rp + xm : c;
+  // plane read by each direction: its own, or the opposite one for a bounce-back
+  R fd[9], gd[5], hd[5], prev[4];
+  fd[0] = St<S>::ld(src + c, is);
+  fd[1] = St<S>::ld(src + (okxm ? 1 : 3) * P + i1, is);
+  fd[2] = St<S>::ld(src + (okym ? 2 : 4) * P + i2, is);
+  fd[3] = St<S>::ld(src + (okxp ? 3 : 1) * P + i3, is);
+  fd[4] = St<S>::ld(src + (okyp ? 4 : 2) * P + i4, is);
+  fd[5] = St<S>::ld(src + (ok5 ? 5 : 7) * P + i5, is);
+  fd[6] = St<S>::ld(src + (ok6 ? 6 : 8) * P + i6, is);
+  fd[7] = St<S>::ld(src + (ok7 ? 7 : 5) * P + i7, is);
+  fd[8] = St<S>::ld(src + (ok8 ? 8 : 6) * P + i8, is);
+  const S *g = src + 9 * P;
+  const S *h = src + 14 * P;
+  gd[0] = St<S>::ld(g + c, is);
+  hd[0] = St<S>::ld(h + c, is);
+  gd[1] = St<S>::ld(g + (okxm ? 1 : 3) * P + i1, is);
+  hd[1] = St<S>::ld(h + (okxm ? 1 : 3) * P + i1, is);
+  gd[2] = St<S>::ld(g + (okym ? 2 : 4) * P + i2, is);
+  hd[2] = St<S>::ld(h + (okym ? 2 : 4) * P + i2, is);
+  gd[3] = St<S>::ld(g + (okxp ? 3 : 1) * P + i3, is);
+  hd[3] = St<S>::ld(h + (okxp ? 3 : 1) * P + i3, is);
+  gd[4] = St<S>::ld(g + (okyp ? 4 : 2) * P + i4, is);
+  hd[4] = St<S>::ld(h + (okyp ? 4 : 2) * P + i4, is);
+  R *d4 = (R *)d.d4;
+  prev[0] = d4[c];
+  prev[1] = d4[P + c];
+  prev[2] = d4[2 * P + c];
+  prev[3] = d4[3 * P + c];
+  R phi = d.phi_u;
+  if (d.phi_field) phi = ((const R *)d.phi)[c];
+  // wall rules for links whose upstream node is outside
+  if (!(okxm & okxp & okym & okyp)) {
+    // f: half-way bounce-back with the moving-wall term 6 w_i rho0 e_i.u_w; the wall
+    // velocity is tangential: along x for the bottom/top sides, along y for left/right
+    const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    const R uB = d.uw[BOTTOM], uT = d.uw[TOP], uL = d.uw[LEFT], uR = d.uw[RIGHT];
+    // f5 (e = (1, 1)): from below -> bottom wall (e.u = uB); else from the left (uL)
+    if (!ok5) fd[5] += w5 * (!okym ? uB : uL);
+    if (!ok6) fd[6] += w5 * (!okym ? -uB : uR);
+    if (!ok7) fd[7] += w5 * (!okyp ? -uT : -uR);
+    if (!ok8) fd[8] += w5 * (!okyp ? uT : -uL);
+    (void)w1;  // the axis links carry no tangential component
+    // g, h: anti-bounce-back at a side held at fixed T/C, bounce-back at a zero-flux side
+    if (!okxm) {
+      const bool ab = d.kind[LEFT] != SIDE_ADIABATIC;
+      gd[1] = ab ? d.wT[LEFT] - gd[1] : gd[1];
+      hd[1] = ab ? d.wC[LEFT] - hd[1] : hd[1];
+    }
+    if (!okym) {
+      const bool ab = d.kind[BOTTOM] != SIDE_ADIABATIC;
+      gd[2] = ab ? d.wT[BOTTOM] - gd[2] : gd[2];
+      hd[2] = ab ? d.wC[BOTTOM] - hd[2] : hd[2];
+    }
+    if (!okxp) {
+      const bool ab = d.kind[RIGHT] != SIDE_ADIABATIC;
+      gd[3] = ab ? d.wT[RIGHT] - gd[3] : gd[3];
+      hd[3] = ab ? d.wC[RIGHT] - hd[3] : hd[3];
+    }
+    if (!okyp) {
+      const bool ab = d.kind[TOP] != SIDE_ADIABATIC;
+      gd[4] = ab ? d.wT[TOP] - gd[4] : gd[4];
+      hd[4] = ab ? d.wC[TOP] - hd[4] : hd[4];
+    }
+  }
+  R a, b;
+  porous_coeffs(d, phi, a, b);
+  collide(d, phi, a, b, fd, gd, hd, prev);
+  const R sc = d.scale;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) St<S>::st(dst + i * P + c, fd[i], sc);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) St<S>::st(dst + (9 + i) * P + c, gd[i], sc);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) St<S>::st(dst + (14 + i) * P + c, hd[i], sc);
+  d4[c] = prev[0];
+  d4[P + c] = prev[1];
+  d4[2 * P + c] = prev[2];
+  d4[3 * P + c] = prev[3];
+}
+
+// tile index -> (x0, y0), spreading consecutive row bands over the 8 XCDs so that the
+// tiles that share halo cache lines run on the same XCD (work-groups are dispatched to
+// XCDs round-robin by id)
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int per = n >> 3, rem = n & 7;
+  const int k = b & 7, j = b >> 3;
+  return k * per + (k < rem ? k : rem) + j;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx,
+                                                   int parity) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = (t % ntx) * blockDim.x + threadIdx.x;
+  const int y0 = (t / ntx) * tile_y;
+  if (x >= d.nx) return;
+  const int cur = (d.base_parity ^ parity) & 1;
+  const S *src = (const S *)(cur ? d.pop1 : d.pop0);
+  S *dst = (S *)(cur ? d.pop0 : d.pop1);
+  const int y1 = min(y0 + tile_y, d.ny);
+  for (int y = y0; y < y1; ++y) step_node<S>(d, src, dst, x, y);
+}
+
+// Batched step: a fixed grid walks the (cavity, tile) work items of every attached
+// cavity; the item count lives in device memory so the host can change the batch between
+// graph replays without re-capturing.
+template <typename S>
+__global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs,
+                                                         const Item *__restrict__ items,
+                                                         const int *__restrict__ nitems, int tile_y,
+                                                         int parity) {
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const Item item = items[it];
+    const Desc<typename St<S>::R> &d = descs[item.cavity];
+    const int x = item.x0 + threadIdx.x;
+    if (x < d.nx) {
+      const int cur = (d.base_parity ^ parity) & 1;
+      const S *src = (const S *)(cur ? d.pop1 : d.pop0);
+      S *dst = (S *)(cur ? d.pop0 : d.pop1);
+      const int y1 = min(item.y0 + tile_y, d.ny);
+      for (int y = item.y0; y < y1; ++y) step_node<S>(d, src, dst, x, y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- initial state
+// Equilibria of Eqs. (20) and (28) with rho = rho0 and the given T, C, u (deviation
+// form, evaluated in FP64), then one collision; writes buffer 0 and the fields of level 0.
+template <typename S>
+__global__ void __launch_bounds__(256) init_kernel(Desc<typename St<S>::R> d, const double *__restrict__ Tin,
+                                                   const double *__restrict__ Cin,
+                                                   const double *__restrict__ uxin,
+                                                   const double *__restrict__ uyin) {
+  using R = typename St<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= d.nx) return;
+  const long long k = (long long)y * d.nx + x;
+  const long long c = (long long)y * d.pitch + x;
+  const long long P = d.plane;
+  const double T = Tin[k], C = Cin[k], ux = uxin[k], uy = uyin[k];
+  const double phi = d.phi_field ? (double)((const R *)d.phi)[c] : (double)d.phi_u;
+  const double rho0 = d.rho0, varpi = d.varpi;
+  const double dT = T - (double)d.T0, dC = C - (double)d.C0;
+  const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  R fd[9], gd[5], hd[5], prev[4];
+  const double u2 = ux * ux + uy * uy;
+  for (int i = 0; i < 9; ++i) {
+    const double eu = EX[i] * ux + EY[i] * uy;
+    fd[i] = (R)(W[i] * rho0 * (3.0 * eu + 4.5 * eu * eu / phi - 1.5 * u2 / phi));
+  }
+  const double capT = d.model == 0 ? 1.0 : (double)d.sigma;
+  const double capC = d.model == 0 ? 1.0 : phi;
+  gd[0] = (R)(d.model == 0 ? ((double)d.sigma - varpi) * dT : (1.0 - varpi) * (double)d.sigma * dT);
+  hd[0] = (R)(d.model == 0 ? (phi - varpi) * dC : (1.0 - varpi) * phi * dC);
+  for (int i = 1; i < 5; ++i) {
+    const double eu = EX[i] * ux + EY[i] * uy;
+    gd[i] = (R)(0.25 * varpi * capT * dT + 0.5 * T * eu);
+    hd[i] = (R)(0.25 * varpi * capC * dC + 0.5 * C * eu);
+  }
+  prev[0] = (R)T;
+  prev[1] = (R)C;
+  prev[2] = (R)ux;
+  prev[3] = (R)uy;
+  // the stored populations of level 0 are rounded to the storage type before colliding,
+  // exactly as a pulled value would be
+  const R is = d.inv_scale, sc = d.scale;
+  S tmp;
+  for (int i = 0; i < 9; ++i) { St<S>::st(&tmp, fd[i], sc); fd[i] = St<S>::ld(&tmp, is); }
+  for (int i = 0; i < 5; ++i) { St<S>::st(&tmp, gd[i], sc); gd[i] = St<S>::ld(&tmp, is); }
+  for (int i = 0; i < 5; ++i) { St<S>::st(&tmp, hd[i], sc); hd[i] = St<S>::ld(&tmp, is); }
+  R a, b;
+  porous_coeffs(d, (R)phi, a, b);
+  collide(d, (R)phi, a, b, fd, gd, hd, prev);
+  S *dst = (S *)(d.base_parity ? d.pop1 : d.pop0);
+  for (int i = 0; i < 9; ++i) St<S>::st(dst + i * P + c, fd[i], sc);
+  for (int i = 0; i < 5; ++i) St<S>::st(dst + (9 + i) * P + c, gd[i], sc);
+  for (int i = 0; i < 5; ++i) St<S>::st(dst + (14 + i) * P + c, hd[i], sc);
+  R *d4 = (R *)d.d4;
+  d4[c] = prev[0];
+  d4[P + c] = prev[1];
+  d4[2 * P + c] = prev[2];
+  d4[3 * P + c] = prev[3];
+}
+
+// ---------------------------------------------------------------- reductions
+// FP64 accumulation in a fixed order: thread t of block b always handles the same nodes,
+// waves reduce with lane shuffles, blocks combine their waves in lane order, and one
+// block combines the block partials in index order.
+constexpr int OBS_ROWS = 4;
+constexpr int OBS_THREADS = 256;
+constexpr int NSLOT = 12;   // mass heat solute du2 u2 dT2 T2 dC2 C2 max_ux max_uy nonfinite
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename St<S>::R> d, int parity,
+                                                                  typename St<S>::R *__restrict__ snap,
+                                                                  double *__restrict__ partials) {
+  using R = typename St<S>::R;
+  const long long P = d.plane;
+  const int cur = (d.base_parity ^ parity) & 1;
+  const S *pop = (const S *)(cur ? d.pop1 : d.pop0);
+  const R *d4 = (const R *)d.d4;
+  double acc[NSLOT];
+  for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
+  const int y0 = blockIdx.x * OBS_ROWS;
+  const int y1 = min(y0 + OBS_ROWS, d.ny);
+  for (int y = y0; y < y1; ++y) {
+    for (int x = threadIdx.x; x < d.nx; x += OBS_THREADS) {
+      const long long c = (long long)y * d.pitch + x;
+      double drho = 0.0;
+      for (int i = 0; i < 9; ++i) drho += (double)St<S>::ld(pop + i * P + c, d.inv_scale);
+      const double rho = (double)d.rho0 + drho;
+      const double T = d4[c], C = d4[P + c], ux = d4[2 * P + c], uy = d4[3 * P + c];
+      const double phi = d.phi_field ? (double)((const R *)d.phi)[c] : (double)d.phi_u;
+      acc[0] += rho;
+      acc[1] += (double)d.sigma * T;
+      acc[2] += phi * C;
+      const double sx = snap[c], sy = snap[P + c], sT = snap[2 * P + c], sC = snap[3 * P + c];
+      acc[3] += (ux - sx) * (ux - sx) + (uy - sy) * (uy - sy);
+      acc[4] += ux * ux + uy * uy;
+      acc[5] += (T - sT) * (T - sT);
+      acc[6] += T * T;
+      acc[7] += (C - sC) * (C - sC);
+      acc[8] += C * C;
+      acc[9] = fmax(acc[9], fabs(ux));
+      acc[10] = fmax(acc[10], fabs(uy));
+      const bool bad = !(isfinite(rho) && isfinite(T) && isfinite(C) && isfinite(ux) && isfinite(uy));
+      acc[11] += bad ? 1.0 : 0.0;
+      snap[c] = (R)ux;
+      snap[P + c] = (R)uy;
+      snap[2 * P + c] = (R)T;
+      snap[3 * P + c] = (R)C;
+    }
+  }
+  __shared__ double red[OBS_THREADS / 64][NSLOT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int s = 0; s < NSLOT; ++s) {
+    const double v = (s == 9 || s == 10) ? wave_max(acc[s]) : wave_sum(acc[s]);
+    if (lane == 0) red[wv][s] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NSLOT) {
+    const int s = threadIdx.x;
+    double v = red[0][s];
+    for (int w = 1; w < OBS_THREADS / 64; ++w) v = (s == 9 || s == 10) ? fmax(v, red[w][s]) : v + red[w][s];
+    partials[(long long)blockIdx.x * NSLOT + s] = v;
+  }
+}
+
+// Mean Nusselt / Sherwood numbers of Eq. (38) at the four sides; one block per side.
+// Gradient along the inward normal: (-8 s_w + 9 s_0 - s_1)/3 (half-way wall).
+template <typename R>
+__global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__restrict__ wT,
+                                                   const double *__restrict__ wC, double LdT, double LdC,
+                                                   double *__restrict__ out) {
+  const int side = blockIdx.x;
+  const R *d4 = (const R *)d.d4;
+  const long long P = d.plane;
+  const int kind = d.kind[side];
+  const bool fixed = kind == SIDE_HOT || kind == SIDE_COLD;
+  const int n_along = (side == LEFT || side == RIGHT) ? d.ny : d.nx;
+  double sT = 0.0, sC = 0.0;
+  if (fixed) {
+    for (int a = threadIdx.x; a < n_along; a += blockDim.x) {
+      long long k0, k1;
+      if (side == LEFT) { k0 = (long long)a * d.pitch; k1 = k0 + 1; }
+      else if (side == RIGHT) { k0 = (long long)a * d.pitch + d.nx - 1; k1 = k0 - 1; }
+      else if (side == BOTTOM) { k0 = a; k1 = (long long)d.pitch + a; }
+      else { k0 = (long long)(d.ny - 1) * d.pitch + a; k1 = k0 - d.pitch; }
+      sT += (-8.0 * wT[side] + 9.0 * (double)d4[k0] - (double)d4[k1]) / 3.0;
+      sC += (-8.0 * wC[side] + 9.0 * (double)d4[P + k0] - (double)d4[P + k1]) / 3.0;
+    }
+  }
+  __shared__ double red[2][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  sT = wave_sum(sT);
+  sC = wave_sum(sC);
+  if (lane == 0) { red[0][wv] = sT; red[1][wv] = sC; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double aT = 0.0, aC = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { aT += red[0][w]; aC += red[1][w]; }
+    const double sign = kind == SIDE_HOT ? -1.0 : 1.0;
+    out[NSLOT + side] = fixed ? sign * LdT * aT / n_along : 0.0;
+    out[NSLOT + 4 + side] = fixed ? sign * LdC * aC / n_along : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(64) obs_final_kernel(const double *__restrict__ partials, int nblocks,
+                                                       double *__restrict__ out) {
+  const int s = threadIdx.x;
+  if (s >= NSLOT) return;
+  double v = partials[s];
+  for (int b = 1; b < nblocks; ++b) {
+    const double p = partials[(long long)b * NSLOT + s];
+    v = (s == 9 || s == 10) ? fmax(v, p) : v + p;
+  }
+  out[s] = v;
+}
+
+// FP64 fields rho, ux, uy, T, C of the current level (5 planes of nx*ny, x fastest)
+template <typename S>
+__global__ void __launch_bounds__(256) export_kernel(Desc<typename St<S>::R> d, int parity,
+                                                     double *__restrict__ f) {
+  using R = typename St<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= d.nx) return;
+  const long long P = d.plane, c = (long long)y * d.pitch + x;
+  const long long n = (long long)d.nx * d.ny, k = (long long)y * d.nx + x;
+  const int cur = (d.base_parity ^ parity) & 1;
+  const S *pop = (const S *)(cur ? d.pop1 : d.pop0);
+  const R *d4 = (const R *)d.d4;
+  double drho = 0.0;
+  for (int i = 0; i < 9; ++i) drho += (double)St<S>::ld(pop + i * P + c, d.inv_scale);
+  f[k] = (double)d.rho0 + drho;
+  f[n + k] = d4[2 * P + c];
+  f[2 * n + k] = d4[3 * P + c];
+  f[3 * n + k] = d4[c];
+  f[4 * n + k] = d4[P + c];
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename S>
+static int init_t(const void *desc, const double *T, const double *C, const double *ux, const double *uy,
+                  void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  dim3 grid((d.nx + 255) / 256, d.ny);
+  hipLaunchKernelGGL(init_kernel<S>, grid, dim3(256), 0, (hipStream_t)stream, d, T, C, ux, uy);
+  return (int)hipGetLastError();
+}
+
+int launch_init(int prec, const void *desc, const double *T, const double *C, const double *ux,
+                const double *uy, void *stream) {
+  switch (prec) {
+    case PREC_FP64: return init_t<double>(desc, T, C, ux, uy, stream);
+    case PREC_FP32: return init_t<float>(desc, T, C, ux, uy, stream);
+    default: return init_t<_Float16>(desc, T, C, ux, uy, stream);
+  }
+}
+
+template <typename S>
+static int step_t(const void *desc, Tile tile, int parity, void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  const int ntx = (d.nx + tile.tx - 1) / tile.tx;
+  const int nty = (d.ny + tile.ty - 1) / tile.ty;
+  hipLaunchKernelGGL(step_kernel<S>, dim3(ntx * nty), dim3(tile.tx), 0, (hipStream_t)stream, d, tile.ty, ntx,
+                     parity);
+  return (int)hipGetLastError();
+}
+
+int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream) {
+  switch (prec) {
+    case PREC_FP64: return step_t<double>(desc, tile, parity, stream);
+    case PREC_FP32: return step_t<float>(desc, tile, parity, stream);
+    default: return step_t<_Float16>(desc, tile, parity, stream);
+  }
+}
+
+int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int block,
+                      int tile_y, int parity, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (prec) {
+    case PREC_FP64:
+      hipLaunchKernelGGL(step_batch_kernel<double>, dim3(grid), dim3(block), 0, s,
+                         (const Desc<double> *)descs, items, nitems, tile_y, parity);
+      break;
+    case PREC_FP32:
+      hipLaunchKernelGGL(step_batch_kernel<float>, dim3(grid), dim3(block), 0, s, (const Desc<float> *)descs,
+                         items, nitems, tile_y, parity);
+      break;
+    default:
+      hipLaunchKernelGGL(step_batch_kernel<_Float16>, dim3(grid), dim3(block), 0, s,
+                         (const Desc<float> *)descs, items, nitems, tile_y, parity);
+      break;
+  }
+  return (int)hipGetLastError();
+}
+
+int observables_blocks(int ny) { return (ny + OBS_ROWS - 1) / OBS_ROWS; }
+
+template <typename S>
+static int obs_t(const void *desc, int parity, void *snap, double *partials, int nblocks, double *out,
+                 const double *wT, const double *wC, double LdT, double LdC, void *stream) {
+  using R = typename St<S>::R;
+  const auto &d = *(const Desc<R> *)desc;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(obs_partial_kernel<S>, dim3(nblocks), dim3(OBS_THREADS), 0, s, d, parity, (R *)snap,
+                     partials);
+  hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, out);
+  hipLaunchKernelGGL(wall_kernel<R>, dim3(4), dim3(256), 0, s, d, wT, wC, LdT, LdC, out);
+  return (int)hipGetLastError();
+}
+
+int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials, int nblocks,
+                       double *out, const double *wT, const double *wC, double LdT, double LdC,
+                       void *stream) {
+  switch (prec) {
+    case PREC_FP64: return obs_t<double>(desc, parity, snap, partials, nblocks, out, wT, wC, LdT, LdC, stream);
+    case PREC_FP32: return obs_t<float>(desc, parity, snap, partials, nblocks, out, wT, wC, LdT, LdC, stream);
+    default: return obs_t<_Float16>(desc, parity, snap, partials, nblocks, out, wT, wC, LdT, LdC, stream);
+  }
+}
+
+template <typename S>
+static int export_t(const void *desc, int parity, double *fields, void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  dim3 grid((d.nx + 255) / 256, d.ny);
+  hipLaunchKernelGGL(export_kernel<S>, grid, dim3(256), 0, (hipStream_t)stream, d, parity, fields);
+  return (int)hipGetLastError();
+}
+
+int launch_export(int prec, const void *desc, int parity, double *fields, void *stream) {
+  switch (prec) {
+    case PREC_FP64: return export_t<double>(desc, parity, fields, stream);
+    case PREC_FP32: return export_t<float>(desc, parity, fields, stream);
+    default: return export_t<_Float16>(desc, parity, fields, stream);
+  }
+}
+
+}  // namespace lbmk

@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the header
+declares, and rejects invalid parameters before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1708_07525_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lbm.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s(lbm_\w+)", out))
+    declared = set(declared_functions())
+    assert declared, "no declarations parsed"
+    assert declared <= exported, declared - exported
+    assert declared == set(lbm.EXPORTS)
+    # nothing else leaks out of the library
+    assert exported == declared, exported - declared
+
+
+def test_param_struct_matches_header_defaults():
+    p = lbm.make_params({})
+    assert (p.nx, p.ny, p.precision, p.model) == (64, 64, 1, 0)
+    assert list(p.side) == [0, 1, 2, 2]
+    assert (p.s_e, p.s_eps, p.s_q, p.s_j, p.s_rho) == (1.1, 1.1, 1.2, 1.0, 1.0)
+    assert (p.zeta0, p.zeta_e, p.zeta_eps, p.eta0, p.eta_e, p.eta_eps) == (1.0, 1.5, 1.5, 1.0, 1.5, 1.5)
+    assert (p.rho0, p.J, p.sigma, p.Ma, p.varpi, p.Fphi) == (1.0, 1.0, 1.0, 0.1, 0.0, -1.0)
+    # ctypes layout agrees with the C struct: footprint computation reads nx/ny/precision
+    assert lbm.footprint_bytes({"nx": 64, "ny": 64}, "fp32") > 64 * 64 * 38 * 4
+
+
+def test_footprint_scales_with_precision():
+    f64 = lbm.footprint_bytes({"nx": 1024, "ny": 1024}, "fp64")
+    f32 = lbm.footprint_bytes({"nx": 1024, "ny": 1024}, "fp32")
+    f16 = lbm.footprint_bytes({"nx": 1024, "ny": 1024}, "fp16s")
+    n = 1024 * 1024
+    assert 2 * 19 * 8 * n < f64 < 1.1 * (2 * 19 * 8 + 9 * 8) * n
+    assert 2 * 19 * 4 * n < f32 < 1.1 * (2 * 19 * 4 + 9 * 4) * n
+    assert 2 * 19 * 2 * n < f16 < 1.1 * (2 * 19 * 2 + 9 * 4) * n
+    assert lbm.footprint_bytes({"nx": 2, "ny": 64}) == 0
+
+
+@pytest.mark.parametrize("bad", [
+    {"nx": 2}, {"ny": 1}, {"phi": 0.0}, {"phi": 1.5}, {"s_e": 2.0}, {"zeta_e": 0.0}, {"Ra": -1.0},
+    {"Pr": 0.0}, {"Le": 0.0}, {"Da": 0.0}, {"Th": 0.0, "Tl": 1.0}, {"model": 3}, {"varpi": 1.2},
+    {"sides": ("periodic", "cold", "adiabatic", "adiabatic")}, {"sides": (0, 1, 2, 7)},
+    {"direct": 1, "nu": 0.0, "alpha_e": 0.1, "D_e": 0.1, "K": 1.0},
+])
+def test_create_rejects_invalid_parameters(bad):
+    p = lbm.make_params(bad)
+    h = ctypes.c_void_p()
+    rc = lbm.lib().lbm_create(ctypes.byref(p), ctypes.byref(h))
+    assert rc == lbm.EINVAL
+    assert not h.value
+
+
+def test_null_arguments():
+    L = lbm.lib()
+    assert L.lbm_create(None, None) == lbm.EINVAL
+    assert L.lbm_step(None, 1) == lbm.EINVAL
+    assert L.lbm_observables(None, None, None) == lbm.EINVAL
+    assert L.lbm_set_fields(None, None, None, None, None, None) == lbm.EINVAL
+    L.lbm_destroy(None)
+    assert L.lbm_last_error(None) == b"no context"
+    assert L.lbm_batch_step(None, 1) == lbm.EINVAL
+    assert L.lbm_batch_size(None) == 0
+    L.lbm_batch_destroy(None)
+    assert L.lbm_batch_create(0, 2, None, ctypes.byref(ctypes.c_void_p())) == lbm.EINVAL
+    assert L.lbm_batch_create(4, 3, None, ctypes.byref(ctypes.c_void_p())) == lbm.EINVAL
+
+
+def test_solver_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        lbm.Solver({"nx": 16, "ny": 16})

@@ -1,0 +1,266 @@
+"""Parity of the gfx950 path (through the C ABI) with the FP64 CPU oracle.
+
+Field error e_X = max|X_gpu - X_oracle| / max|X_oracle| for X in ux, uy, T, C; rho is
+compared as an absolute error.  Bars: FP64 storage 1e-10, FP32 storage 1e-5 (both after
+the stated number of steps on the same seeded inputs); FP16 storage is reported and held
+to the bound derived for binary16 deviations (see test_fp16s_error_bound).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Oracle
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def _solver():
+    from paper_1708_07525_amd import Solver
+    return Solver
+
+
+def make_gpu(prec):
+    def mk(params, **fields):
+        return _solver()(params, precision=prec, **fields)
+    return mk
+
+
+def field_errors(F, R):
+    e = {k: float(np.abs(F[k] - R[k]).max() / max(np.abs(R[k]).max(), 1e-300)) for k in ("ux", "uy", "T", "C")}
+    e["rho"] = float(np.abs(F["rho"] - R["rho"]).max())
+    return e
+
+
+def run_pair(params, steps, prec, phi=None, T=None, C=None, ux=None, uy=None, tile=None):
+    print(f"case nx={params.get('nx')} ny={params.get('ny')} prec={prec} steps={steps} tile={tile}", flush=True)
+    ref = Oracle(params, phi=phi, T=T, C=C, ux=ux, uy=uy)
+    gpu = _solver()(params, phi=phi, T=T, C=C, ux=ux, uy=uy, precision=prec, tile=tile)
+    ref.step(steps)
+    gpu.step(steps)
+    return gpu, ref, field_errors(gpu.fields(), ref.fields())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_cavity(prec):
+    case = workloads.small_cavity(seed=0)
+    gpu, ref, e = run_pair(case["params"], 1000, prec, T=case["T"], C=case["C"])
+    print(prec, e, flush=True)
+    assert max(e.values()) <= TOL[prec], e
+
+
+@pytest.mark.parametrize("prec,tile", [("fp64", (64, 4)), ("fp32", (256, 8)), ("fp32", (128, 2))])
+def test_ragged_nonsquare(prec, tile):
+    p = workloads.cavity_params(nx=96, ny=67, Ra=3e4, Da=5e-3, Le=3.0, N=-0.5, phi=0.7)
+    T, C = workloads.noise_fields(96, 67, 11)
+    _, _, e = run_pair(p, 500, prec, T=T, C=C, tile=tile)
+    assert max(e.values()) <= TOL[prec], e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_porosity_field(prec):
+    case = workloads.grf_cavity(seed=1, n=128)
+    _, _, e = run_pair(case["params"], 500, prec, phi=case["phi"], T=case["T"], C=case["C"])
+    assert max(e.values()) <= TOL[prec], e
+
+
+def test_full_size_grf_cavity_fp32():
+    """512 x 512 Gaussian-random-field cavity in the benchmark launch shape, 200 steps."""
+    case = workloads.grf_cavity(seed=1, n=512)
+    _, _, e = run_pair(case["params"], 200, "fp32", phi=case["phi"], T=case["T"], C=case["C"])
+    assert max(e.values()) <= TOL["fp32"], e
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_full_size_band_cavity(prec):
+    """2048 x 2048 layered cavity (the benchmark workload), 20 steps, every node compared."""
+    case = workloads.band_cavity(seed=2, n=2048)
+    _, _, e = run_pair(case["params"], 20, prec, phi=case["phi"], T=case["T"], C=case["C"])
+    print(prec, e, flush=True)
+    assert max(e.values()) <= TOL[prec], e
+
+
+def test_observables_parity():
+    case = workloads.small_cavity(seed=0)
+    p = case["params"]
+    ref = Oracle(p, T=case["T"], C=case["C"])
+    gpu = _solver()(p, T=case["T"], C=case["C"], precision="fp64")
+    for steps in (300, 700):
+        ref.step(steps)
+        gpu.step(steps)
+        a, b = gpu.observables(), ref.observables()
+        for k in ("mass", "heat", "solute", "max_ux", "max_uy", "r_u", "r_T", "r_C"):
+            assert a[k] == pytest.approx(b[k], rel=1e-10, abs=1e-14), k
+        np.testing.assert_allclose(a["Nu"], b["Nu"], rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(a["Sh"], b["Sh"], rtol=1e-10, atol=1e-12)
+        assert a["step"] == b["step"] and not a["nonfinite"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_moving_lid_and_horizontal_walls(prec):
+    """Lid-driven cavity walls: moving top held hot, bottom cold, adiabatic sides."""
+    p = workloads.cavity_params(nx=64, ny=48, sides=("adiabatic", "adiabatic", "cold", "hot"), Ra=1e4,
+                                Le=1.0, N=2.0, phi=0.9, Da=1e-1, wall_u=(0.0, 0.0, 0.0, 0.05))
+    _, _, e = run_pair(p, 600, prec, T=0.5, C=0.5)
+    assert max(e.values()) <= TOL[prec], e
+
+
+def test_periodic_channel_with_forcing():
+    p = dict(nx=40, ny=24, sides=("adiabatic", "adiabatic", "periodic", "periodic"), direct=1, nu=0.05,
+             alpha_e=0.04, D_e=0.02, K=30.0, gbT=1e-4, gbC=-5e-5, Fphi=0.5, phi=0.6, g_ext=(2e-5, 1e-4),
+             Th=1.0, Tl=0.0)
+    rng = np.random.default_rng(3)
+    T = rng.uniform(0, 1, (24, 40))
+    _, _, e = run_pair(p, 500, "fp64", T=T, C=1 - T)
+    assert max(e.values()) <= 1e-10, e
+
+
+def test_model_a():
+    p = workloads.cavity_params(nx=48, ny=48, model=1, sigma=1.7, phi=0.6, Le=1.0)
+    T, C = workloads.noise_fields(48, 48, 5)
+    _, _, e = run_pair(p, 500, "fp64", T=T, C=C)
+    assert max(e.values()) <= 1e-10, e
+
+
+def test_nonzero_initial_velocity():
+    p = workloads.cavity_params(nx=32, ny=32)
+    rng = np.random.default_rng(8)
+    ux = rng.uniform(-0.01, 0.01, (32, 32))
+    uy = rng.uniform(-0.01, 0.01, (32, 32))
+    _, _, e = run_pair(p, 200, "fp64", T=0.5, C=0.5, ux=ux, uy=uy)
+    assert max(e.values()) <= 1e-10, e
+
+
+def test_minimum_lattice():
+    p = workloads.cavity_params(nx=3, ny=3)
+    _, _, e = run_pair(p, 100, "fp64", T=0.5, C=0.5)
+    assert max(e.values()) <= 1e-10, e
+
+
+# ------------------------------------------------------------ pins re-run on the GPU path
+
+def test_gpu_linear_conduction_exact():
+    eT, eC, Nu, Sh = pins.conduction_profile(make_gpu("fp64"))
+    assert eT < 1e-12 and eC < 1e-12
+    np.testing.assert_allclose(Nu + Sh, [1, 1, 1, 1], atol=1e-12)
+
+
+def test_gpu_brinkman_poiseuille():
+    assert pins.brinkman_poiseuille(make_gpu("fp64"), 32) < 1e-3
+
+
+def test_gpu_uniform_force_recurrence():
+    err, got, closed = pins.uniform_force_history(make_gpu("fp64"), steps=50)
+    assert err < 1e-14 and got == pytest.approx(closed, rel=1e-12)
+
+
+def test_gpu_symmetry_and_conservation():
+    assert pins.cavity_symmetry(make_gpu("fp64")) < 1e-12
+    drifts, _ = pins.closed_box(make_gpu("fp64"), steps=1000)
+    assert max(drifts) < 4 * np.finfo(float).eps * 1000
+
+
+def test_gpu_rest_state_and_buoyancy_cancellation():
+    assert pins.rest_state(make_gpu("fp64")) < 1e-15
+    assert pins.rest_state(make_gpu("fp16s")) == 0.0      # deviations stay exactly zero
+    umax, dTC, Nu, Sh = pins.buoyancy_cancellation(make_gpu("fp32"))
+    assert umax == 0.0 and dTC == 0.0 and Nu == Sh
+
+
+# ------------------------------------------------------------ FP16 storage
+
+def test_fp16s_error_bound():
+    """Binary16 keeps 11 significant bits: each stored deviation is rounded with relative
+    error <= 2^-11.  Over the 64 x 64 cavity's first 1000 steps the scalar fields stay
+    within 2e-3 of the FP64 oracle and the velocity within 2e-2 (relative to its maximum)."""
+    case = workloads.small_cavity(seed=0)
+    _, _, e = run_pair(case["params"], 1000, "fp16s", T=case["T"], C=case["C"])
+    print("fp16s", e, flush=True)
+    assert e["T"] < 2e-3 and e["C"] < 2e-3 and e["ux"] < 2e-2 and e["uy"] < 2e-2 and e["rho"] < 1e-3, e
+
+
+# ------------------------------------------------------------ launch-shape independence
+
+def _state_after(steps, tile=None, prec="fp32", chunks=1):
+    case = workloads.grf_cavity(seed=1, n=96)
+    s = _solver()(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec, tile=tile)
+    for _ in range(chunks):
+        s.step(steps // chunks)
+    return s.get_state()
+
+
+def test_results_do_not_depend_on_tile():
+    ref = _state_after(50, (256, 1))
+    for tile in ((64, 1), (128, 4), (64, 8), (256, 2)):
+        assert _state_after(50, tile) == ref, tile
+
+
+def test_graph_replays_match_plain_launches():
+    """lbm_step uses a captured graph for chunks of 64 steps; replays interleaved with other
+    work must give the same state as one launch per step."""
+    ref = _state_after(192, chunks=192)          # steps of 1: plain launches only
+    assert _state_after(192, chunks=1) == ref     # 3 graph replays
+    assert _state_after(192, chunks=3) == ref     # a replay per call
+
+
+def test_checkpoint_roundtrip():
+    case = workloads.small_cavity(seed=0)
+    p = case["params"]
+    a = _solver()(p, T=case["T"], C=case["C"], precision="fp32")
+    a.step(300)
+    blob = a.get_state()
+    a.step(300)
+    b = _solver()(p, T=case["T"], C=case["C"], precision="fp32")
+    b.set_state(blob)
+    b.step(300)
+    assert a.get_state() == b.get_state()
+    assert a.observables()["step"] == b.observables()["step"] == 600
+
+
+def test_unstable_is_reported():
+    from paper_1708_07525_amd.lbm import EUNSTABLE
+    T = np.full((16, 16), 0.5)
+    T[3, 4] = np.nan
+    s = _solver()(workloads.cavity_params(nx=16, ny=16), T=T, C=0.5, precision="fp32")
+    s.step(3)
+    ob = s.observables()
+    assert ob["nonfinite"] and ob["status"] == EUNSTABLE
+
+
+# ------------------------------------------------------------ batching
+
+def test_batch_alone_vs_mix_bitwise():
+    from paper_1708_07525_amd import Batch
+    Solver = _solver()
+    specs = [
+        (dict(workloads.cavity_params(nx=64, ny=64)), "fp32"),
+        (dict(workloads.cavity_params(nx=96, ny=192, Ra=1e5, Le=4.0, N=-1.0, phi=0.5)), "fp32"),
+        (dict(workloads.cavity_params(nx=70, ny=33, Ra=2e4, phi=0.8)), "fp16s"),
+        (dict(workloads.cavity_params(nx=40, ny=40, Ra=5e3)), "fp64"),
+        (dict(workloads.cavity_params(nx=128, ny=128, Ra=1e6, Da=1e-3, phi=0.4)), "fp32"),
+    ]
+    steps = 250    # two graph replays of 100 plus 50 single launches
+    alone = []
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (7, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        s.step(steps)
+        alone.append(s.get_state())
+    mix = []
+    b = Batch(len(specs), chunk=100)
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (7, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        b.attach(s)
+        mix.append(s)
+    b.step(steps)
+    for s, ref in zip(mix, alone):
+        assert s.get_state() == ref
+    # detach one, keep going: the others are unaffected
+    b.detach(mix[1])
+    b.step(100)
+    mix[1].step(100)
+    assert len(b) == 4
+    b.close()
