@@ -35,7 +35,27 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="", help="tile_x,tile_y (default: library default)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
+                         "(reference kernel for scaling the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_probe_MiB": mib, "ms_per_copy": ms,
+                      "GB_s_read_plus_write": 2 * mib * 1048576 / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def timed_run(case, prec, steps, warmup, tile=None):
@@ -88,6 +108,9 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     case = workloads.band_cavity(seed=2, n=a.n)
     nodes = a.n * a.n
     tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None

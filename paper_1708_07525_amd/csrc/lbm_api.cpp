@@ -274,6 +274,8 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     D.cb = (R)(p->Fphi < 0 ? 1.75 / std::sqrt(150.0 * Ks) : p->Fphi / std::sqrt(Ks));
     D.kg3 = (R)(p->model == 0 ? 5.0 * d.varpi - 4.0 * p->sigma : (5.0 * d.varpi - 4.0) * p->sigma);
     D.c5v = (R)(5.0 * d.varpi);
+    D.inv_phi_u = (R)(1.0 / phi);
+    D.kh3_u = (R)(p->model == 0 ? 5.0 * d.varpi - 4.0 * phi : (5.0 * d.varpi - 4.0) * phi);
     const double capT = p->model == 0 ? 1.0 : p->sigma;
     const double capC = p->model == 0 ? 1.0 : p->phi;
     for (int s = 0; s < 4; ++s) {
@@ -452,7 +454,9 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = put(uy, 0.0, 3);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->phi(), 0, plane_bytes, c->stream);
+  // every buffer starts zeroed, row and plane padding included, so that checkpoints
+  // of equal states are equal byte for byte
+  if (e == hipSuccess) e = hipMemsetAsync(c->base, 0, c->lay.off_small, c->stream);
   if (e == hipSuccess && phi) {
     // porosity plane in the arithmetic type, row pitch applied
     const size_t rs = real_size(c->prec);

@@ -9,7 +9,7 @@
 //   d4      4 planes of the fields of the previous step: T, C, ux, uy (FP64 for FP64
 //           storage, FP32 otherwise).  Read and rewritten in place by the node itself.
 //   phi     1 plane of porosity (only when the porosity is a field).
-//   snap    4 planes: residual snapshot of ux, uy, T, C.
+//   snap    4 planes: residual snapshot of T, C, ux, uy.
 //   Populations are stored as deviations from the rest state (rho0, T0, C0).
 #pragma once
 #include <stdint.h>
@@ -41,6 +41,7 @@ struct Desc {
   R ca, cb;                // porosity field: a = ca (1-phi)^2/phi^2; b = cb (1-phi)/phi^2 (Ergun)
                            // or cb (1-phi)/sqrt(phi) (fixed F_phi)
   R kg3, c5v;              // n3eq - n3ref = kg3 (T - T0) for g; c5v = 5 varpi
+  R inv_phi_u, kh3_u;      // uniform porosity: 1/phi and the h energy factor (as kg3 for g)
   R wT[4], wC[4];          // anti-bounce-back constants (deviation form) per side
   R uw[4];                 // 6 rho0 u_wall per side (moving-wall term of the bounce-back)
   R scale, inv_scale;      // FP16 pre-scale (1 for FP32/FP64)

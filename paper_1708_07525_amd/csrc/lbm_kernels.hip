@@ -75,7 +75,7 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R jy = (fd[2] - fd[4]) + (fd[5] + fd[6]) - (fd[7] + fd[8]);
   const R sg = gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
   const R sh = hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
-  const R inv_phi = one / phi;
+  const R inv_phi = d.phi_field ? one / phi : d.inv_phi_u;
   const R dT = sg * d.inv_sigma;          // T - T0
   const R dC = sh * inv_phi;              // C - C0
   const R T = d.T0 + dT, C = d.C0 + dC;
@@ -139,7 +139,6 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R a8 = p8 * R(0.25);
   const R axis = a0 - a1 - R(2) * a2;
   const R diag = a0 + R(2) * a1 + a2;
-  fd[0] = a0 - R(4) * a1 + R(4) * a2;
   fd[1] = axis + a3 - R(2) * a4 + a7;
   fd[2] = axis + a5 - R(2) * a6 - a7;
   fd[3] = axis - a3 + R(2) * a4 + a7;
@@ -148,13 +147,16 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   fd[6] = diag - a3 - a4 + a5 + a6 - a8;
   fd[7] = diag - a3 - a4 - a5 - a6 + a8;
   fd[8] = diag + a3 + a4 - a5 - a6 - a8;
+  // rest population from the conserved density: keeps sum f* = sum f up to one rounding
+  // (M^-1 with rounded 1/9, 1/36 would otherwise drift the mass by a fixed bias per step)
+  fd[0] = drho - ((fd[1] + fd[2]) + (fd[3] + fd[4])) - ((fd[5] + fd[6]) + (fd[7] + fd[8]));
 
   // ---- D2Q5 for T (Eq. 21) and C (Eq. 22)
   // source moments N S~ = (0, d(T ux)/dt, d(T uy)/dt, 0, 0) from Eq. (27)
   const R TuX = T * ux, TuY = T * uy, CuX = C * ux, CuY = C * uy;
   const R STx = TuX - prev[0] * prev[2], STy = TuY - prev[0] * prev[3];
   const R SCx = CuX - prev[1] * prev[2], SCy = CuY - prev[1] * prev[3];
-  const R kh3 = d.model == 0 ? (d.c5v - R(4) * phi) : (d.c5v - R(4)) * phi;
+  const R kh3 = !d.phi_field ? d.kh3_u : (d.model == 0 ? (d.c5v - R(4) * phi) : (d.c5v - R(4)) * phi);
   {
     const R n0 = sg;
     const R n1 = gd[1] - gd[3], n2 = gd[2] - gd[4];
@@ -165,11 +167,11 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
     const R q3 = n3 - d.z_e * (n3 - d.kg3 * dT);
     const R q4 = n4 - d.z_eps * n4;
     const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
-    gd[0] = b0 - R(4) * b3;
     gd[1] = b0 + b1 + b3 + b4;
     gd[2] = b0 + b2 + b3 - b4;
     gd[3] = b0 - b1 + b3 + b4;
     gd[4] = b0 - b2 + b3 - b4;
+    gd[0] = n0 - ((gd[1] + gd[2]) + (gd[3] + gd[4]));   // conserved scalar, as for f
   }
   {
     const R eD = d.e_D;
@@ -182,11 +184,11 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
     const R q3 = n3 - d.e_e * (n3 - kh3 * dC);
     const R q4 = n4 - d.e_eps * n4;
     const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
-    hd[0] = b0 - R(4) * b3;
     hd[1] = b0 + b1 + b3 + b4;
     hd[2] = b0 + b2 + b3 - b4;
     hd[3] = b0 - b1 + b3 + b4;
     hd[4] = b0 - b2 + b3 - b4;
+    hd[0] = n0 - ((hd[1] + hd[2]) + (hd[3] + hd[4]));
   }
   prev[0] = T;
   prev[1] = C;
@@ -211,110 +213,197 @@ __device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &
   b = d.ergun ? d.cb * q * ip * ip : d.cb * q * rsqrt_(phi);
 }
 
-// ---------------------------------------------------------------- one node of a step
+// ---------------------------------------------------------------- buffer memory access
+// The step kernels address every plane through buffer resources: the plane offset is a
+// uniform (scalar) byte offset and each lane carries one 32-bit byte offset, which keeps
+// 64-bit address arithmetic out of the per-node code.  Out-of-range accesses are dropped
+// by the hardware range check (loads return 0).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit dwords (gfx9 family)
+constexpr int kStoreAux = 2;             // non-temporal stores: the next read is a full step later
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
 template <typename S>
-__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const S *__restrict__ src,
-                                          S *__restrict__ dst, int x, int y) {
+struct BufIO;
+template <>
+struct BufIO<float> {
+  static __device__ __forceinline__ float ld(rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(float x, rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, kStoreAux);
+  }
+};
+template <>
+struct BufIO<double> {
+  typedef unsigned int V2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ double ld(rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(double x, rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, kStoreAux);
+  }
+};
+template <>
+struct BufIO<_Float16> {
+  static __device__ __forceinline__ _Float16 ld(rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(_Float16 x, rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kStoreAux);
+  }
+};
+
+template <typename S>
+__device__ __forceinline__ typename St<S>::R to_real(S v, typename St<S>::R inv_scale);
+template <>
+__device__ __forceinline__ double to_real(double v, double) { return v; }
+template <>
+__device__ __forceinline__ float to_real(float v, float) { return v; }
+template <>
+__device__ __forceinline__ float to_real(_Float16 v, float inv_scale) { return (float)v * inv_scale; }
+
+template <typename S>
+__device__ __forceinline__ S from_real(typename St<S>::R v, typename St<S>::R scale);
+template <>
+__device__ __forceinline__ double from_real(double v, double) { return v; }
+template <>
+__device__ __forceinline__ float from_real(float v, float) { return v; }
+template <>
+__device__ __forceinline__ _Float16 from_real(float v, float scale) { return (_Float16)(v * scale); }
+
+// resources of one cavity for one step
+struct StepRes {
+  rsrc_t src, dst, d4, phi;
+};
+
+template <typename S>
+__device__ __forceinline__ StepRes step_resources(const Desc<typename St<S>::R> &d, int cur) {
   using R = typename St<S>::R;
-  const long long P = d.plane;
+  const uint32_t pb = (uint32_t)d.plane * (uint32_t)sizeof(S);
+  const uint32_t pr = (uint32_t)d.plane * (uint32_t)sizeof(R);
+  StepRes r;
+  r.src = make_rsrc(cur ? d.pop1 : d.pop0, NPOP * pb);
+  r.dst = make_rsrc(cur ? d.pop0 : d.pop1, NPOP * pb);
+  r.d4 = make_rsrc(d.d4, ND4 * pr);
+  r.phi = make_rsrc(d.phi, pr);
+  return r;
+}
+
+// ---------------------------------------------------------------- one node of a step
+// INTERIOR: every upstream node of the tile lies inside the domain (no wall link, no wrap).
+template <typename S, bool INTERIOR>
+__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y) {
+  using R = typename St<S>::R;
+  using IO = BufIO<S>;
+  constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
+  const uint32_t PB = (uint32_t)d.plane * ES;        // plane stride in bytes (populations)
+  const uint32_t PR = (uint32_t)d.plane * RS;        // plane stride in bytes (fields)
   const int pitch = d.pitch, nx = d.nx, ny = d.ny;
-  const long long c = (long long)y * pitch + x;
-  // upstream coordinates, periodic wrap, and whether they lie inside
-  const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
-  const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
-  const int xm = x > 0 ? x - 1 : nx - 1, xp = x < nx - 1 ? x + 1 : 0;
-  const long long rm = (long long)(y > 0 ? y - 1 : ny - 1) * pitch;
-  const long long rp = (long long)(y < ny - 1 ? y + 1 : 0) * pitch;
-  const long long r0 = (long long)y * pitch;
-  const R is = d.inv_scale;
-  // source index of each direction (own index when the link crosses a wall)
-  const long long i1 = okxm ? r0 + xm : c;
-  const long long i2 = okym ? rm + x : c;
-  const long long i3 = okxp ? r0 + xp : c;
-  const long long i4 = okyp ? rp + x : c;
+  const uint32_t c = (uint32_t)y * pitch + x;
+  bool okxm = true, okxp = true, okym = true, okyp = true;
+  uint32_t xm = x - 1, xp = x + 1, rm = (uint32_t)(y - 1) * pitch, rp = (uint32_t)(y + 1) * pitch;
+  if (!INTERIOR) {
+    okxm = (x > 0) | d.perx;
+    okxp = (x < nx - 1) | d.perx;
+    okym = (y > 0) | d.pery;
+    okyp = (y < ny - 1) | d.pery;
+    xm = x > 0 ? x - 1 : nx - 1;
+    xp = x < nx - 1 ? x + 1 : 0;
+    rm = (uint32_t)(y > 0 ? y - 1 : ny - 1) * pitch;
+    rp = (uint32_t)(y < ny - 1 ? y + 1 : 0) * pitch;
+  }
+  const uint32_t r0 = (uint32_t)y * pitch;
   const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
-  const long long i5 = ok5 ? rm + xm : c;
-  const long long i6 = ok6 ? rm + xp : c;
-  const long long i7 = ok7 ? rp + xp : c;
-  const long long i8 = ok8 ? rp + xm : c;
-  // plane read by each direction: its own, or the opposite one for a bounce-back
+  // byte offset of the value pulled into direction i, relative to plane min(i, opp):
+  // the upstream node in plane i, or this node in plane opp(i) for a bounce-back
+  auto pull = [&](bool ok, uint32_t up, int i, int o) -> uint32_t {
+    const int lo = i < o ? i : o;
+    const uint32_t own = c * ES + (uint32_t)(o - lo) * PB;
+    const uint32_t nb = up * ES + (uint32_t)(i - lo) * PB;
+    return INTERIOR ? up * ES : (ok ? nb : own);
+  };
+  // for INTERIOR the plane is i itself
+  auto plane = [&](int i, int o) -> uint32_t { return (uint32_t)(INTERIOR ? i : (i < o ? i : o)) * PB; };
+  const uint32_t o1 = pull(okxm, r0 + xm, 1, 3), o3 = pull(okxp, r0 + xp, 3, 1);
+  const uint32_t o2 = pull(okym, rm + x, 2, 4), o4 = pull(okyp, rp + x, 4, 2);
+  const uint32_t o5 = pull(ok5, rm + xm, 5, 7), o7 = pull(ok7, rp + xp, 7, 5);
+  const uint32_t o6 = pull(ok6, rm + xp, 6, 8), o8 = pull(ok8, rp + xm, 8, 6);
+  const R is = d.inv_scale;
   R fd[9], gd[5], hd[5], prev[4];
-  fd[0] = St<S>::ld(src + c, is);
-  fd[1] = St<S>::ld(src + (okxm ? 1 : 3) * P + i1, is);
-  fd[2] = St<S>::ld(src + (okym ? 2 : 4) * P + i2, is);
-  fd[3] = St<S>::ld(src + (okxp ? 3 : 1) * P + i3, is);
-  fd[4] = St<S>::ld(src + (okyp ? 4 : 2) * P + i4, is);
-  fd[5] = St<S>::ld(src + (ok5 ? 5 : 7) * P + i5, is);
-  fd[6] = St<S>::ld(src + (ok6 ? 6 : 8) * P + i6, is);
-  fd[7] = St<S>::ld(src + (ok7 ? 7 : 5) * P + i7, is);
-  fd[8] = St<S>::ld(src + (ok8 ? 8 : 6) * P + i8, is);
-  const S *g = src + 9 * P;
-  const S *h = src + 14 * P;
-  gd[0] = St<S>::ld(g + c, is);
-  hd[0] = St<S>::ld(h + c, is);
-  gd[1] = St<S>::ld(g + (okxm ? 1 : 3) * P + i1, is);
-  hd[1] = St<S>::ld(h + (okxm ? 1 : 3) * P + i1, is);
-  gd[2] = St<S>::ld(g + (okym ? 2 : 4) * P + i2, is);
-  hd[2] = St<S>::ld(h + (okym ? 2 : 4) * P + i2, is);
-  gd[3] = St<S>::ld(g + (okxp ? 3 : 1) * P + i3, is);
-  hd[3] = St<S>::ld(h + (okxp ? 3 : 1) * P + i3, is);
-  gd[4] = St<S>::ld(g + (okyp ? 4 : 2) * P + i4, is);
-  hd[4] = St<S>::ld(h + (okyp ? 4 : 2) * P + i4, is);
-  R *d4 = (R *)d.d4;
-  prev[0] = d4[c];
-  prev[1] = d4[P + c];
-  prev[2] = d4[2 * P + c];
-  prev[3] = d4[3 * P + c];
+  fd[0] = to_real<S>(IO::ld(rs.src, c * ES, 0), is);
+  fd[1] = to_real<S>(IO::ld(rs.src, o1, plane(1, 3)), is);
+  fd[2] = to_real<S>(IO::ld(rs.src, o2, plane(2, 4)), is);
+  fd[3] = to_real<S>(IO::ld(rs.src, o3, plane(3, 1)), is);
+  fd[4] = to_real<S>(IO::ld(rs.src, o4, plane(4, 2)), is);
+  fd[5] = to_real<S>(IO::ld(rs.src, o5, plane(5, 7)), is);
+  fd[6] = to_real<S>(IO::ld(rs.src, o6, plane(6, 8)), is);
+  fd[7] = to_real<S>(IO::ld(rs.src, o7, plane(7, 5)), is);
+  fd[8] = to_real<S>(IO::ld(rs.src, o8, plane(8, 6)), is);
+  // g and h use the same offsets from planes 9.. and 14..
+  gd[0] = to_real<S>(IO::ld(rs.src, c * ES, 9 * PB), is);
+  hd[0] = to_real<S>(IO::ld(rs.src, c * ES, 14 * PB), is);
+  gd[1] = to_real<S>(IO::ld(rs.src, o1, 9 * PB + plane(1, 3)), is);
+  hd[1] = to_real<S>(IO::ld(rs.src, o1, 14 * PB + plane(1, 3)), is);
+  gd[2] = to_real<S>(IO::ld(rs.src, o2, 9 * PB + plane(2, 4)), is);
+  hd[2] = to_real<S>(IO::ld(rs.src, o2, 14 * PB + plane(2, 4)), is);
+  gd[3] = to_real<S>(IO::ld(rs.src, o3, 9 * PB + plane(3, 1)), is);
+  hd[3] = to_real<S>(IO::ld(rs.src, o3, 14 * PB + plane(3, 1)), is);
+  gd[4] = to_real<S>(IO::ld(rs.src, o4, 9 * PB + plane(4, 2)), is);
+  hd[4] = to_real<S>(IO::ld(rs.src, o4, 14 * PB + plane(4, 2)), is);
+  const uint32_t cr = c * RS;
+  prev[0] = BufIO<R>::ld(rs.d4, cr, 0);
+  prev[1] = BufIO<R>::ld(rs.d4, cr, PR);
+  prev[2] = BufIO<R>::ld(rs.d4, cr, 2 * PR);
+  prev[3] = BufIO<R>::ld(rs.d4, cr, 3 * PR);
   R phi = d.phi_u;
-  if (d.phi_field) phi = ((const R *)d.phi)[c];
-  // wall rules for links whose upstream node is outside
-  if (!(okxm & okxp & okym & okyp)) {
+  if (d.phi_field) phi = BufIO<R>::ld(rs.phi, cr, 0);
+  if (!INTERIOR && !(okxm & okxp & okym & okyp)) {
     // f: half-way bounce-back with the moving-wall term 6 w_i rho0 e_i.u_w; the wall
-    // velocity is tangential: along x for the bottom/top sides, along y for left/right
-    const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    // velocity is tangential: along x for the bottom/top sides, along y for left/right.
+    // The axis links carry no tangential component.
+    const R w5 = R(1.0 / 36.0);
     const R uB = d.uw[BOTTOM], uT = d.uw[TOP], uL = d.uw[LEFT], uR = d.uw[RIGHT];
-    // f5 (e = (1, 1)): from below -> bottom wall (e.u = uB); else from the left (uL)
     if (!ok5) fd[5] += w5 * (!okym ? uB : uL);
     if (!ok6) fd[6] += w5 * (!okym ? -uB : uR);
     if (!ok7) fd[7] += w5 * (!okyp ? -uT : -uR);
     if (!ok8) fd[8] += w5 * (!okyp ? uT : -uL);
-    (void)w1;  // the axis links carry no tangential component
     // g, h: anti-bounce-back at a side held at fixed T/C, bounce-back at a zero-flux side
-    if (!okxm) {
-      const bool ab = d.kind[LEFT] != SIDE_ADIABATIC;
-      gd[1] = ab ? d.wT[LEFT] - gd[1] : gd[1];
-      hd[1] = ab ? d.wC[LEFT] - hd[1] : hd[1];
+    if (!okxm && d.kind[LEFT] != SIDE_ADIABATIC) {
+      gd[1] = d.wT[LEFT] - gd[1];
+      hd[1] = d.wC[LEFT] - hd[1];
     }
-    if (!okym) {
-      const bool ab = d.kind[BOTTOM] != SIDE_ADIABATIC;
-      gd[2] = ab ? d.wT[BOTTOM] - gd[2] : gd[2];
-      hd[2] = ab ? d.wC[BOTTOM] - hd[2] : hd[2];
+    if (!okym && d.kind[BOTTOM] != SIDE_ADIABATIC) {
+      gd[2] = d.wT[BOTTOM] - gd[2];
+      hd[2] = d.wC[BOTTOM] - hd[2];
     }
-    if (!okxp) {
-      const bool ab = d.kind[RIGHT] != SIDE_ADIABATIC;
-      gd[3] = ab ? d.wT[RIGHT] - gd[3] : gd[3];
-      hd[3] = ab ? d.wC[RIGHT] - hd[3] : hd[3];
+    if (!okxp && d.kind[RIGHT] != SIDE_ADIABATIC) {
+      gd[3] = d.wT[RIGHT] - gd[3];
+      hd[3] = d.wC[RIGHT] - hd[3];
     }
-    if (!okyp) {
-      const bool ab = d.kind[TOP] != SIDE_ADIABATIC;
-      gd[4] = ab ? d.wT[TOP] - gd[4] : gd[4];
-      hd[4] = ab ? d.wC[TOP] - hd[4] : hd[4];
+    if (!okyp && d.kind[TOP] != SIDE_ADIABATIC) {
+      gd[4] = d.wT[TOP] - gd[4];
+      hd[4] = d.wC[TOP] - hd[4];
     }
   }
   R a, b;
   porous_coeffs(d, phi, a, b);
   collide(d, phi, a, b, fd, gd, hd, prev);
   const R sc = d.scale;
+  const uint32_t co = c * ES;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) St<S>::st(dst + i * P + c, fd[i], sc);
+  for (int i = 0; i < 9; ++i) IO::st(from_real<S>(fd[i], sc), rs.dst, co, (uint32_t)i * PB);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) St<S>::st(dst + (9 + i) * P + c, gd[i], sc);
+  for (int i = 0; i < 5; ++i) IO::st(from_real<S>(gd[i], sc), rs.dst, co, (uint32_t)(9 + i) * PB);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) St<S>::st(dst + (14 + i) * P + c, hd[i], sc);
-  d4[c] = prev[0];
-  d4[P + c] = prev[1];
-  d4[2 * P + c] = prev[2];
-  d4[3 * P + c] = prev[3];
+  for (int i = 0; i < 5; ++i) IO::st(from_real<S>(hd[i], sc), rs.dst, co, (uint32_t)(14 + i) * PB);
+  BufIO<R>::st(prev[0], rs.d4, cr, 0);
+  BufIO<R>::st(prev[1], rs.d4, cr, PR);
+  BufIO<R>::st(prev[2], rs.d4, cr, 2 * PR);
+  BufIO<R>::st(prev[3], rs.d4, cr, 3 * PR);
 }
 
 // tile index -> (x0, y0), spreading consecutive row bands over the 8 XCDs so that the
@@ -326,18 +415,28 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return k * per + (k < rem ? k : rem) + j;
 }
 
+// one tile: tile_y rows of blockDim.x nodes starting at (x0, y0)
+template <typename S>
+__device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, const StepRes &rs, int x0, int y0,
+                                          int tile_y) {
+  const int x = x0 + threadIdx.x;
+  const int y1 = min(y0 + tile_y, d.ny);
+  const bool interior = x0 >= 1 && x0 + (int)blockDim.x <= d.nx - 1 && y0 >= 1 && y0 + tile_y <= d.ny - 1;
+  if (x >= d.nx) return;
+  if (interior) {
+    for (int y = y0; y < y1; ++y) step_node<S, true>(d, rs, x, y);
+  } else {
+    for (int y = y0; y < y1; ++y) step_node<S, false>(d, rs, x, y);
+  }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx,
                                                    int parity) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int x = (t % ntx) * blockDim.x + threadIdx.x;
-  const int y0 = (t / ntx) * tile_y;
-  if (x >= d.nx) return;
   const int cur = (d.base_parity ^ parity) & 1;
-  const S *src = (const S *)(cur ? d.pop1 : d.pop0);
-  S *dst = (S *)(cur ? d.pop0 : d.pop1);
-  const int y1 = min(y0 + tile_y, d.ny);
-  for (int y = y0; y < y1; ++y) step_node<S>(d, src, dst, x, y);
+  const StepRes rs = step_resources<S>(d, cur);
+  step_tile<S>(d, rs, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
 }
 
 // Batched step: a fixed grid walks the (cavity, tile) work items of every attached
@@ -351,15 +450,10 @@ __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<
   const int n = *nitems;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const Item item = items[it];
-    const Desc<typename St<S>::R> &d = descs[item.cavity];
-    const int x = item.x0 + threadIdx.x;
-    if (x < d.nx) {
-      const int cur = (d.base_parity ^ parity) & 1;
-      const S *src = (const S *)(cur ? d.pop1 : d.pop0);
-      S *dst = (S *)(cur ? d.pop0 : d.pop1);
-      const int y1 = min(item.y0 + tile_y, d.ny);
-      for (int y = item.y0; y < y1; ++y) step_node<S>(d, src, dst, x, y);
-    }
+    const Desc<typename St<S>::R> d = descs[item.cavity];
+    const int cur = (d.base_parity ^ parity) & 1;
+    const StepRes rs = step_resources<S>(d, cur);
+    step_tile<S>(d, rs, item.x0, item.y0, tile_y);
   }
 }
 
@@ -466,7 +560,7 @@ __global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename 
       acc[0] += rho;
       acc[1] += (double)d.sigma * T;
       acc[2] += phi * C;
-      const double sx = snap[c], sy = snap[P + c], sT = snap[2 * P + c], sC = snap[3 * P + c];
+      const double sT = snap[c], sC = snap[P + c], sx = snap[2 * P + c], sy = snap[3 * P + c];
       acc[3] += (ux - sx) * (ux - sx) + (uy - sy) * (uy - sy);
       acc[4] += ux * ux + uy * uy;
       acc[5] += (T - sT) * (T - sT);
@@ -477,10 +571,10 @@ __global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename 
       acc[10] = fmax(acc[10], fabs(uy));
       const bool bad = !(isfinite(rho) && isfinite(T) && isfinite(C) && isfinite(ux) && isfinite(uy));
       acc[11] += bad ? 1.0 : 0.0;
-      snap[c] = (R)ux;
-      snap[P + c] = (R)uy;
-      snap[2 * P + c] = (R)T;
-      snap[3 * P + c] = (R)C;
+      snap[c] = (R)T;
+      snap[P + c] = (R)C;
+      snap[2 * P + c] = (R)ux;
+      snap[3 * P + c] = (R)uy;
     }
   }
   __shared__ double red[OBS_THREADS / 64][NSLOT];
