@@ -35,6 +35,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="", help="tile_x,tile_y (default: library default)")
+    ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve"),
+                    help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
+                         "batched launch vs one by one; serve: continuous-batching request stream")
+    ap.add_argument("--cavities", type=int, default=256, help="sweep: number of cavities")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
+    ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -98,6 +105,105 @@ def cpu_baseline(case, target_s):
                        f"FP64 oracle, OpenMP over rows")
 
 
+def sweep(a):
+    """Independent cavities of uneven size and parameters (sides 64..512, aspect 1 or 2,
+    Ra, Da, porosity, Le, N drawn per cavity), FP32: aggregate MLUPS of one batched launch
+    per step replayed from a HIP graph, against the same cavities stepped one by one, with
+    one plain launch per step and with the per-cavity graph replay."""
+    import torch
+    import workloads
+    from paper_1708_07525_amd import Batch, Solver
+
+    cav = workloads.sweep_cavities(a.cavities, seed=3)
+    solvers = []
+    for e in cav:
+        T, C = workloads.cavity_fields(e)
+        solvers.append(Solver(e["params"], T=T, C=C, precision="fp32"))
+    nodes = sum(s.nx * s.ny for s in solvers)
+    steps = a.steps
+    out = {"metric": "aggregate MLUPS, batched sweep vs one-by-one", "unit": "MLUPS", "cavities": len(solvers),
+           "nodes": nodes, "steps": steps, "data": "synthetic"}
+    # one by one, plain launches
+    for mode, chunk in (("one_by_one_plain", 0), ("one_by_one_graph", 64)):
+        for s in solvers:
+            s.set_graph_chunk(chunk)
+            s.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in solvers:
+            s.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode] = round(nodes * steps / dt / 1e6, 1)
+    b = Batch(len(solvers), chunk=100)
+    for s in solvers:
+        b.attach(s)
+    b.step(200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["batched"] = round(nodes * steps / dt / 1e6, 1)
+    out["value"] = out["batched"]
+    out["speedup_vs_one_by_one_plain"] = round(out["batched"] / out["one_by_one_plain"], 3)
+    out["speedup_vs_one_by_one_graph"] = round(out["batched"] / out["one_by_one_graph"], 3)
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve(a):
+    """Poisson stream of solve requests (square sides 128/256/512/1024 with p = 0.4/0.3/0.2/0.1,
+    parameters drawn as in the sweep, FP32 or FP16 storage 50/50), admitted by device
+    footprint under a 200 GB budget, advanced together until the K-step velocity residual
+    falls below 1e-8 or the step cap; p50/p99 time-to-solution, aggregate MLUPS, and the
+    Nu/Sh error of sampled requests against the FP64 oracle."""
+    import torch
+    import workloads
+    from paper_1708_07525_amd.serving import Request, Server
+
+    def build(stream):
+        out = []
+        for r in stream:
+            T, C = workloads.cavity_fields(r)
+            out.append(Request(r["id"], r["arrival"], r["params"], r["precision"], None, T, C))
+        return out
+
+    budget = 200 * 10 ** 9
+    # closed-loop capacity with everything arriving at once, to set the arrival rate
+    cal = build(workloads.request_stream(count=max(8, a.requests // 4), seed=40, rate=1e9))
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=a.max_steps)
+    _, cs = srv.run(cal)
+    srv.close()
+    capacity = cs["requests"] / cs["wall_s"]
+    rate = 0.8 * capacity
+    reqs = build(workloads.request_stream(count=a.requests, seed=4, rate=rate))
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=a.max_steps)
+    results, summ = srv.run(reqs)
+    srv.close()
+    torch.cuda.synchronize()
+    out = {"metric": "batched p50/p99 solve latency and aggregate MLUPS (continuous batching)",
+           "unit": "s", "value": round(summ["p50_s"], 4), "p50_s": round(summ["p50_s"], 4),
+           "p99_s": round(summ["p99_s"], 4), "aggregate_MLUPS": round(summ["aggregate_MLUPS"], 1),
+           "requests": summ["requests"], "converged": summ["converged"], "rate_per_s": round(rate, 3),
+           "closed_loop_capacity_per_s": round(capacity, 3), "step_cap": a.max_steps, "tol": 1e-8,
+           "higher_is_better": False, "data": "synthetic"}
+    if a.oracle_samples > 0:
+        import oracle
+        by_id = {r.id: r for r in reqs}
+        errs = []
+        for res in [r for r in results if r.nodes == 128 * 128][:a.oracle_samples]:
+            req = by_id[res.id]
+            o = oracle.Oracle(req.params, T=req.T, C=req.C)
+            o.step(res.steps)
+            ob = o.observables()
+            errs.append({"id": res.id, "precision": res.precision, "steps": res.steps,
+                         "Nu_rel_err": abs(res.obs["Nu"][0] - ob["Nu"][0]) / abs(ob["Nu"][0]),
+                         "Sh_rel_err": abs(res.obs["Sh"][0] - ob["Sh"][0]) / abs(ob["Sh"][0])})
+        out["oracle_samples"] = errs
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -110,6 +216,12 @@ def main():
     torch.cuda.set_device(0)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.workload == "sweep":
+        sweep(a)
+        return
+    if a.workload == "serve":
+        serve(a)
         return
     case = workloads.band_cavity(seed=2, n=a.n)
     nodes = a.n * a.n

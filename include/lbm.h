@@ -166,6 +166,10 @@ lbm_status lbm_set_state(struct lbm_ctx *c, const void *host, uint64_t bytes);
 lbm_status lbm_set_tile(struct lbm_ctx *c, int32_t tile_x, int32_t tile_y);
 lbm_status lbm_get_tile(const struct lbm_ctx *c, int32_t *tile_x, int32_t *tile_y);
 
+/* Steps per captured HIP graph replay in lbm_step: an even chunk >= 2, or 0 for one plain
+ * kernel launch per step (default 64).  Results do not depend on it. */
+lbm_status lbm_set_graph_chunk(struct lbm_ctx *c, int32_t chunk);
+
 /* Times every supported launch shape on this context for `steps` steps each (HIP events),
  * keeps the fastest, restores the state it started from, and reports the choice and its
  * time per step.  Synchronises. */

@@ -22,7 +22,7 @@ using namespace lbmk;
 
 namespace {
 
-constexpr int kGraphChunk = 64;     // steps per captured graph in lbm_step (even)
+constexpr int kGraphChunk = 64;     // default steps per captured graph in lbm_step (even)
 constexpr double kCs2 = 1.0 / 3.0;  // D2Q9 sound speed squared
 
 struct DevBuf {
@@ -95,6 +95,7 @@ struct lbm_ctx {
   hipGraphExec_t graph = nullptr;
   int graph_cur = -1;
   Tile graph_tile{0, 0};
+  int graph_chunk = kGraphChunk;   // 0: plain launches only
 
   void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
   void *d4() const { return base + lay.off_d4; }
@@ -506,7 +507,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   const int start = c->cur;
   if (e == hipSuccess) {
     int cur = start;
-    for (int k = 0; k < kGraphChunk && e == hipSuccess; ++k) {
+    for (int k = 0; k < c->graph_chunk && e == hipSuccess; ++k) {
       set_parity(c, cur);
       e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, 0, cs);
       cur ^= 1;
@@ -532,12 +533,12 @@ LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   int64_t left = nsteps;
-  if (left >= kGraphChunk) {
+  if (c->graph_chunk > 0 && left >= c->graph_chunk) {
     lbm_status s = ensure_graph(c);
     if (s != LBM_OK) return s;
-    while (left >= kGraphChunk) {
+    while (left >= c->graph_chunk) {
       HIP_CHECK(c, hipGraphLaunch(c->graph, c->stream), "hipGraphLaunch");
-      left -= kGraphChunk;   // kGraphChunk is even: the current buffer is unchanged
+      left -= c->graph_chunk;   // the chunk is even: the current buffer is unchanged
     }
   }
   lbm_status s = step_plain(c, left);
@@ -687,6 +688,14 @@ LBM_API lbm_status lbm_set_tile(lbm_ctx *c, int32_t tx, int32_t ty) {
   }
   if (!tile_supported(tx, ty)) return fail(c, LBM_EINVAL, "unsupported tile %dx%d", tx, ty);
   c->tile = Tile{tx, ty};
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_graph_chunk(lbm_ctx *c, int32_t chunk) {
+  if (!c) return LBM_EINVAL;
+  if (chunk < 0 || chunk == 1 || (chunk & 1)) return fail(c, LBM_EINVAL, "graph chunk must be 0 or even >= 2");
+  if (chunk != c->graph_chunk) drop_graph(c);
+  c->graph_chunk = chunk;
   return LBM_OK;
 }
 

@@ -79,9 +79,17 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R dT = sg * d.inv_sigma;          // T - T0
   const R dC = sh * inv_phi;              // C - C0
   const R T = d.T0 + dT, C = d.C0 + dC;
-  // buoyancy (Eq. 6) plus any constant acceleration
+  // buoyancy (Eq. 6) plus any constant acceleration.  Both products are rounded before the
+  // sum (no fused multiply-add), so that equal and opposite thermal and solutal terms cancel
+  // exactly, as they do in Eq. (6)
   const R Gx = d.gx;
-  const R Gy = d.gy + d.gbT * dT + d.gbC * dC;
+  R Gy;
+  {
+#pragma clang fp contract(off)
+    const R bT = d.gbT * dT;
+    const R bC = d.gbC * dC;
+    Gy = d.gy + (bT + bC);
+  }
   // explicit velocity (Eqs. 18-19), delta_t = 1
   const R vx = jx * d.inv_rho0 + half * phi * Gx;
   const R vy = jy * d.inv_rho0 + half * phi * Gy;
@@ -141,14 +149,16 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R diag = a0 + R(2) * a1 + a2;
   fd[1] = axis + a3 - R(2) * a4 + a7;
   fd[2] = axis + a5 - R(2) * a6 - a7;
-  fd[3] = axis - a3 + R(2) * a4 + a7;
-  fd[4] = axis - a5 + R(2) * a6 - a7;
   fd[5] = diag + a3 + a4 + a5 + a6 + a8;
   fd[6] = diag - a3 - a4 + a5 + a6 - a8;
   fd[7] = diag - a3 - a4 - a5 - a6 + a8;
   fd[8] = diag + a3 + a4 - a5 - a6 - a8;
-  // rest population from the conserved density: keeps sum f* = sum f up to one rounding
-  // (M^-1 with rounded 1/9, 1/36 would otherwise drift the mass by a fixed bias per step)
+  // f3, f4 and the rest population f0 are formed from the moments they must carry
+  // (sum e_x f* = m3*, sum e_y f* = m5*, sum f* = rho): algebraically the same rows of
+  // M^-1, but each moment then comes back up to one rounding instead of being scaled by
+  // 6 fl(1/6) or 9 fl(1/9) every step, a bias that accumulates in FP32
+  fd[3] = (fd[1] + (fd[5] - fd[6])) - ((fd[7] - fd[8]) + p3);
+  fd[4] = (fd[2] + (fd[5] + fd[6])) - ((fd[7] + fd[8]) + p5);
   fd[0] = drho - ((fd[1] + fd[2]) + (fd[3] + fd[4])) - ((fd[5] + fd[6]) + (fd[7] + fd[8]));
 
   // ---- D2Q5 for T (Eq. 21) and C (Eq. 22)

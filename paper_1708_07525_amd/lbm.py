@@ -24,7 +24,7 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3}
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
     "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-    "lbm_set_tile", "lbm_get_tile", "lbm_autotune", "lbm_last_error", "lbm_destroy",
+    "lbm_set_tile", "lbm_get_tile", "lbm_set_graph_chunk", "lbm_autotune", "lbm_last_error", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_size",
     "lbm_batch_destroy",
 )
@@ -98,6 +98,7 @@ def lib():
         L.lbm_get_state.argtypes = [_VP, _VP, ctypes.c_uint64]
         L.lbm_set_state.argtypes = [_VP, _VP, ctypes.c_uint64]
         L.lbm_set_tile.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_set_graph_chunk.argtypes = [_VP, ctypes.c_int32]
         L.lbm_get_tile.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.lbm_autotune.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
@@ -234,6 +235,9 @@ class Solver:
 
     def set_tile(self, tx: int, ty: int):
         _check(lib().lbm_set_tile(self._h, int(tx), int(ty)), self._h, "lbm_set_tile")
+
+    def set_graph_chunk(self, chunk: int):
+        _check(lib().lbm_set_graph_chunk(self._h, int(chunk)), self._h, "lbm_set_graph_chunk")
 
     def get_tile(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -161,9 +161,10 @@ def closed_box(make, nx=24, ny=20, steps=2000, seed=5, **extra):
     return tuple(abs(o1[k] - o0[k]) / abs(o0[k]) for k in ("mass", "heat", "solute")), o1
 
 
-def rest_state(make, nx=12, ny=10, steps=300, **extra):
+def rest_state(make, nx=12, ny=10, steps=300, detail=False, **extra):
     """u = 0 and T = C = 0.5 everywhere, walls held at the same values: the state must not
-    move.  Returns max |field - initial| over (rho - rho0, u, T, C)."""
+    move.  Returns max |field - initial| over (rho - rho0, u, T, C) (with ``detail``, also
+    the per-field maxima and the first offending nodes)."""
     p = dict(nx=nx, ny=ny, sides=("hot", "cold", "adiabatic", "adiabatic"), Th=0.5, Tl=0.5,
              Ch=0.5, Cl=0.5, direct=1, nu=0.05, alpha_e=0.05, D_e=0.03, K=30.0, gbT=1e-3,
              gbC=-2e-4, Fphi=-1.0, phi=0.55)
@@ -171,9 +172,13 @@ def rest_state(make, nx=12, ny=10, steps=300, **extra):
     s = make(p, T=0.5, C=0.5)
     s.step(steps)
     F = s.fields()
-    return max(float(np.abs(F["rho"] - 1.0).max()), float(np.abs(F["ux"]).max()),
-               float(np.abs(F["uy"]).max()), float(np.abs(F["T"] - 0.5).max()),
-               float(np.abs(F["C"] - 0.5).max()))
+    ref = dict(rho=1.0, ux=0.0, uy=0.0, T=0.5, C=0.5)
+    errs = {k: np.abs(F[k] - ref[k]) for k in ref}
+    worst = max(float(e.max()) for e in errs.values())
+    if detail:
+        info = {k: (float(e.max()), np.argwhere(e > 0)[:4].tolist()) for k, e in errs.items()}
+        return worst, info
+    return worst
 
 
 def cavity_symmetry(make, nx=32, ny=24, steps=2000, **extra):

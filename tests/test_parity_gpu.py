@@ -167,9 +167,14 @@ def test_gpu_symmetry_and_conservation():
     assert max(drifts) < 4 * np.finfo(float).eps * 1000
 
 
-def test_gpu_rest_state_and_buoyancy_cancellation():
-    assert pins.rest_state(make_gpu("fp64")) < 1e-15
-    assert pins.rest_state(make_gpu("fp16s")) == 0.0      # deviations stay exactly zero
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_gpu_rest_state(prec):
+    """In deviation form the rest state is all zeros and must stay exactly so."""
+    worst, info = pins.rest_state(make_gpu(prec), detail=True)
+    assert worst == 0.0, info
+
+
+def test_gpu_buoyancy_cancellation():
     umax, dTC, Nu, Sh = pins.buoyancy_cancellation(make_gpu("fp32"))
     assert umax == 0.0 and dTC == 0.0 and Nu == Sh
 

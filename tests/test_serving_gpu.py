@@ -1,0 +1,63 @@
+"""The continuous-batching loop on the GPU: every request's result is the same served alone
+and served in the mix (bitwise: the batched launch runs the same per-node code and each
+request is checked on its own step clock)."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    from paper_1708_07525_amd.serving import Request
+    rng = np.random.default_rng(12)
+    out = []
+    for i in range(6):
+        side = int(rng.choice((32, 48, 64)))
+        p = workloads.cavity_params(nx=side, ny=side, Ra=float(10 ** rng.uniform(3, 4.5)),
+                                    Da=float(10 ** rng.uniform(-3, -1)), phi=float(rng.uniform(0.4, 0.9)),
+                                    Le=float(rng.uniform(1, 5)), N=float(rng.uniform(-1, 1)))
+        T, C = workloads.noise_fields(side, side, (12, i))
+        out.append(Request(i, 0.002 * i, p, "fp32" if i % 2 else "fp16s", None, T, C))
+    return out
+
+
+def test_alone_equals_mixed():
+    from paper_1708_07525_amd.serving import Request, Server
+    reqs = _requests()
+    mixed = Server(10 ** 10, max_slots=8, chunk=100, check_every=500, tol=1e-6, max_steps=3000, keep_fields=True)
+    res_mix, summ = mixed.run(reqs)
+    mixed.close()
+    assert summ["requests"] == len(reqs)
+    assert summ["p99_s"] >= summ["p50_s"] > 0 and summ["aggregate_MLUPS"] > 0
+    res_mix = {r.id: r for r in res_mix}
+    for req in reqs:
+        alone = Server(10 ** 10, max_slots=1, chunk=100, check_every=500, tol=1e-6, max_steps=3000,
+                       keep_fields=True)
+        (r,), _ = alone.run([Request(req.id, 0.0, req.params, req.precision, None, req.T, req.C)])
+        alone.close()
+        m = res_mix[req.id]
+        assert r.steps == m.steps and r.converged == m.converged
+        for k in ("ux", "uy", "T", "C", "rho"):
+            assert np.array_equal(r.fields[k], m.fields[k]), (req.id, k)
+        assert r.obs["Nu"] == m.obs["Nu"] and r.obs["Sh"] == m.obs["Sh"]
+
+
+def test_budget_limits_residency():
+    from paper_1708_07525_amd import footprint_bytes
+    from paper_1708_07525_amd.serving import Server
+    reqs = _requests()
+    budget = 2 * max(footprint_bytes(r.params, r.precision) for r in reqs)
+    srv = Server(budget, max_slots=8, chunk=100, check_every=500, tol=1e-6, max_steps=1000)
+    seen = []
+    orig = srv._admit
+
+    def admit(req, now):
+        ok = orig(req, now)
+        seen.append(srv.used)
+        return ok
+    srv._admit = admit
+    results, _ = srv.run(reqs)
+    srv.close()
+    assert len(results) == len(reqs) and max(seen) <= budget
