@@ -35,9 +35,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="", help="tile_x,tile_y (default: library default)")
-    ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve"),
+    ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
-                         "batched launch vs one by one; serve: continuous-batching request stream")
+                         "batched launch vs one by one; serve: continuous-batching request stream; "
+                         "precision: FP64/FP32/FP16-storage errors on the 512^2 and 2048^2 cavities")
     ap.add_argument("--cavities", type=int, default=256, help="sweep: number of cavities")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
@@ -63,6 +64,26 @@ def copy_probe(mib):
     ms = e0.elapsed_time(e1) / 10
     print(json.dumps({"copy_probe_MiB": mib, "ms_per_copy": ms,
                       "GB_s_read_plus_write": 2 * mib * 1048576 / (ms * 1e-3) / 1e9}), flush=True)
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_kernels.hip")
+
+
+def profiled_traffic(prec, n):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when there is no
+    summary for this workload or the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{prec}_cavity{n}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256_16") == h else None
 
 
 def timed_run(case, prec, steps, warmup, tile=None):
@@ -152,6 +173,55 @@ def sweep(a):
     print(json.dumps(out), flush=True)
 
 
+def precision_report(a):
+    """The 512^2 Gaussian-random-field cavity (50000 steps) and the 2048^2 banded cavity
+    (20000 steps) run with FP64, FP32 and FP16 storage.  The FP64 GPU path, itself held to
+    1e-10 of the FP64 oracle by the parity tests, is the reference here (the oracle would
+    need 8.4e10 node updates on the host for the large case).  Reports MLUPS, the HBM
+    roofline fraction, the largest field errors and the Nu/Sh errors at the hot wall."""
+    import torch
+    import workloads
+    from paper_1708_07525_amd import Solver
+
+    def errs(F, R):
+        speed = float(np.hypot(R["ux"], R["uy"]).max())
+        e = {k: float(np.abs(F[k] - R[k]).max() / np.abs(R[k]).max()) for k in ("T", "C")}
+        e.update({k: float(np.abs(F[k] - R[k]).max() / speed) for k in ("ux", "uy")})
+        e["rho"] = float(np.abs(F["rho"] - R["rho"]).max())
+        return e
+
+    out = {"metric": "field and Nu/Sh error by storage precision (reference: FP64 GPU path)", "data": "synthetic",
+           "cases": []}
+    for case, steps in ((workloads.grf_cavity(seed=1, n=512), a.steps if a.steps != 20000 else 50000),
+                        (workloads.band_cavity(seed=2, n=2048), 20000)):
+        n = case["params"]["nx"]
+        res = {}
+        for prec in ("fp64", "fp32", "fp16s"):
+            s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ob = s.observables()
+            res[prec] = (s.fields(), ob, n * n * steps / dt / 1e6)
+            s.close()
+        ref_F, ref_ob, _ = res["fp64"]
+        c = {"case": case["name"], "steps": steps}
+        for prec, (F, ob, ml) in res.items():
+            gbs = BYTES_PER_LU[prec] * ml * 1e6 / 1e9
+            row = {"MLUPS": round(ml, 1), "GB_s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                   "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0]}
+            if prec != "fp64":
+                row["field_err"] = errs(F, ref_F)
+                row["Nu_rel_err"] = abs(ob["Nu"][0] - ref_ob["Nu"][0]) / abs(ref_ob["Nu"][0])
+                row["Sh_rel_err"] = abs(ob["Sh"][0] - ref_ob["Sh"][0]) / abs(ref_ob["Sh"][0])
+            c[prec] = row
+        out["cases"].append(c)
+        print(json.dumps(c), flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def serve(a):
     """Poisson stream of solve requests (square sides 128/256/512/1024 with p = 0.4/0.3/0.2/0.1,
     parameters drawn as in the sweep, FP32 or FP16 storage 50/50), admitted by device
@@ -223,6 +293,9 @@ def main():
     if a.workload == "serve":
         serve(a)
         return
+    if a.workload == "precision":
+        precision_report(a)
+        return
     case = workloads.band_cavity(seed=2, n=a.n)
     nodes = a.n * a.n
     tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
@@ -246,7 +319,9 @@ def main():
                                f"Da=1e-4, Pr=0.7, Le=10, N=2, D2Q9+2xD2Q5 MRT, {a.precision} population storage",
                    "nx": a.n, "ny": a.n, "precision": a.precision, "tile": list(tile_used)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": profiled_traffic(a.precision, a.n), "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes,
                      "bytes_per_lu": BYTES_PER_LU[a.precision], "kernel": "step_kernel"},
         "wall_s": round(wall, 3),
         "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0],
