@@ -39,7 +39,7 @@ size_t real_size(int prec) { return prec == PREC_FP64 ? 8 : 4; }
 struct Layout {
   int pitch;
   long long plane;
-  size_t off_pop0, off_pop1, off_d4, off_phi, off_snap, off_small, total;
+  size_t off_pop0, off_pop1, off_d4, off_phi, off_snap, off_counter, off_small, total;
   int nblocks_obs;
 };
 
@@ -63,6 +63,7 @@ Layout plan_layout(int nx, int ny, int prec) {
   L.off_d4 = take((size_t)ND4 * L.plane * rs);
   L.off_phi = take((size_t)L.plane * rs);
   L.off_snap = take((size_t)ND4 * L.plane * rs);
+  L.off_counter = take(2 * sizeof(unsigned));
   // small: wall T (4), wall C (4), obs out (32), partials
   L.off_small = take((8 + 32 + (size_t)L.nblocks_obs * 12) * sizeof(double));
   L.total = off;
@@ -101,6 +102,7 @@ struct lbm_ctx {
   void *d4() const { return base + lay.off_d4; }
   void *phi() const { return base + lay.off_phi; }
   void *snap() const { return base + lay.off_snap; }
+  unsigned *counter() const { return (unsigned *)(base + lay.off_counter); }
   double *wall_dev() const { return (double *)(base + lay.off_small); }
   double *obs_out() const { return wall_dev() + 8; }
   double *partials() const { return wall_dev() + 40; }
@@ -241,6 +243,7 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     D.pop1 = c->pop(1);
     D.d4 = c->d4();
     D.phi = c->phi();
+    D.counter = c->counter();
     D.rho0 = (R)p->rho0;
     D.inv_rho0 = (R)(1.0 / p->rho0);
     D.sigma = (R)p->sigma;
@@ -616,7 +619,8 @@ LBM_API lbm_status lbm_get_derived(const lbm_ctx *c, lbm_derived *out) {
 namespace {
 struct StateHeader {
   char magic[8];
-  int32_t nx, ny, precision, pad;
+  int32_t nx, ny, precision;
+  uint32_t counter;          // device step counter of the stored state
   int64_t step, snap_step;
   uint64_t pop_bytes, d4_bytes;
 };
@@ -633,7 +637,7 @@ LBM_API lbm_status lbm_get_state(lbm_ctx *c, void *host, uint64_t bytes) {
   if (!c->ready) return fail(c, LBM_ESTATE, "no state before lbm_set_fields");
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h{};
-  std::memcpy(h.magic, "LBMDDPS1", 8);
+  std::memcpy(h.magic, "LBMDDPS2", 8);
   h.nx = c->p.nx;
   h.ny = c->p.ny;
   h.precision = c->prec;
@@ -641,6 +645,9 @@ LBM_API lbm_status lbm_get_state(lbm_ctx *c, void *host, uint64_t bytes) {
   h.snap_step = c->snap_step;
   h.pop_bytes = (uint64_t)NPOP * c->lay.plane * store_size(c->prec);
   h.d4_bytes = (uint64_t)ND4 * c->lay.plane * real_size(c->prec);
+  HIP_CHECK(c, hipMemcpyAsync(&h.counter, c->counter() + c->cur, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream),
+            "state copy");
+  HIP_CHECK(c, hipStreamSynchronize(c->stream), "state sync");
   char *dst = (char *)host;
   std::memcpy(dst, &h, sizeof h);
   dst += sizeof h;
@@ -659,13 +666,15 @@ LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h;
   std::memcpy(&h, host, sizeof h);
-  if (std::memcmp(h.magic, "LBMDDPS1", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
+  if (std::memcmp(h.magic, "LBMDDPS2", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
     return fail(c, LBM_EINVAL, "state does not match this context");
   const char *src = (const char *)host + sizeof h;
   drop_graph(c);
   c->cur = 0;
   set_parity(c, 0);
   HIP_CHECK(c, hipMemcpyAsync(c->pop(0), src, h.pop_bytes, hipMemcpyHostToDevice, c->stream), "state copy");
+  HIP_CHECK(c, hipMemcpyAsync(c->counter(), &h.counter, sizeof(unsigned), hipMemcpyHostToDevice, c->stream),
+            "state copy");
   HIP_CHECK(c, hipMemcpyAsync(c->d4(), src + h.pop_bytes, h.d4_bytes, hipMemcpyHostToDevice, c->stream), "state copy");
   HIP_CHECK(c, hipMemcpyAsync(c->snap(), src + h.pop_bytes + h.d4_bytes, h.d4_bytes, hipMemcpyHostToDevice, c->stream),
             "state copy");
@@ -714,12 +723,14 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   const size_t pop_bytes = (size_t)NPOP * c->lay.plane * store_size(c->prec);
   const size_t d4_bytes = (size_t)ND4 * c->lay.plane * real_size(c->prec);
   char *save = nullptr;
-  HIP_CHECK(c, hipMalloc((void **)&save, pop_bytes + d4_bytes), "hipMalloc autotune");
+  HIP_CHECK(c, hipMalloc((void **)&save, pop_bytes + d4_bytes + 2 * sizeof(unsigned)), "hipMalloc autotune");
   const int cur0 = c->cur;
   const int64_t step0 = c->step;
   const Tile tile0 = c->tile;
   hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(save + pop_bytes + d4_bytes, c->counter(), 2 * sizeof(unsigned), hipMemcpyDeviceToDevice, c->stream);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -748,6 +759,8 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   set_parity(c, cur0);
   if (e == hipSuccess) e = hipMemcpyAsync(c->pop(cur0), save, pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d4(), save + pop_bytes, d4_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->counter(), save + pop_bytes + d4_bytes, 2 * sizeof(unsigned), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);

@@ -10,6 +10,7 @@
 //           storage, FP32 otherwise).  Read and rewritten in place by the node itself.
 //   phi     1 plane of porosity (only when the porosity is a field).
 //   snap    4 planes: residual snapshot of T, C, ux, uy.
+//   counter 2 words: the step count, kept beside the state it belongs to (index = buffer).
 //   Populations are stored as deviations from the rest state (rho0, T0, C0).
 #pragma once
 #include <stdint.h>
@@ -33,6 +34,8 @@ struct Desc {
   void *pop0, *pop1;       // population buffers (storage type)
   void *d4;                // previous-step fields (type R)
   void *phi;               // porosity plane (type R), when phi_field
+  unsigned *counter;       // step counters [2]: counter[cur] is the step count of the state in
+                           // buffer cur (drives the FP16 stochastic rounding)
   R rho0, inv_rho0, sigma, inv_sigma, varpi, T0, C0;
   R s_e, s_eps, s_j, s_q, s_v;
   R z_a, z_e, z_eps, e_D, e_e, e_eps;

@@ -285,6 +285,48 @@ __device__ __forceinline__ float from_real(float v, float) { return v; }
 template <>
 __device__ __forceinline__ _Float16 from_real(float v, float scale) { return (_Float16)(v * scale); }
 
+// ---------------------------------------------------------------- FP16 stochastic rounding
+// Round-to-nearest binary16 storage stagnates: a population that changes by less than half a
+// binary16 ulp per step never changes at all, which freezes slow diffusion.  The step kernel
+// therefore rounds stochastically: 13 random bits (the bits binary16 drops from a binary32
+// mantissa) are added to the scaled value's bit pattern before a round-toward-zero
+// conversion, so the stored value is unbiased.  The random bits are a function of (node,
+// step) only -- the hash of Jarzynski & Olano, "Hash functions for GPU rendering" (JCGT
+// 2020, PCG-based), seeding Marsaglia's xorshift32 -- so results are reproducible and do
+// not depend on the launch shape or on the other cavities of a batch.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+  const uint32_t state = v * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+
+struct Dither {
+  uint32_t s, pool;
+  int left;
+  __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step)) | 1u), pool(0), left(0) {}
+  __device__ __forceinline__ uint32_t next13() {
+    if (left == 0) {
+      s ^= s << 13;
+      s ^= s >> 17;
+      s ^= s << 5;
+      pool = s;
+      left = 2;
+    }
+    const uint32_t r = pool & 0x1FFFu;
+    pool >>= 13;
+    --left;
+    return r;
+  }
+};
+
+__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r13) {
+  // beyond the binary16 range: round to nearest, which gives the infinity the
+  // non-finite check looks for
+  if (!(__builtin_fabsf(v) < 65504.0f)) return (_Float16)v;
+  const float d = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) + r13);
+  return __builtin_amdgcn_cvt_pkrtz(d, 0.0f)[0];
+}
+
 // resources of one cavity for one step
 struct StepRes {
   rsrc_t src, dst, d4, phi;
@@ -303,10 +345,22 @@ __device__ __forceinline__ StepRes step_resources(const Desc<typename St<S>::R> 
   return r;
 }
 
+template <typename S>
+__device__ __forceinline__ void store_pop(typename St<S>::R v, typename St<S>::R scale, rsrc_t r, uint32_t voff,
+                                          uint32_t soff, Dither &dz) {
+  if constexpr (__is_same(S, _Float16)) {
+    BufIO<S>::st(half_stochastic(v * scale, dz.next13()), r, voff, soff);
+  } else {
+    (void)dz;
+    BufIO<S>::st(from_real<S>(v, scale), r, voff, soff);
+  }
+}
+
 // ---------------------------------------------------------------- one node of a step
 // INTERIOR: every upstream node of the tile lies inside the domain (no wall link, no wrap).
 template <typename S, bool INTERIOR>
-__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y) {
+__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
+                                          uint32_t step) {
   using R = typename St<S>::R;
   using IO = BufIO<S>;
   constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
@@ -404,12 +458,13 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   collide(d, phi, a, b, fd, gd, hd, prev);
   const R sc = d.scale;
   const uint32_t co = c * ES;
+  Dither dz(c, step);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) IO::st(from_real<S>(fd[i], sc), rs.dst, co, (uint32_t)i * PB);
+  for (int i = 0; i < 9; ++i) store_pop<S>(fd[i], sc, rs.dst, co, (uint32_t)i * PB, dz);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) IO::st(from_real<S>(gd[i], sc), rs.dst, co, (uint32_t)(9 + i) * PB);
+  for (int i = 0; i < 5; ++i) store_pop<S>(gd[i], sc, rs.dst, co, (uint32_t)(9 + i) * PB, dz);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) IO::st(from_real<S>(hd[i], sc), rs.dst, co, (uint32_t)(14 + i) * PB);
+  for (int i = 0; i < 5; ++i) store_pop<S>(hd[i], sc, rs.dst, co, (uint32_t)(14 + i) * PB, dz);
   BufIO<R>::st(prev[0], rs.d4, cr, 0);
   BufIO<R>::st(prev[1], rs.d4, cr, PR);
   BufIO<R>::st(prev[2], rs.d4, cr, 2 * PR);
@@ -426,17 +481,22 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 }
 
 // one tile: tile_y rows of blockDim.x nodes starting at (x0, y0)
+// The tile at the origin also advances the step counter: it reads counter[cur] (the count
+// of the state being read) and writes counter[cur ^ 1] (the count of the state being
+// written); no other thread writes either word during the launch.
 template <typename S>
-__device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, const StepRes &rs, int x0, int y0,
-                                          int tile_y) {
+__device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int x0,
+                                          int y0, int tile_y) {
   const int x = x0 + threadIdx.x;
   const int y1 = min(y0 + tile_y, d.ny);
   const bool interior = x0 >= 1 && x0 + (int)blockDim.x <= d.nx - 1 && y0 >= 1 && y0 + tile_y <= d.ny - 1;
+  const uint32_t step = d.counter[cur];
+  if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 1u;
   if (x >= d.nx) return;
   if (interior) {
-    for (int y = y0; y < y1; ++y) step_node<S, true>(d, rs, x, y);
+    for (int y = y0; y < y1; ++y) step_node<S, true>(d, rs, x, y, step);
   } else {
-    for (int y = y0; y < y1; ++y) step_node<S, false>(d, rs, x, y);
+    for (int y = y0; y < y1; ++y) step_node<S, false>(d, rs, x, y, step);
   }
 }
 
@@ -446,7 +506,7 @@ __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, in
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int cur = (d.base_parity ^ parity) & 1;
   const StepRes rs = step_resources<S>(d, cur);
-  step_tile<S>(d, rs, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
+  step_tile<S>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
 }
 
 // Batched step: a fixed grid walks the (cavity, tile) work items of every attached
@@ -463,7 +523,7 @@ __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<
     const Desc<typename St<S>::R> d = descs[item.cavity];
     const int cur = (d.base_parity ^ parity) & 1;
     const StepRes rs = step_resources<S>(d, cur);
-    step_tile<S>(d, rs, item.x0, item.y0, tile_y);
+    step_tile<S>(d, rs, cur, item.x0, item.y0, tile_y);
   }
 }
 
