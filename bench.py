@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
     ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="instead of the solver, time the step kernel's memory access pattern without its "
+                         "arithmetic (FP32, aligned and with the pull shifts) on the same lattice")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -84,6 +87,26 @@ def profiled_traffic(prec, n):
     d = json.loads(m.group(1))
     h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
     return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256_16") == h else None
+
+
+def stream_probe(n, reps=200):
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1708_07525_amd", "libstreamprobe.so"))
+    lib.stream_probe_run.restype = ctypes.c_double
+    lib.stream_probe_run.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int] * 6
+    pitch = (n + 63) // 64 * 64
+    plane = (pitch * n + 1023) // 1024 * 1024 + 256
+    src = torch.zeros(19 * plane, device="cuda")
+    dst = torch.zeros(19 * plane, device="cuda")
+    d4 = torch.zeros(4 * plane, device="cuda")
+    phi = torch.full((plane,), 0.5, device="cuda")
+    out = {"stream_probe": f"{n}x{n} FP32, 19+4 planes read and written, 1 plane read"}
+    for mode, name in ((0, "aligned"), (1, "pull_shifted"), (2, "pull_shifted_blocked64")):
+        ms = lib.stream_probe_run(src.data_ptr(), dst.data_ptr(), d4.data_ptr(), phi.data_ptr(), n, n, pitch, plane,
+                                  mode, reps)
+        out[name] = {"ms": ms, "GB_s": round(BYTES_PER_LU["fp32"] * n * n / (ms * 1e-3) / 1e9, 1)}
+    print(json.dumps(out), flush=True)
 
 
 def timed_run(case, prec, steps, warmup, tile=None):
@@ -286,6 +309,9 @@ def main():
     torch.cuda.set_device(0)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.stream_probe:
+        stream_probe(a.n)
         return
     if a.workload == "sweep":
         sweep(a)
