@@ -790,7 +790,6 @@ struct lbm_batch {
   int *nitems[3] = {nullptr, nullptr, nullptr};
   int item_cap[3] = {0, 0, 0};
   int grid = 2048;
-  int tile_y = 1;
   hipGraphExec_t graph = nullptr;
   unsigned graph_mask = 0;   // precisions present when the graph was captured
   bool dirty = true;
@@ -809,9 +808,15 @@ lbm_status batch_upload(lbm_batch *b) {
       set_parity(c, c->cur);
       if (prec == PREC_FP64) d64.push_back(c->d64);
       else d32.push_back(c->d32);
-      const int ntx = (c->p.nx + 255) / 256, nty = (c->p.ny + b->tile_y - 1) / b->tile_y;
+      // 256-thread tiles of tw x (256/tw) nodes; tw in {256, 128, 64} wastes the fewest
+      // lanes on the ragged right edge (ties go to the wider tile)
+      int tw = 256;
+      for (int cand : {128, 64})
+        if ((c->p.nx + cand - 1) / cand * cand < (c->p.nx + tw - 1) / tw * tw) tw = cand;
+      const int rows = 256 / tw;
+      const int ntx = (c->p.nx + tw - 1) / tw, nty = (c->p.ny + rows - 1) / rows;
       for (int ty = 0; ty < nty; ++ty)
-        for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * 256, ty * b->tile_y, 0});
+        for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * tw, ty * rows, tw});
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {
@@ -851,8 +856,7 @@ unsigned batch_mask(const lbm_batch *b) {
 hipError_t batch_launch_step(lbm_batch *b, unsigned mask, int parity, hipStream_t s) {
   for (int prec = 0; prec < 3; ++prec) {
     if (!(mask & (1u << prec))) continue;
-    int e = launch_step_batch(prec, b->descs[prec], b->items[prec], b->nitems[prec], b->grid, 256, b->tile_y,
-                              parity, s);
+    int e = launch_step_batch(prec, b->descs[prec], b->items[prec], b->nitems[prec], b->grid, parity, s);
     if (e) return (hipError_t)e;
   }
   return hipSuccess;

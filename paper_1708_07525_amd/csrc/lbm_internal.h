@@ -50,8 +50,8 @@ struct Desc {
   R scale, inv_scale;      // FP16 pre-scale (1 for FP32/FP64)
 };
 
-struct Item {              // one tile of one cavity, for the batched kernel
-  int cavity, x0, y0, _pad;
+struct Item {              // one tile of one cavity, for the batched kernel: tw nodes along x
+  int cavity, x0, y0, tw;  // (64, 128 or 256) by 256/tw rows, one node per thread
 };
 
 // Launch shape of the step kernel
@@ -65,7 +65,7 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
                 const double *uy, void *stream);
 int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream);
 int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems,
-                      int grid, int block, int tile_y, int parity, void *stream);
+                      int grid, int parity, void *stream);
 // observables: partial sums per block, then a final fixed-order reduction.
 // out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)
 int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials,

@@ -532,21 +532,43 @@ __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, in
   step_tile<S>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
 }
 
+// A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
+// keep every lane busy.
+template <typename S>
+__device__ __forceinline__ void step_tile2d(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int x0,
+                                            int y0, int tw) {
+  const int rows = (int)blockDim.x / tw;
+  const int x = x0 + ((int)threadIdx.x & (tw - 1));
+  const int y = y0 + (int)threadIdx.x / tw;
+  const bool interior = x0 >= 1 && x0 + tw <= d.nx - 1 && y0 >= 1 && y0 + rows <= d.ny - 1;
+  const uint32_t step = d.counter[cur];
+  if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 1u;
+  if (x >= d.nx || y >= d.ny) return;
+  if (interior)
+    step_node<S, true>(d, rs, x, y, step);
+  else
+    step_node<S, false>(d, rs, x, y, step);
+}
+
 // Batched step: a fixed grid walks the (cavity, tile) work items of every attached
 // cavity; the item count lives in device memory so the host can change the batch between
-// graph replays without re-capturing.
+// graph replays without re-capturing.  Each work-group takes a contiguous run of items
+// (neighbouring tiles of one cavity, so shared halo lines stay in its L2), and runs are
+// laid out over the XCDs in bands as in the single-cavity kernel.
 template <typename S>
 __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs,
                                                          const Item *__restrict__ items,
-                                                         const int *__restrict__ nitems, int tile_y,
-                                                         int parity) {
+                                                         const int *__restrict__ nitems, int parity) {
   const int n = *nitems;
-  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b = Policy<S>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int end = min(n, (b + 1) * per);
+  for (int it = b * per; it < end; ++it) {
     const Item item = items[it];
     const Desc<typename St<S>::R> d = descs[item.cavity];
     const int cur = (d.base_parity ^ parity) & 1;
     const StepRes rs = step_resources<S>(d, cur);
-    step_tile<S>(d, rs, cur, item.x0, item.y0, tile_y);
+    step_tile2d<S>(d, rs, cur, item.x0, item.y0, item.tw);
   }
 }
 
@@ -795,21 +817,22 @@ int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream)
   }
 }
 
-int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int block,
-                      int tile_y, int parity, void *stream) {
+int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int parity,
+                      void *stream) {
+  const int block = 256;
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
     case PREC_FP64:
       hipLaunchKernelGGL(step_batch_kernel<double>, dim3(grid), dim3(block), 0, s,
-                         (const Desc<double> *)descs, items, nitems, tile_y, parity);
+                         (const Desc<double> *)descs, items, nitems, parity);
       break;
     case PREC_FP32:
       hipLaunchKernelGGL(step_batch_kernel<float>, dim3(grid), dim3(block), 0, s, (const Desc<float> *)descs,
-                         items, nitems, tile_y, parity);
+                         items, nitems, parity);
       break;
     default:
       hipLaunchKernelGGL(step_batch_kernel<_Float16>, dim3(grid), dim3(block), 0, s,
-                         (const Desc<float> *)descs, items, nitems, tile_y, parity);
+                         (const Desc<float> *)descs, items, nitems, parity);
       break;
   }
   return (int)hipGetLastError();
