@@ -40,8 +40,12 @@ def parse():
                          "batched launch vs one by one; serve: continuous-batching request stream; "
                          "precision: FP64/FP32/FP16-storage errors on the 512^2 and 2048^2 cavities")
     ap.add_argument("--cavities", type=int, default=256, help="sweep: number of cavities")
+    ap.add_argument("--until-converged", action="store_true",
+                    help="sweep: run every cavity to steady state (residual 1e-8) or --max-steps, "
+                         "batched through the serving loop and one by one with plain launches")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
-    ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="step cap per solve (serve: default 20000; sweep --until-converged: 100000)")
     ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
     ap.add_argument("--stream-probe", action="store_true",
                     help="instead of the solver, time the step kernel's memory access pattern without its "
@@ -159,6 +163,9 @@ def sweep(a):
     from paper_1708_07525_amd import Batch, Solver
 
     cav = workloads.sweep_cavities(a.cavities, seed=3)
+    if a.until_converged:
+        sweep_until_converged(a, cav)
+        return
     solvers = []
     for e in cav:
         T, C = workloads.cavity_fields(e)
@@ -245,6 +252,53 @@ def precision_report(a):
     print(json.dumps(out), flush=True)
 
 
+def sweep_until_converged(a, cav):
+    """Every cavity of the sweep to steady state (K-step velocity residual below 1e-8, checked
+    every 1000 steps) or the step cap: all together through the continuous-batching loop, then
+    the same solves one by one with one plain launch per step."""
+    import torch
+    import workloads
+    from paper_1708_07525_amd import Solver
+    from paper_1708_07525_amd.serving import Request, Server, converged
+
+    cap = a.max_steps or 100000
+    reqs = []
+    for i, e in enumerate(cav):
+        T, C = workloads.cavity_fields(e)
+        reqs.append(Request(i, 0.0, e["params"], "fp32", None, T, C))
+    srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
+    res, summ = srv.run(reqs)
+    srv.close()
+    steps_batched = {r.id: r.steps for r in res}
+    node_steps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_alone = {}
+    for r in reqs:
+        s = Solver(r.params, T=r.T, C=r.C, precision="fp32")
+        s.set_graph_chunk(0)
+        n = 0
+        while True:
+            s.step(1000)
+            n += 1000
+            ob = s.observables()
+            if converged(ob, 1e-8, 1e-12 * max(s.derived()["U"], 1e-30)) or ob["nonfinite"] or n >= cap:
+                break
+        steps_alone[r.id] = n
+        node_steps += s.nx * s.ny * n
+        s.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"metric": "aggregate MLUPS to steady state, batched vs one-by-one", "unit": "MLUPS",
+           "cavities": len(reqs), "step_cap": cap, "tol": 1e-8, "data": "synthetic",
+           "batched": round(summ["aggregate_MLUPS"], 1), "batched_wall_s": round(summ["wall_s"], 2),
+           "one_by_one_plain": round(node_steps / dt / 1e6, 1), "one_by_one_wall_s": round(dt, 2),
+           "converged": summ["converged"], "same_stopping_step": steps_alone == steps_batched}
+    out["value"] = out["batched"]
+    out["speedup"] = round(out["batched"] / out["one_by_one_plain"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def serve(a):
     """Poisson stream of solve requests (square sides 128/256/512/1024 with p = 0.4/0.3/0.2/0.1,
     parameters drawn as in the sweep, FP32 or FP16 storage 50/50), admitted by device
@@ -265,13 +319,14 @@ def serve(a):
     budget = 200 * 10 ** 9
     # closed-loop capacity with everything arriving at once, to set the arrival rate
     cal = build(workloads.request_stream(count=max(8, a.requests // 4), seed=40, rate=1e9))
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=a.max_steps)
+    cap = a.max_steps or 20000
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
     _, cs = srv.run(cal)
     srv.close()
     capacity = cs["requests"] / cs["wall_s"]
     rate = 0.8 * capacity
     reqs = build(workloads.request_stream(count=a.requests, seed=4, rate=rate))
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=a.max_steps)
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
     results, summ = srv.run(reqs)
     srv.close()
     torch.cuda.synchronize()
@@ -279,7 +334,7 @@ def serve(a):
            "unit": "s", "value": round(summ["p50_s"], 4), "p50_s": round(summ["p50_s"], 4),
            "p99_s": round(summ["p99_s"], 4), "aggregate_MLUPS": round(summ["aggregate_MLUPS"], 1),
            "requests": summ["requests"], "converged": summ["converged"], "rate_per_s": round(rate, 3),
-           "closed_loop_capacity_per_s": round(capacity, 3), "step_cap": a.max_steps, "tol": 1e-8,
+           "closed_loop_capacity_per_s": round(capacity, 3), "step_cap": cap, "tol": 1e-8,
            "higher_is_better": False, "data": "synthetic"}
     if a.oracle_samples > 0:
         import oracle

@@ -1,0 +1,66 @@
+"""Launch-shape autotuning with a persistent cache.
+
+``lbm_autotune`` (C ABI) times every supported tile shape of the step kernel on a context,
+keeps the fastest and restores the state it started from.  This module keys the winner by
+GPU, storage precision, lattice size class and porosity kind, stores it in a JSON file, and
+applies the cached shape to later contexts of the same class without re-timing.  Results never
+depend on the tile shape (the per-node arithmetic is one function), only the speed does.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_dd", "autotune.json")
+
+
+def cache_path() -> str:
+    return os.environ.get("LBM_AUTOTUNE_CACHE", DEFAULT_CACHE)
+
+
+def size_class(n: int) -> int:
+    """Smallest power of two >= n (lattices of one class share a tuned shape)."""
+    c = 1
+    while c < n:
+        c *= 2
+    return c
+
+
+def key(device_name: str, precision: str, nx: int, ny: int, porosity_field: bool) -> str:
+    return f"{device_name}|{precision}|{size_class(nx)}x{size_class(ny)}|{'field' if porosity_field else 'uniform'}"
+
+
+def load(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store(entries: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: str | None = None,
+         force: bool = False):
+    """Apply the cached tile shape for this solver's class, or time all shapes and cache the
+    fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
+    k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field)
+    entries = load(path)
+    if not force and k in entries:
+        tx, ty = entries[k]["tile"]
+        solver.set_tile(tx, ty)
+        return (tx, ty), None
+    (tx, ty), ms = solver.autotune(steps)
+    entries = load(path)          # re-read: another process may have added entries
+    entries[k] = {"tile": [tx, ty], "ms_per_step": ms, "steps": steps}
+    store(entries, path)
+    return (tx, ty), ms

@@ -164,7 +164,8 @@ def _ptr(a):
 class Solver:
     """One cavity on the GPU.  ``precision`` is 'fp64', 'fp32' or 'fp16s'.  Device memory
     comes from a torch arena tensor on ``device`` and work runs on torch's current stream of
-    that device (or ``stream``, a torch.cuda.Stream)."""
+    that device (or ``stream``, a torch.cuda.Stream).  ``tile``: (tile_x, tile_y), or "auto"
+    for the cached autotuned shape of this lattice class (timed once per class)."""
 
     def __init__(self, params: dict, phi=None, T=None, C=None, ux=None, uy=None, precision="fp32",
                  device=None, stream=None, tile=None):
@@ -189,7 +190,10 @@ class Solver:
             shape = (self.ny, self.nx)
             arrs = [_host(a, shape) for a in (phi, T, C, ux, uy)]
             _check(lib().lbm_set_fields(self._h, *[_ptr(a) for a in arrs]), self._h, "lbm_set_fields")
-            if tile is not None:
+            if tile == "auto":
+                from . import autotune
+                autotune.tune(self, torch.cuda.get_device_name(self.device), phi is not None)
+            elif tile is not None:
                 self.set_tile(*tile)
 
     @property

@@ -277,3 +277,16 @@ def test_batch_alone_vs_mix_bitwise():
     mix[1].step(100)
     assert len(b) == 4
     b.close()
+
+
+def test_autotuned_tile_is_cached_and_changes_nothing(tmp_path, monkeypatch):
+    from paper_1708_07525_amd import autotune
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(tmp_path / "tiles.json"))
+    Solver = _solver()
+    case = workloads.grf_cavity(seed=1, n=96)
+    a = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision="fp32", tile="auto")
+    assert len(autotune.load()) == 1
+    b = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision="fp32", tile=(64, 8))
+    a.step(50)
+    b.step(50)
+    assert a.get_state() == b.get_state()
