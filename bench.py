@@ -267,7 +267,10 @@ def sweep_until_converged(a, cav):
         T, C = workloads.cavity_fields(e)
         reqs.append(Request(i, 0.0, e["params"], "fp32", None, T, C))
     srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
-    res, summ = srv.run(reqs)
+
+    def note(d):
+        print("progress", json.dumps(d), file=sys.stderr, flush=True)
+    res, summ = srv.run(reqs, progress=note)
     srv.close()
     steps_batched = {r.id: r.steps for r in res}
     node_steps = 0
@@ -287,6 +290,7 @@ def sweep_until_converged(a, cav):
         steps_alone[r.id] = n
         node_steps += s.nx * s.ny * n
         s.close()
+        print("one-by-one", r.id, n, round(time.perf_counter() - t0, 1), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out = {"metric": "aggregate MLUPS to steady state, batched vs one-by-one", "unit": "MLUPS",

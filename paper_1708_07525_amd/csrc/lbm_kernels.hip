@@ -523,12 +523,8 @@ __device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, cons
   }
 }
 
-#ifndef LBM_STEP_WAVES
-#define LBM_STEP_WAVES 1
-#endif
 template <typename S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES)))
-step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity) {
+__global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity) {
   const int t = Policy<S>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int cur = (d.base_parity ^ parity) & 1;
   const StepRes rs = step_resources<S>(d, cur);

@@ -101,14 +101,16 @@ class Server:
         self.used -= need
         return Result(req.id, req.arrival, adm, now, steps, conv, nodes, req.precision, ob, fields)
 
-    def run(self, requests, clock=time.perf_counter, log=None):
+    def run(self, requests, clock=time.perf_counter, log=None, progress=None, progress_every=10000):
         """Serve ``requests`` (sorted by arrival or not) to completion; returns the results in
-        completion order and a summary."""
+        completion order and a summary.  ``log(result)`` is called as each request retires,
+        ``progress(dict)`` every ``progress_every`` batched steps."""
         pending = [(r.arrival, r.id, r) for r in requests]
         heapq.heapify(pending)
         waiting = []
         results = []
         t0 = clock()
+        batched_steps = 0
         while pending or waiting or self.active:
             now = clock() - t0
             while pending and pending[0][0] <= now:
@@ -124,6 +126,10 @@ class Server:
             for a in self.active:
                 a[4] += self.chunk
                 self.node_steps += a[0].nx * a[0].ny * self.chunk
+            batched_steps += self.chunk
+            if progress and batched_steps % progress_every == 0:
+                progress(dict(t=clock() - t0, batched_steps=batched_steps, active=len(self.active),
+                              waiting=len(waiting), done=len(results)))
             # each cavity is checked on its own clock (every check_every of its steps), so a
             # request's trajectory and stopping step do not depend on what else is resident
             now = clock() - t0
