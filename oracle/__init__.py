@@ -16,7 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 
-SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3}
+SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
+        "nee_hot": 4, "nee_cold": 5, "nee_adiabatic": 6, "nee_robin": 7}
 MUTATION = {"none": 0, "no_source": 1, "no_half_force": 2, "rho_in_meq": 3, "buoy_sign": 4,
             "model_a_diff": 5, "no_forch": 6, "wall_const": 7}
 
@@ -32,7 +33,7 @@ DEFAULTS = dict(
     zeta0=1.0, zeta_e=1.5, zeta_eps=1.5, eta0=1.0, eta_e=1.5, eta_eps=1.5,
     Th=1.0, Tl=0.0, Ch=1.0, Cl=0.0,
     Fphi=-1.0, g_ext=(0.0, 0.0), wall_u=(0.0, 0.0, 0.0, 0.0),
-    direct=0, nu=0.0, alpha_e=0.0, D_e=0.0, K=0.0, gbT=0.0, gbC=0.0,
+    direct=0, nu=0.0, alpha_e=0.0, D_e=0.0, K=0.0, gbT=0.0, gbC=0.0, Bi_T=0.0, Bi_C=0.0,
 )
 
 
@@ -53,6 +54,7 @@ class _Params(ctypes.Structure):
         ("wall_u", ctypes.c_double * 4), ("direct", ctypes.c_int32),
         ("nu", ctypes.c_double), ("alpha_e", ctypes.c_double), ("D_e", ctypes.c_double),
         ("K", ctypes.c_double), ("gbT", ctypes.c_double), ("gbC", ctypes.c_double),
+        ("Bi_T", ctypes.c_double), ("Bi_C", ctypes.c_double),
     ]
 
 

@@ -185,6 +185,7 @@ static void velocity(double vx, double vy, double l0, double l1, double *ux, dou
 /* ---- state --------------------------------------------------------------------- */
 struct orc {
   orc_params p;
+  int nee;            /* walls through the boundary nodes (kinds 4-7) */
   int nx, ny;
   long nn;
   int ready;
@@ -210,9 +211,22 @@ static void *xcalloc(size_t n, size_t s) {
 orc *orc_create(const orc_params *p) {
   build_inverses();
   if (!p || p->nx < 3 || p->ny < 3) return NULL;
+  /* either every non-periodic side is a half-way wall (0-2) or every one is a wall through
+     the boundary nodes (4-7) */
+  int n_half = 0, n_node = 0;
+  for (int s = 0; s < 4; ++s) {
+    if (p->side[s] < 0 || p->side[s] > 7) return NULL;
+    if (p->side[s] <= 2) n_half++;
+    else if (p->side[s] >= 4) n_node++;
+  }
+  if (n_half && n_node) return NULL;
+  /* a node wall needs two more nodes inward (f and ff) before the opposite wall */
+  if (n_node && p->side[ORC_LEFT] != ORC_SIDE_PERIODIC && p->nx < 5) return NULL;
+  if (n_node && p->side[ORC_BOTTOM] != ORC_SIDE_PERIODIC && p->ny < 5) return NULL;
   orc *o = (orc *)xcalloc(1, sizeof(orc));
   if (!o) return NULL;
   o->p = *p;
+  o->nee = n_node > 0;
   o->nx = p->nx;
   o->ny = p->ny;
   o->nn = (long)p->nx * p->ny;
@@ -252,7 +266,8 @@ void orc_destroy(orc *o) {
 static int derive(orc *o) {
   const orc_params *p = &o->p;
   const double cs2 = 1.0 / 3.0;
-  o->L = o->nx;
+  /* the cavity width: nx for walls half a spacing outside, nx - 1 for walls through nodes */
+  o->L = o->nee ? o->nx - 1 : o->nx;
   o->dT = p->Th - p->Tl;
   o->T0 = 0.5 * (p->Th + p->Tl);
   o->dC = p->Ch - p->Cl;
@@ -521,7 +536,9 @@ static void stream_node(orc *o, int x, int y) {
         continue;
       }
       int side = side_of_link(i);
-      if (p->side[side] == ORC_SIDE_ADIABATIC) {
+      if (p->side[side] >= ORC_SIDE_NEE_HOT) {
+        dst[i * nn + k] = src[OPP[i] * nn + k];   /* placeholder: replaced by the extrapolation */
+      } else if (p->side[side] == ORC_SIDE_ADIABATIC) {
         dst[i * nn + k] = src[OPP[i] * nn + k];               /* zero flux: bounce-back */
       } else {
         /* fixed value: anti-bounce-back, g_i = -g*_opp + g^eq_i(w) + g^eq_opp(w) */
@@ -541,6 +558,101 @@ static void stream_node(orc *o, int x, int y) {
   }
 }
 
+/* Walls through the boundary nodes (section 3.3).  After streaming, every boundary node
+ * takes the populations of Eqs. (33)-(35):
+ *   f_i(b) = f_i^eq(rho_f, u_b) + [f_i(f) - f_i^eq(rho_f, u_f)],
+ *   g_i(b) = g_i^eq(T_b, u_b) + [g_i(f) - g_i^eq(T_f, u_f)],   h likewise with C,
+ * where f is the neighbouring node along the inward normal (the inward diagonal at a corner)
+ * and every value on the right is the streamed (pre-collision) state of this level.  T_b is
+ * the side's fixed value, or Eq. (36) with zero gradient, or Eq. (36) with the convective
+ * gradient of Eq. (39) (flux out = Bi/L (T_b - T_inf)):
+ *   T_b = (4 T_f - T_ff + 2 (Bi/L) T_inf) / (3 + 2 Bi/L),
+ * ff being the next node inward.  A corner takes its neighbours along the inward diagonal
+ * and the rule of one of its two sides, in this order: a fixed value of the left/right side,
+ * of the bottom/top side, a convective left/right side, a convective bottom/top side, else
+ * zero gradient (the diagonal step has unit component along each normal, so the rule of a
+ * side applies unchanged when the other side carries no flux); its wall velocity is zero. */
+static int is_fixed(int kind) { return kind == ORC_SIDE_NEE_HOT || kind == ORC_SIDE_NEE_COLD; }
+
+static void boundary_scalar(const orc *o, int kind, double sf, double sff, int conc, double *sb) {
+  const orc_params *p = &o->p;
+  if (kind == ORC_SIDE_NEE_HOT) { *sb = conc ? p->Ch : p->Th; return; }
+  if (kind == ORC_SIDE_NEE_COLD) { *sb = conc ? p->Cl : p->Tl; return; }
+  double beta = 0.0, amb = 0.0;
+  if (kind == ORC_SIDE_NEE_ROBIN) {
+    beta = (conc ? p->Bi_C : p->Bi_T) / o->L;
+    amb = conc ? p->Cl : p->Tl;
+  }
+  *sb = (4.0 * sf - sff + 2.0 * beta * amb) / (3.0 + 2.0 * beta);
+}
+
+static void apply_nee(orc *o) {
+  const orc_params *p = &o->p;
+  const int nx = o->nx, ny = o->ny;
+  const long nn = o->nn;
+  const int wx = p->side[ORC_LEFT] != ORC_SIDE_PERIODIC;    /* x sides are walls */
+  const int wy = p->side[ORC_BOTTOM] != ORC_SIDE_PERIODIC;
+  /* list of boundary nodes and their new populations, computed from the streamed state */
+  long nb = 0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x)
+      if ((wx && (x == 0 || x == nx - 1)) || (wy && (y == 0 || y == ny - 1))) nb++;
+  long *idx = malloc(nb * sizeof(long));
+  double *val = malloc(nb * 19 * sizeof(double));
+  if (!idx || !val) { free(idx); free(val); return; }
+  long m = 0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int onx = wx && (x == 0 || x == nx - 1), ony = wy && (y == 0 || y == ny - 1);
+      if (!onx && !ony) continue;
+      const int sx = x == 0 ? ORC_LEFT : ORC_RIGHT, sy = y == 0 ? ORC_BOTTOM : ORC_TOP;
+      const int dx = onx ? (x == 0 ? 1 : -1) : 0, dy = ony ? (y == 0 ? 1 : -1) : 0;
+      const long kb = (long)y * nx + x;
+      const long kf = (long)(y + dy) * nx + (x + dx);
+      const long kff = (long)(y + 2 * dy) * nx + (x + 2 * dx);
+      node_macro qf, qff;
+      node_fields(o, kf, &qf);
+      node_fields(o, kff, &qff);
+      double ubx = 0.0, uby = 0.0, Tb, Cb;
+      if (onx && ony) {
+        const int kx = p->side[sx], ky = p->side[sy];
+        int kind = ORC_SIDE_NEE_ADIABATIC;
+        if (is_fixed(kx)) kind = kx;
+        else if (is_fixed(ky)) kind = ky;
+        else if (kx == ORC_SIDE_NEE_ROBIN) kind = kx;
+        else if (ky == ORC_SIDE_NEE_ROBIN) kind = ky;
+        boundary_scalar(o, kind, qf.T, qff.T, 0, &Tb);
+        boundary_scalar(o, kind, qf.C, qff.C, 1, &Cb);
+      } else {
+        const int side = onx ? sx : sy;
+        if (onx) uby = p->wall_u[side];
+        else ubx = p->wall_u[side];
+        boundary_scalar(o, p->side[side], qf.T, qff.T, 0, &Tb);
+        boundary_scalar(o, p->side[side], qf.C, qff.C, 1, &Cb);
+      }
+      const double phib = o->phi[kb], phif = o->phi[kf];
+      double eb[9], ef[9], gb[5], gf[5], hb[5], hf[5];
+      feq9(qf.rho, ubx, uby, phib, p->rho0, eb);               /* Eq. (33) */
+      feq9(qf.rho, qf.ux, qf.uy, phif, p->rho0, ef);
+      geq5(Tb, ubx, uby, p->sigma, o->varpi, p->model, gb);    /* Eq. (34) */
+      geq5(qf.T, qf.ux, qf.uy, p->sigma, o->varpi, p->model, gf);
+      geq5(Cb, ubx, uby, phib, o->varpi, p->model, hb);        /* Eq. (35) */
+      geq5(qf.C, qf.ux, qf.uy, phif, o->varpi, p->model, hf);
+      idx[m] = kb;
+      for (int i = 0; i < 9; ++i) val[m * 19 + i] = eb[i] + (o->f[i * nn + kf] - ef[i]);
+      for (int i = 0; i < 5; ++i) val[m * 19 + 9 + i] = gb[i] + (o->g[i * nn + kf] - gf[i]);
+      for (int i = 0; i < 5; ++i) val[m * 19 + 14 + i] = hb[i] + (o->h[i * nn + kf] - hf[i]);
+      m++;
+    }
+  for (long j = 0; j < nb; ++j) {
+    for (int i = 0; i < 9; ++i) o->f[i * nn + idx[j]] = val[j * 19 + i];
+    for (int i = 0; i < 5; ++i) o->g[i * nn + idx[j]] = val[j * 19 + 9 + i];
+    for (int i = 0; i < 5; ++i) o->h[i * nn + idx[j]] = val[j * 19 + 14 + i];
+  }
+  free(idx);
+  free(val);
+}
+
 int orc_step(orc *o, int64_t nsteps) {
   if (!o || !o->ready) return -1;
   const int nx = o->nx, ny = o->ny;
@@ -551,6 +663,7 @@ int orc_step(orc *o, int64_t nsteps) {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) stream_node(o, x, y);
+    if (o->nee) apply_nee(o);
     o->step++;
   }
   return 0;
@@ -608,6 +721,31 @@ static double wall_number(const orc *o, const double *s, int side, double sw, do
   return sum / n_along;
 }
 
+/* Eq. (38) at a wall through the boundary nodes: second-order one-sided gradient
+ * (-3 s_b + 4 s_1 - s_2)/2 along the inward normal, trapezoidal mean along the wall.  Heat
+ * leaving through a cold or convective side counts positive, as at a hot side entering. */
+static double wall_number_nodes(const orc *o, const double *s, int side, double ds) {
+  const int nx = o->nx, ny = o->ny;
+  const int kind = o->p.side[side];
+  if (ds == 0.0 || kind == ORC_SIDE_NEE_ADIABATIC) return 0.0;
+  const double sign = kind == ORC_SIDE_NEE_HOT ? -1.0 : 1.0;
+  int n_along = (side == ORC_LEFT || side == ORC_RIGHT) ? ny : nx;
+  double sum = 0.0;
+  for (int a = 0; a < n_along; ++a) {
+    long k0, k1, k2;
+    switch (side) {
+      case ORC_LEFT: k0 = (long)a * nx; k1 = k0 + 1; k2 = k0 + 2; break;
+      case ORC_RIGHT: k0 = (long)a * nx + nx - 1; k1 = k0 - 1; k2 = k0 - 2; break;
+      case ORC_BOTTOM: k0 = a; k1 = (long)nx + a; k2 = 2L * nx + a; break;
+      default: k0 = (long)(ny - 1) * nx + a; k1 = k0 - nx; k2 = k0 - 2L * nx; break;
+    }
+    const double dn = (-3.0 * s[k0] + 4.0 * s[k1] - s[k2]) / 2.0;
+    const double w = (a == 0 || a == n_along - 1) ? 0.5 : 1.0;
+    sum += w * sign * o->L * dn / ds;
+  }
+  return sum / (n_along - 1);
+}
+
 int orc_observables(orc *o, orc_obs *out) {
   if (!o || !o->ready || !out) return -1;
   long nn = o->nn;
@@ -628,6 +766,9 @@ int orc_observables(orc *o, orc_obs *out) {
       wall_values(o, s, &Tw, &Cw);
       out->Nu[s] = wall_number(o, T, s, Tw, o->dT);
       out->Sh[s] = wall_number(o, C, s, Cw, o->dC);
+    } else if (kind >= ORC_SIDE_NEE_HOT) {
+      out->Nu[s] = wall_number_nodes(o, T, s, o->dT);
+      out->Sh[s] = wall_number_nodes(o, C, s, o->dC);
     }
   }
   double du2 = 0, u2 = 0, dT2 = 0, T2 = 0, dC2 = 0, C2 = 0;

@@ -20,8 +20,15 @@
 extern "C" {
 #endif
 
-/* kinds of a side of the rectangular domain */
-enum { ORC_SIDE_HOT = 0, ORC_SIDE_COLD = 1, ORC_SIDE_ADIABATIC = 2, ORC_SIDE_PERIODIC = 3 };
+/* kinds of a side of the rectangular domain.  0-2: wall half a spacing outside the first
+ * node (bounce-back rules); 4-7: wall through the first node, whose populations are set by
+ * the non-equilibrium extrapolation of Eqs. (33)-(35), with T and C fixed (hot/cold), from
+ * the zero-flux extrapolation of Eqs. (36)-(37), or from the convective (Robin) condition of
+ * Eq. (39) through Eqs. (36)-(37). */
+enum {
+  ORC_SIDE_HOT = 0, ORC_SIDE_COLD = 1, ORC_SIDE_ADIABATIC = 2, ORC_SIDE_PERIODIC = 3,
+  ORC_SIDE_NEE_HOT = 4, ORC_SIDE_NEE_COLD = 5, ORC_SIDE_NEE_ADIABATIC = 6, ORC_SIDE_NEE_ROBIN = 7
+};
 /* side order */
 enum { ORC_LEFT = 0, ORC_RIGHT = 1, ORC_BOTTOM = 2, ORC_TOP = 3 };
 /* deliberate mistakes a test can plant in the oracle to show that a pin catches them */
@@ -54,6 +61,7 @@ typedef struct orc_params {
                                  1: take the lattice values below as given */
   double nu, alpha_e, D_e, K, gbT, gbC;  /* lattice viscosity, diffusivities, mean permeability,
                                             g*beta_T and g*beta_C, used when direct == 1 */
+  double Bi_T, Bi_C;          /* Biot numbers of a convective side (Eq. 39); ambient Tl, Cl */
 } orc_params;
 
 typedef struct orc orc;

@@ -243,3 +243,47 @@ def buoyancy_cancellation(make, n=20, steps=1500, seed=9, **extra):
     ob = s.observables()
     return (float(max(np.abs(F["ux"]).max(), np.abs(F["uy"]).max())), float(np.abs(F["T"] - F["C"]).max()),
             ob["Nu"][0], ob["Sh"][0])
+
+
+# ------------------------------------------------------------------ walls through the nodes
+
+NODE_CAVITY = ("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")
+
+
+def nee_conduction(make, nx=12, ny=6, sigma=1.5, phi=0.7, steps=8000, robin_bi=None, **extra):
+    """Conduction with walls through the boundary nodes (Eqs. 33-37): hot left wall; right
+    wall cold, or convective with Biot number Bi (Eq. 39, flux out = Bi/L (T_b - T_inf), with
+    L = nx - 1 the wall-to-wall width and T_inf = Tl); zero-flux top and bottom.  The steady
+    profile is linear and the schemes are exact for it: T = Th - (Th - T_R) x/(nx - 1) with
+    T_R = Tl, or T_R = (Th + Bi T_inf)/(1 + Bi).  Returns (max |T - exact|, max |C - exact|,
+    Nu at the left, the exact Nu)."""
+    sides = ("nee_hot", "nee_robin" if robin_bi is not None else "nee_cold", "nee_adiabatic", "nee_adiabatic")
+    p = dict(nx=nx, ny=ny, sides=sides, sigma=sigma, phi=phi, nu=0.1, alpha_e=0.15, D_e=0.1, K=1e30,
+             Bi_T=robin_bi or 0.0, Bi_C=robin_bi or 0.0, **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    TR = 0.0 if robin_bi is None else 1.0 / (1.0 + robin_bi)
+    exact = 1.0 - (1.0 - TR) * np.arange(nx) / (nx - 1)
+    ob = s.observables()
+    return (float(np.abs(F["T"] - exact[None, :]).max()), float(np.abs(F["C"] - exact[None, :]).max()),
+            ob["Nu"][0], 1.0 - TR)
+
+
+def nee_poiseuille(make, nx, J=2.0, nu=0.05, K16=50.0, phi=0.7, G=1e-5, steps=None, **extra):
+    """Brinkman channel flow with no-slip walls through the nodes x = 0 and x = nx - 1
+    (u_b = 0 imposed by Eq. 33), periodic in y; closed form with width W = nx - 1:
+    u = (G K/nu) [1 - cosh(r (x - W/2))/cosh(r W/2)].  Returns the relative L2 error."""
+    K = K16 * (nx / 16.0) ** 2
+    p = dict(nx=nx, ny=3, sides=("nee_adiabatic", "nee_adiabatic", "periodic", "periodic"), J=J, phi=phi,
+             nu=nu, alpha_e=0.1, D_e=0.1, K=K, g_ext=(0.0, G), **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps or int(20 * nx * nx / (J * nu)))
+    u = s.fields()["uy"][1]
+    x = np.arange(nx)
+    W = nx - 1
+    r = np.sqrt(phi * nu / (J * nu * K))
+    ua = (G * K / nu) * (1.0 - np.cosh(r * (x - W / 2.0)) / np.cosh(r * W / 2.0))
+    return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))

@@ -378,3 +378,29 @@ def test_oracle_rejects_bad_input():
         Oracle(dict(nx=2, ny=8))
     with pytest.raises(ValueError):
         Oracle(dict(nx=8, ny=8), phi=np.full((8, 8), 1.5))
+
+
+# -------------------------------------------- walls through the boundary nodes (section 3.3)
+
+def test_nee_linear_conduction_is_exact():
+    eT, eC, Nu, exact = pins.nee_conduction(make_oracle)
+    assert eT < 1e-12 and eC < 1e-12
+    assert Nu == pytest.approx(exact, abs=1e-11)
+
+
+@pytest.mark.parametrize("bi", [1.0, 200.0])
+def test_convective_wall_is_exact(bi):
+    eT, eC, Nu, exact = pins.nee_conduction(make_oracle, robin_bi=bi)
+    assert eT < 1e-11 and eC < 1e-11
+    assert Nu == pytest.approx(exact, abs=1e-10)
+
+
+def test_nee_brinkman_poiseuille_second_order():
+    e16 = pins.nee_poiseuille(make_oracle, 17)
+    e32 = pins.nee_poiseuille(make_oracle, 33)
+    assert e32 < 3e-3
+    assert 3.0 < e16 / e32 < 5.0, (e16, e32)
+
+
+def test_nee_cavity_centro_symmetry():
+    assert pins.cavity_symmetry(make_oracle, sides=pins.NODE_CAVITY) < 1e-12
