@@ -59,21 +59,34 @@ typedef enum lbm_status {
  * the source term of Eq. (27) stay FP32. */
 typedef enum lbm_precision { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
 
-/* Kind of a side of the rectangle.  HOT holds T = Th and C = Ch, COLD holds T = Tl and
- * C = Cl (anti-bounce-back for g, h); ADIABATIC is zero flux for T and C (bounce-back).  All
- * three are impermeable no-slip walls for f (half-way bounce-back, moving with wall_u).
- * PERIODIC must be set on both left and right, or on both bottom and top. */
+/* Kind of a side of the rectangle.
+ * 0-2: the wall lies half a spacing outside the first node.  HOT holds T = Th and C = Ch,
+ *      COLD holds T = Tl and C = Cl (anti-bounce-back for g, h, constant from Eq. 28);
+ *      ADIABATIC is zero flux for T and C (bounce-back).  All three are impermeable no-slip
+ *      walls for f (half-way bounce-back, moving with wall_u).  L = nx.
+ * 4-7: the wall passes through the first node (section 3.3): the boundary node's populations
+ *      come from the non-equilibrium extrapolation of Eqs. (33)-(35) with the wall velocity
+ *      wall_u and T, C fixed (NEE_HOT, NEE_COLD), extrapolated with zero gradient
+ *      (NEE_ADIABATIC, Eqs. 36-37) or with the convective condition of Eq. (39)
+ *      (NEE_ROBIN: flux out = Bi/L (T_b - Tl), Bi_T and Bi_C below).  L = nx - 1.
+ *      Needs nx >= 5 (ny >= 5) for walls on the x (y) sides.
+ * The two families cannot be mixed in one cavity.  PERIODIC must be set on both left and
+ * right, or on both bottom and top. */
 typedef enum lbm_side {
   LBM_SIDE_HOT = 0,
   LBM_SIDE_COLD = 1,
   LBM_SIDE_ADIABATIC = 2,
-  LBM_SIDE_PERIODIC = 3
+  LBM_SIDE_PERIODIC = 3,
+  LBM_SIDE_NEE_HOT = 4,
+  LBM_SIDE_NEE_COLD = 5,
+  LBM_SIDE_NEE_ADIABATIC = 6,
+  LBM_SIDE_NEE_ROBIN = 7
 } lbm_side;
 
 enum { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
 
 typedef struct lbm_params {
-  int32_t nx, ny;        /* lattice nodes; walls lie half a spacing outside; L = nx      */
+  int32_t nx, ny;        /* lattice nodes; L = nx (or nx - 1 for walls through the nodes)  */
   int32_t precision;     /* lbm_precision                                               */
   int32_t model;         /* 0: present model (Eqs. 24-25, 29); 1: Model-A (Eqs. 30-32)    */
   int32_t side[4];       /* lbm_side of left, right, bottom, top                         */
@@ -91,6 +104,7 @@ typedef struct lbm_params {
   int32_t direct;             /* 1: take nu, alpha_e, D_e, K, gbT, gbC below as lattice values
                                  instead of mapping Ra, Pr, Le, Da, N, Ma                 */
   double nu, alpha_e, D_e, K, gbT, gbC;
+  double Bi_T, Bi_C;          /* Biot numbers of a NEE_ROBIN side (Eq. 39)                 */
   void *stream;               /* hipStream_t for all work of the context (NULL: null stream) */
   void *arena;                /* optional device memory for every buffer of the context   */
   uint64_t arena_bytes;       /* size of arena; must be >= lbm_footprint_bytes()          */
@@ -195,7 +209,9 @@ typedef struct lbm_batch lbm_batch;
  * stream: hipStream_t the batch runs on (NULL: null stream). */
 lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *stream, lbm_batch **out);
 /* The context must be initialised (lbm_set_fields), on the batch's device and not in
- * another batch; its work moves to the batch's stream until detached. */
+ * another batch; its work moves to the batch's stream until detached.  A context with
+ * walls through the boundary nodes (LBM_NEE_* sides) is refused with LBM_EINVAL: it
+ * advances with lbm_step only. */
 lbm_status lbm_batch_attach(lbm_batch *b, struct lbm_ctx *c);
 lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
 /* Advances every attached context by nsteps (asynchronous). */

@@ -145,8 +145,16 @@ lbm_status validate(const lbm_params *p, std::string &msg) {
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return bad("lattice too large");
   if (p->precision < 0 || p->precision > 2) return bad("unknown precision");
   if (p->model != 0 && p->model != 1) return bad("model must be 0 (present) or 1 (Model-A)");
-  for (int s = 0; s < 4; ++s)
-    if (p->side[s] < 0 || p->side[s] > 3) return bad("unknown side kind");
+  int n_half = 0, n_node = 0;
+  for (int s = 0; s < 4; ++s) {
+    if (p->side[s] < 0 || p->side[s] > 7) return bad("unknown side kind");
+    if (p->side[s] <= SIDE_ADIABATIC) n_half++;
+    if (p->side[s] >= SIDE_NEE_HOT) n_node++;
+  }
+  if (n_half && n_node) return bad("walls half a spacing outside and walls through the nodes cannot be mixed");
+  if (n_node && p->side[LEFT] != SIDE_PERIODIC && p->nx < 5) return bad("walls through the nodes need nx >= 5");
+  if (n_node && p->side[BOTTOM] != SIDE_PERIODIC && p->ny < 5) return bad("walls through the nodes need ny >= 5");
+  if (!(p->Bi_T >= 0.0) || !(p->Bi_C >= 0.0)) return bad("Biot numbers must be >= 0");
   if ((p->side[LEFT] == SIDE_PERIODIC) != (p->side[RIGHT] == SIDE_PERIODIC) ||
       (p->side[BOTTOM] == SIDE_PERIODIC) != (p->side[TOP] == SIDE_PERIODIC))
     return bad("periodic sides must come in opposite pairs");
@@ -169,8 +177,15 @@ lbm_status validate(const lbm_params *p, std::string &msg) {
 }
 
 // Lattice values of sections 2 and 4.1 (nothing that needs the porosity field).
+bool node_walls(const lbm_params *p) {
+  for (int s = 0; s < 4; ++s)
+    if (p->side[s] >= SIDE_NEE_HOT) return true;
+  return false;
+}
+
 void map_params(const lbm_params *p, lbm_derived &d) {
-  d.L = p->nx;
+  // cavity width: nx for walls half a spacing outside, nx - 1 for walls through the nodes
+  d.L = node_walls(p) ? p->nx - 1 : p->nx;
   d.dT = p->Th - p->Tl;
   d.T0 = 0.5 * (p->Th + p->Tl);
   d.dC = p->Ch - p->Cl;
@@ -293,12 +308,26 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     }
     D.scale = (R)d.fp16_scale;
     D.inv_scale = (R)(1.0 / d.fp16_scale);
+    D.nee = node_walls(p);
+    for (int s = 0; s < 4; ++s) {
+      const bool hot = p->side[s] == SIDE_NEE_HOT;
+      D.Tfix[s] = (R)((hot ? p->Th : p->Tl) - d.T0);
+      D.Cfix[s] = (R)((hot ? p->Ch : p->Cl) - d.C0);
+      D.betaT[s] = (R)(p->side[s] == SIDE_NEE_ROBIN ? p->Bi_T / d.L : 0.0);
+      D.betaC[s] = (R)(p->side[s] == SIDE_NEE_ROBIN ? p->Bi_C / d.L : 0.0);
+    }
+    D.Tinf = (R)(p->Tl - d.T0);
+    D.Cinf = (R)(p->Cl - d.C0);
+    D.kg0 = (R)(p->model == 0 ? p->sigma - d.varpi : (1.0 - d.varpi) * p->sigma);
+    D.capT = (R)capT;
+    D.capC = (R)capC;
   };
   fill(c->d64);
   fill(c->d32);
   for (int s = 0; s < 4; ++s) {
-    c->wallT[s] = p->side[s] == SIDE_HOT ? p->Th : p->Tl;
-    c->wallC[s] = p->side[s] == SIDE_HOT ? p->Ch : p->Cl;
+    const bool hot = p->side[s] == SIDE_HOT || p->side[s] == SIDE_NEE_HOT;
+    c->wallT[s] = hot ? p->Th : p->Tl;
+    c->wallC[s] = hot ? p->Ch : p->Cl;
   }
   return LBM_OK;
 }
@@ -847,6 +876,7 @@ lbm_status batch_upload(lbm_batch *b) {
   return LBM_OK;
 }
 
+// bit prec: some cavity of that precision is attached
 unsigned batch_mask(const lbm_batch *b) {
   unsigned m = 0;
   for (lbm_ctx *c : b->ctx) m |= 1u << c->prec;
@@ -913,6 +943,7 @@ LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   if (!c->ready) return fail(c, LBM_ESTATE, "attach before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context already in a batch");
   if ((int)b->ctx.size() >= b->cap) return fail(c, LBM_ENOMEM, "batch is full");
+  if (node_walls(&c->p)) return fail(c, LBM_EINVAL, "walls through the boundary nodes are not batched");
   // make prior work of the context visible to the batch stream
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before attach");
   c->in_batch = true;

@@ -17,7 +17,8 @@
 
 namespace lbmk {
 
-enum { SIDE_HOT = 0, SIDE_COLD = 1, SIDE_ADIABATIC = 2, SIDE_PERIODIC = 3 };
+enum { SIDE_HOT = 0, SIDE_COLD = 1, SIDE_ADIABATIC = 2, SIDE_PERIODIC = 3,
+       SIDE_NEE_HOT = 4, SIDE_NEE_COLD = 5, SIDE_NEE_ADIABATIC = 6, SIDE_NEE_ROBIN = 7 };
 enum { LEFT = 0, RIGHT = 1, BOTTOM = 2, TOP = 3 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
 constexpr int NPOP = 19;       // 9 + 5 + 5 planes
@@ -48,6 +49,12 @@ struct Desc {
   R wT[4], wC[4];          // anti-bounce-back constants (deviation form) per side
   R uw[4];                 // 6 rho0 u_wall per side (moving-wall term of the bounce-back)
   R scale, inv_scale;      // FP16 pre-scale (1 for FP32/FP64)
+  // walls through the boundary nodes (side kinds 4-7)
+  int nee, pad2_[3];
+  R Tfix[4], Cfix[4];      // fixed T - T0, C - C0 of each side (kinds 4, 5)
+  R betaT[4], betaC[4];    // Bi/L of each side (kind 7), 0 otherwise
+  R Tinf, Cinf;            // ambient of a convective side, as T - T0, C - C0
+  R kg0, capT, capC;       // g0 equilibrium factor and the T, C capacities of g_i^eq, h_i^eq
 };
 
 struct Item {              // one tile of one cavity, for the batched kernel: tw nodes along x
@@ -64,8 +71,8 @@ struct Tile {
 int launch_init(int prec, const void *desc, const double *T, const double *C, const double *ux,
                 const double *uy, void *stream);
 int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream);
-int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems,
-                      int grid, int parity, void *stream);
+int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int parity,
+                      void *stream);
 // observables: partial sums per block, then a final fixed-order reduction.
 // out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)
 int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials,

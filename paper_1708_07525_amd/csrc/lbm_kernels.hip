@@ -379,6 +379,218 @@ __device__ __forceinline__ void store_pop(typename St<S>::R v, typename St<S>::R
   }
 }
 
+// ---------------------------------------------------------------- walls through the nodes
+// Side kinds 4-7 put the wall through the first and last node of a direction.  A boundary
+// node's pre-collision populations are then given by the non-equilibrium extrapolation of
+// Eqs. (33)-(35) from its neighbour f along the inward normal (the inward diagonal at a
+// corner):  x_b <- x^eq(b) + [x(f) - x^eq(f)], with rho_f and the wall velocity for f, and
+// the boundary T, C for g, h: the side's fixed value, or Eq. (36)-(37) with zero gradient or
+// with the convective gradient of Eq. (39):  T_b = (4 T_f - T_ff + 2 beta T_inf)/(3 + 2 beta),
+// beta = Bi/L.  The pre-collision values of f and ff are the pulls of this same step, which
+// the boundary thread recomputes from the previous level (every upstream node of f lies in
+// the domain).  The boundary nodes are updated by work-groups of their own at the front of
+// the step launch (nee_node); the tiles skip them, so the tile code keeps the registers and
+// occupancy of the plain update.  A corner takes the rule of one of
+// its sides: fixed left/right, fixed bottom/top, convective left/right, convective
+// bottom/top, else zero gradient; its wall velocity is zero.
+template <typename S>
+__device__ __forceinline__ void pull_inner(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
+                                           typename St<S>::R *fd, typename St<S>::R *gd, typename St<S>::R *hd) {
+  using R = typename St<S>::R;
+  using IO = BufIO<S>;
+  constexpr uint32_t ES = sizeof(S);
+  const uint32_t PB = (uint32_t)d.plane * ES;
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const int xm = x > 0 ? x - 1 : nx - 1, xp = x < nx - 1 ? x + 1 : 0;
+  const uint32_t rm = (uint32_t)(y > 0 ? y - 1 : ny - 1) * pitch, rp = (uint32_t)(y < ny - 1 ? y + 1 : 0) * pitch;
+  const uint32_t r0 = (uint32_t)y * pitch;
+  const uint32_t up[9] = {r0 + x, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+  const R is = d.inv_scale;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fd[i] = to_real<S>(IO::ld(rs.src, up[i] * ES, (uint32_t)i * PB), is);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    gd[i] = to_real<S>(IO::ld(rs.src, up[i] * ES, (uint32_t)(9 + i) * PB), is);
+    hd[i] = to_real<S>(IO::ld(rs.src, up[i] * ES, (uint32_t)(14 + i) * PB), is);
+  }
+}
+
+// rho - rho0, u, T - T0 and C - C0 of pre-collision populations (Eqs. 16-19, 26)
+template <typename R>
+__device__ __forceinline__ void node_fields(const Desc<R> &d, R phi, R a, R b, const R *fd, const R *gd, const R *hd,
+                                            R &drho, R &ux, R &uy, R &dT, R &dC) {
+  const R half = R(0.5);
+  drho = fd[0] + (fd[1] + fd[2] + fd[3] + fd[4]) + (fd[5] + fd[6] + fd[7] + fd[8]);
+  const R jx = (fd[1] - fd[3]) + (fd[5] - fd[6]) - (fd[7] - fd[8]);
+  const R jy = (fd[2] - fd[4]) + (fd[5] + fd[6]) - (fd[7] + fd[8]);
+  dT = (gd[0] + gd[1] + gd[2] + gd[3] + gd[4]) * d.inv_sigma;
+  dC = (hd[0] + hd[1] + hd[2] + hd[3] + hd[4]) / phi;
+  R Gy;
+  {
+#pragma clang fp contract(off)
+    const R bT = d.gbT * dT;
+    const R bC = d.gbC * dC;
+    Gy = d.gy + (bT + bC);
+  }
+  const R vx = jx * d.inv_rho0 + half * phi * d.gx;
+  const R vy = jy * d.inv_rho0 + half * phi * Gy;
+  const R l0 = half + R(0.25) * a, l1 = half * b;
+  const R inv_den = R(1) / (l0 + sqrt_(l0 * l0 + l1 * sqrt_(vx * vx + vy * vy)));
+  ux = vx * inv_den;
+  uy = vy * inv_den;
+}
+
+// deviation-form equilibria: Eq. (20) minus w_i rho0; Eq. (28) (or the Model-A form) minus
+// its value at (T0, u = 0)
+template <typename R>
+__device__ __forceinline__ void feq_dev(const Desc<R> &d, R drho, R ux, R uy, R phi, R *e) {
+  const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const R W[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                  R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+  const R ip = R(1) / phi, u2 = ux * ux + uy * uy;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const R eu = R(EX[i]) * ux + R(EY[i]) * uy;
+    e[i] = W[i] * (drho + d.rho0 * (R(3) * eu + R(4.5) * eu * eu * ip - R(1.5) * u2 * ip));
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void seq_dev(const Desc<R> &d, R ds, R s, R ux, R uy, R e0, R cap, R *e) {
+  const R q = R(0.25) * d.varpi * cap * ds, hs = R(0.5) * s;
+  e[0] = e0 * ds;
+  e[1] = q + hs * ux;
+  e[2] = q + hs * uy;
+  e[3] = q - hs * ux;
+  e[4] = q - hs * uy;
+}
+
+template <typename R>
+__device__ __forceinline__ R boundary_scalar(int kind, R fixed, R beta, R amb, R sf, R sff) {
+  if (kind == SIDE_NEE_HOT || kind == SIDE_NEE_COLD) return fixed;
+  return (R(4) * sf - sff + R(2) * beta * amb) / (R(3) + R(2) * beta);
+}
+
+// The boundary update of node (x, y): bx / by mark a wall through the node in x / y.  Every
+// load it needs (the pulls of f and ff, the porosities, the previous-step fields of the
+// node) is issued before any arithmetic, so a boundary thread waits for memory once.
+template <typename S>
+__device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y, bool bx,
+                                          bool by, typename St<S>::R *fd, typename St<S>::R *gd,
+                                          typename St<S>::R *hd, typename St<S>::R *prev, typename St<S>::R &phib) {
+  using R = typename St<S>::R;
+  const int dx = bx ? (x == 0 ? 1 : -1) : 0, dy = by ? (y == 0 ? 1 : -1) : 0;
+  const int sx = x == 0 ? LEFT : RIGHT, sy = y == 0 ? BOTTOM : TOP;
+  int side, kind;
+  R ubx = R(0), uby = R(0);
+  if (bx && by) {
+    const int kx = d.kind[sx], ky = d.kind[sy];
+    auto fixed = [](int k) { return k == SIDE_NEE_HOT || k == SIDE_NEE_COLD; };
+    side = fixed(kx) ? sx : fixed(ky) ? sy : kx == SIDE_NEE_ROBIN ? sx : ky == SIDE_NEE_ROBIN ? sy : sx;
+    kind = (fixed(kx) || fixed(ky) || kx == SIDE_NEE_ROBIN || ky == SIDE_NEE_ROBIN) ? d.kind[side] : SIDE_NEE_ADIABATIC;
+  } else {
+    side = bx ? sx : sy;
+    kind = d.kind[side];
+    if (bx) uby = d.uw[side] * R(1.0 / 6.0);
+    else ubx = d.uw[side] * R(1.0 / 6.0);
+  }
+  const bool fixed_scalars = kind == SIDE_NEE_HOT || kind == SIDE_NEE_COLD;
+  // loads: pre-collision state of f and ff (the pulls of this step), porosities, and the
+  // previous-step fields of the boundary node
+  const int xf = x + dx, yf = y + dy, xff = x + 2 * dx, yff = y + 2 * dy;
+  const uint32_t RS = sizeof(R), PR = (uint32_t)d.plane * RS;
+  const uint32_t cb = ((uint32_t)y * d.pitch + x) * RS;
+  R ff[9], gf[5], hf[5], f2[9], g2[5], h2[5];
+  pull_inner<S>(d, rs, xf, yf, ff, gf, hf);
+  pull_inner<S>(d, rs, xff, yff, f2, g2, h2);
+  R phif = d.phi_u, phiff = d.phi_u;
+  phib = d.phi_u;
+  if (d.phi_field) {
+    phib = BufIO<R>::ld(rs.phi, cb, 0);
+    phif = BufIO<R>::ld(rs.phi, ((uint32_t)yf * d.pitch + xf) * RS, 0);
+    phiff = BufIO<R>::ld(rs.phi, ((uint32_t)yff * d.pitch + xff) * RS, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) prev[k] = BufIO<R>::ld(rs.d4, cb, (uint32_t)k * PR);
+  R af, bf;
+  porous_coeffs(d, phif, af, bf);
+  R drho, uxf, uyf, dTf, dCf;
+  node_fields(d, phif, af, bf, ff, gf, hf, drho, uxf, uyf, dTf, dCf);
+  R dTb = d.Tfix[side], dCb = d.Cfix[side];
+  if (!fixed_scalars) {
+    const R dTff = (g2[0] + g2[1] + g2[2] + g2[3] + g2[4]) * d.inv_sigma;
+    const R dCff = (h2[0] + h2[1] + h2[2] + h2[3] + h2[4]) / phiff;
+    const R bT = kind == SIDE_NEE_ROBIN ? d.betaT[side] : R(0);
+    const R bC = kind == SIDE_NEE_ROBIN ? d.betaC[side] : R(0);
+    // Eq. (36) is linear, so it holds for the deviations T - T0 as well
+    dTb = boundary_scalar(kind, dTb, bT, d.Tinf, dTf, dTff);
+    dCb = boundary_scalar(kind, dCb, bC, d.Cinf, dCf, dCff);
+  }
+  R eb[9], ef[9];
+  feq_dev(d, drho, ubx, uby, phib, eb);      // Eq. (33): rho of f, velocity of the wall
+  feq_dev(d, drho, uxf, uyf, phif, ef);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fd[i] = eb[i] + (ff[i] - ef[i]);
+  R sb[5], sf[5];
+  seq_dev(d, dTb, d.T0 + dTb, ubx, uby, d.kg0, d.capT, sb);   // Eq. (34)
+  seq_dev(d, dTf, d.T0 + dTf, uxf, uyf, d.kg0, d.capT, sf);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) gd[i] = sb[i] + (gf[i] - sf[i]);
+  const R h0b = d.model == 0 ? phib - d.varpi : (R(1) - d.varpi) * phib;
+  const R h0f = d.model == 0 ? phif - d.varpi : (R(1) - d.varpi) * phif;
+  seq_dev(d, dCb, d.C0 + dCb, ubx, uby, h0b, d.model == 0 ? R(1) : phib, sb);   // Eq. (35)
+  seq_dev(d, dCf, d.C0 + dCf, uxf, uyf, h0f, d.model == 0 ? R(1) : phif, sf);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) hd[i] = sb[i] + (hf[i] - sf[i]);
+}
+
+// Second half of a node update: collision (moment space) with the previous-step fields
+// `prev`, then the stores.
+template <typename S>
+__device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
+                                              uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
+                                              typename St<S>::R *gd, typename St<S>::R *hd, typename St<S>::R *prev) {
+  using R = typename St<S>::R;
+  constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
+  const uint32_t PB = (uint32_t)d.plane * ES;
+  const uint32_t PR = (uint32_t)d.plane * RS;
+  const uint32_t cr = c * RS;
+  R a, b;
+  porous_coeffs(d, phi, a, b);
+  collide(d, phi, a, b, fd, gd, hd, prev);
+  const R sc = d.scale;
+  const uint32_t co = c * ES;
+  Dither dz(c, step);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) store_pop<S>(fd[i], sc, rs.dst, co, (uint32_t)i * PB, dz);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) store_pop<S>(gd[i], sc, rs.dst, co, (uint32_t)(9 + i) * PB, dz);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) store_pop<S>(hd[i], sc, rs.dst, co, (uint32_t)(14 + i) * PB, dz);
+  BufIO<R>::st(prev[0], rs.d4, cr, 0);
+  BufIO<R>::st(prev[1], rs.d4, cr, PR);
+  BufIO<R>::st(prev[2], rs.d4, cr, 2 * PR);
+  BufIO<R>::st(prev[3], rs.d4, cr, 3 * PR);
+}
+
+// Second half of an interior or half-way-wall node update: previous-step fields, then
+// collide_store.
+template <typename S>
+__device__ __forceinline__ void finish_node(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
+                                            uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
+                                            typename St<S>::R *gd, typename St<S>::R *hd) {
+  using R = typename St<S>::R;
+  const uint32_t PR = (uint32_t)d.plane * (uint32_t)sizeof(R);
+  const uint32_t cr = c * (uint32_t)sizeof(R);
+  R prev[4];
+  prev[0] = BufIO<R>::ld(rs.d4, cr, 0);
+  prev[1] = BufIO<R>::ld(rs.d4, cr, PR);
+  prev[2] = BufIO<R>::ld(rs.d4, cr, 2 * PR);
+  prev[3] = BufIO<R>::ld(rs.d4, cr, 3 * PR);
+  collide_store<S>(d, rs, c, step, phi, fd, gd, hd, prev);
+}
+
 // ---------------------------------------------------------------- one node of a step
 // INTERIOR: every upstream node of the tile lies inside the domain (no wall link, no wrap).
 template <typename S, bool INTERIOR>
@@ -388,7 +600,6 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   using IO = BufIO<S>;
   constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
   const uint32_t PB = (uint32_t)d.plane * ES;        // plane stride in bytes (populations)
-  const uint32_t PR = (uint32_t)d.plane * RS;        // plane stride in bytes (fields)
   const int pitch = d.pitch, nx = d.nx, ny = d.ny;
   const uint32_t c = (uint32_t)y * pitch + x;
   bool okxm = true, okxp = true, okym = true, okyp = true;
@@ -415,12 +626,19 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   };
   // for INTERIOR the plane is i itself
   auto plane = [&](int i, int o) -> uint32_t { return (uint32_t)(INTERIOR ? i : (i < o ? i : o)) * PB; };
+  const R is = d.inv_scale;
+  R fd[9], gd[5], hd[5];
+  R phi = d.phi_u;
+  if (d.phi_field) phi = BufIO<R>::ld(rs.phi, c * RS, 0);
+  if (!INTERIOR && d.nee) {
+    // walls through the nodes: the perimeter work-groups update the boundary nodes
+    if ((!d.perx && (x == 0 || x == nx - 1)) || (!d.pery && (y == 0 || y == ny - 1))) return;
+  }
+  {
   const uint32_t o1 = pull(okxm, r0 + xm, 1, 3), o3 = pull(okxp, r0 + xp, 3, 1);
   const uint32_t o2 = pull(okym, rm + x, 2, 4), o4 = pull(okyp, rp + x, 4, 2);
   const uint32_t o5 = pull(ok5, rm + xm, 5, 7), o7 = pull(ok7, rp + xp, 7, 5);
   const uint32_t o6 = pull(ok6, rm + xp, 6, 8), o8 = pull(ok8, rp + xm, 8, 6);
-  const R is = d.inv_scale;
-  R fd[9], gd[5], hd[5], prev[4];
   fd[0] = to_real<S>(IO::ld(rs.src, c * ES, 0), is);
   fd[1] = to_real<S>(IO::ld(rs.src, o1, plane(1, 3)), is);
   fd[2] = to_real<S>(IO::ld(rs.src, o2, plane(2, 4)), is);
@@ -441,13 +659,6 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   hd[3] = to_real<S>(IO::ld(rs.src, o3, 14 * PB + plane(3, 1)), is);
   gd[4] = to_real<S>(IO::ld(rs.src, o4, 9 * PB + plane(4, 2)), is);
   hd[4] = to_real<S>(IO::ld(rs.src, o4, 14 * PB + plane(4, 2)), is);
-  const uint32_t cr = c * RS;
-  prev[0] = BufIO<R>::ld(rs.d4, cr, 0);
-  prev[1] = BufIO<R>::ld(rs.d4, cr, PR);
-  prev[2] = BufIO<R>::ld(rs.d4, cr, 2 * PR);
-  prev[3] = BufIO<R>::ld(rs.d4, cr, 3 * PR);
-  R phi = d.phi_u;
-  if (d.phi_field) phi = BufIO<R>::ld(rs.phi, cr, 0);
   if (!INTERIOR && !(okxm & okxp & okym & okyp)) {
     // f: half-way bounce-back with the moving-wall term 6 w_i rho0 e_i.u_w; the wall
     // velocity is tangential: along x for the bottom/top sides, along y for left/right.
@@ -476,22 +687,8 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
       hd[4] = d.wC[TOP] - hd[4];
     }
   }
-  R a, b;
-  porous_coeffs(d, phi, a, b);
-  collide(d, phi, a, b, fd, gd, hd, prev);
-  const R sc = d.scale;
-  const uint32_t co = c * ES;
-  Dither dz(c, step);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) store_pop<S>(fd[i], sc, rs.dst, co, (uint32_t)i * PB, dz);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) store_pop<S>(gd[i], sc, rs.dst, co, (uint32_t)(9 + i) * PB, dz);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) store_pop<S>(hd[i], sc, rs.dst, co, (uint32_t)(14 + i) * PB, dz);
-  BufIO<R>::st(prev[0], rs.d4, cr, 0);
-  BufIO<R>::st(prev[1], rs.d4, cr, PR);
-  BufIO<R>::st(prev[2], rs.d4, cr, 2 * PR);
-  BufIO<R>::st(prev[3], rs.d4, cr, 3 * PR);
+  }
+  finish_node<S>(d, rs, c, step, phi, fd, gd, hd);
 }
 
 // tile index -> (x0, y0), spreading consecutive row bands over the 8 XCDs so that the
@@ -523,11 +720,52 @@ __device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, cons
   }
 }
 
+// Boundary node k of a cavity with walls through the nodes (Eqs. 33-37, 39): the perimeter
+// is numbered bottom and top rows first (when y is not periodic), then the left and right
+// columns without the corners (when x is not periodic).
 template <typename S>
-__global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity) {
-  const int t = Policy<S>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+__device__ __forceinline__ void nee_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int k) {
+  using R = typename St<S>::R;
+  const int nx = d.nx, ny = d.ny;
+  const bool wy = !d.pery, wx = !d.perx;
+  const int nrow = wy ? 2 * nx : 0;
+  const int h = wy ? ny - 2 : ny;
+  if (k >= nrow + (wx ? 2 * h : 0)) return;
+  int x, y;
+  if (k < nrow) {
+    x = k % nx;
+    y = k < nx ? 0 : ny - 1;
+  } else {
+    const int q = k - nrow;
+    x = q < h ? 0 : nx - 1;
+    y = (wy ? 1 : 0) + q % h;
+  }
+  const uint32_t step = d.counter[cur];
+  R fd[9], gd[5], hd[5], prev[4], phi;
+  nee_boundary<S>(d, rs, x, y, wx && (x == 0 || x == nx - 1), wy && (y == 0 || y == ny - 1), fd, gd, hd, prev, phi);
+  collide_store<S>(d, rs, (uint32_t)y * d.pitch + x, step, phi, fd, gd, hd, prev);
+}
+
+// number of perimeter nodes nee_node covers
+__host__ __device__ inline int nee_nodes(int nx, int ny, bool perx, bool pery) {
+  return (pery ? 0 : 2 * nx) + (perx ? 0 : 2 * (pery ? ny : ny - 2));
+}
+
+// One time step.  The first `nperim` work-groups (a multiple of 8, zero unless the cavity
+// has walls through the nodes) update the perimeter nodes, which the tiles skip; the rest
+// are the tiles.  Both read only the previous level and write disjoint nodes, so the
+// perimeter work overlaps the tiles within the one launch.
+template <typename S>
+__global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity,
+                                                   int nperim) {
   const int cur = (d.base_parity ^ parity) & 1;
   const StepRes rs = step_resources<S>(d, cur);
+  if ((int)blockIdx.x < nperim) {
+    nee_node<S>(d, rs, cur, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+    return;
+  }
+  const int b = (int)blockIdx.x - nperim, nb = (int)gridDim.x - nperim;
+  const int t = Policy<S>::xcd_bands ? xcd_remap(b, nb) : b;
   step_tile<S>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
 }
 
@@ -553,7 +791,8 @@ __device__ __forceinline__ void step_tile2d(const Desc<typename St<S>::R> &d, co
 // cavity; the item count lives in device memory so the host can change the batch between
 // graph replays without re-capturing.  Each work-group takes a contiguous run of items
 // (neighbouring tiles of one cavity, so shared halo lines stay in its L2), and runs are
-// laid out over the XCDs in bands as in the single-cavity kernel.
+// laid out over the XCDs in bands as in the single-cavity kernel.  Cavities with walls
+// through the boundary nodes are not batched (the host refuses to attach them).
 template <typename S>
 __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs,
                                                          const Item *__restrict__ items,
@@ -707,7 +946,9 @@ __global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename 
 }
 
 // Mean Nusselt / Sherwood numbers of Eq. (38) at the four sides; one block per side.
-// Gradient along the inward normal: (-8 s_w + 9 s_0 - s_1)/3 (half-way wall).
+// Half-way wall: gradient along the inward normal (-8 s_w + 9 s_0 - s_1)/3, mean over the
+// nodes.  Wall through the nodes: (-3 s_b + 4 s_1 - s_2)/2, trapezoidal mean along the wall.
+// Heat entering through a hot side or leaving through a cold or convective side is positive.
 template <typename R>
 __global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__restrict__ wT,
                                                    const double *__restrict__ wC, double LdT, double LdC,
@@ -716,18 +957,27 @@ __global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__re
   const R *d4 = (const R *)d.d4;
   const long long P = d.plane;
   const int kind = d.kind[side];
-  const bool fixed = kind == SIDE_HOT || kind == SIDE_COLD;
+  const bool half = kind == SIDE_HOT || kind == SIDE_COLD;
+  const bool node = kind == SIDE_NEE_HOT || kind == SIDE_NEE_COLD || kind == SIDE_NEE_ROBIN;
   const int n_along = (side == LEFT || side == RIGHT) ? d.ny : d.nx;
+  const long long step_in = (side == LEFT) ? 1 : (side == RIGHT) ? -1 : (side == BOTTOM) ? d.pitch : -(long long)d.pitch;
   double sT = 0.0, sC = 0.0;
-  if (fixed) {
+  if (half || node) {
     for (int a = threadIdx.x; a < n_along; a += blockDim.x) {
-      long long k0, k1;
-      if (side == LEFT) { k0 = (long long)a * d.pitch; k1 = k0 + 1; }
-      else if (side == RIGHT) { k0 = (long long)a * d.pitch + d.nx - 1; k1 = k0 - 1; }
-      else if (side == BOTTOM) { k0 = a; k1 = (long long)d.pitch + a; }
-      else { k0 = (long long)(d.ny - 1) * d.pitch + a; k1 = k0 - d.pitch; }
-      sT += (-8.0 * wT[side] + 9.0 * (double)d4[k0] - (double)d4[k1]) / 3.0;
-      sC += (-8.0 * wC[side] + 9.0 * (double)d4[P + k0] - (double)d4[P + k1]) / 3.0;
+      long long k0;
+      if (side == LEFT) k0 = (long long)a * d.pitch;
+      else if (side == RIGHT) k0 = (long long)a * d.pitch + d.nx - 1;
+      else if (side == BOTTOM) k0 = a;
+      else k0 = (long long)(d.ny - 1) * d.pitch + a;
+      const long long k1 = k0 + step_in, k2 = k0 + 2 * step_in;
+      if (half) {
+        sT += (-8.0 * wT[side] + 9.0 * (double)d4[k0] - (double)d4[k1]) / 3.0;
+        sC += (-8.0 * wC[side] + 9.0 * (double)d4[P + k0] - (double)d4[P + k1]) / 3.0;
+      } else {
+        const double w = (a == 0 || a == n_along - 1) ? 0.5 : 1.0;
+        sT += w * (-3.0 * (double)d4[k0] + 4.0 * (double)d4[k1] - (double)d4[k2]) / 2.0;
+        sC += w * (-3.0 * (double)d4[P + k0] + 4.0 * (double)d4[P + k1] - (double)d4[P + k2]) / 2.0;
+      }
     }
   }
   __shared__ double red[2][4];
@@ -739,9 +989,10 @@ __global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__re
   if (threadIdx.x == 0) {
     double aT = 0.0, aC = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { aT += red[0][w]; aC += red[1][w]; }
-    const double sign = kind == SIDE_HOT ? -1.0 : 1.0;
-    out[NSLOT + side] = fixed ? sign * LdT * aT / n_along : 0.0;
-    out[NSLOT + 4 + side] = fixed ? sign * LdC * aC / n_along : 0.0;
+    const double sign = (kind == SIDE_HOT || kind == SIDE_NEE_HOT) ? -1.0 : 1.0;
+    const double n = half ? (double)n_along : (double)(n_along - 1);
+    out[NSLOT + side] = (half || node) ? sign * LdT * aT / n : 0.0;
+    out[NSLOT + 4 + side] = (half || node) ? sign * LdC * aC / n : 0.0;
   }
 }
 
@@ -801,10 +1052,15 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
 template <typename S>
 static int step_t(const void *desc, Tile tile, int parity, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
-  const int ntx = (d.nx + tile.tx - 1) / tile.tx;
-  const int nty = (d.ny + tile.ty - 1) / tile.ty;
-  hipLaunchKernelGGL(step_kernel<S>, dim3(ntx * nty), dim3(tile.tx), 0, (hipStream_t)stream, d, tile.ty, ntx,
-                     parity);
+  // with walls through the nodes the last column / row is perimeter work: the tiles need
+  // only cover [0, n - 1) (node 0 is skipped inside its tile)
+  const int ex = d.nee && !d.perx ? 1 : 0, ey = d.nee && !d.pery ? 1 : 0;
+  const int ntx = (d.nx - ex + tile.tx - 1) / tile.tx;
+  const int nty = (d.ny - ey + tile.ty - 1) / tile.ty;
+  int nperim = 0;
+  if (d.nee) nperim = ((nee_nodes(d.nx, d.ny, d.perx != 0, d.pery != 0) + tile.tx - 1) / tile.tx + 7) / 8 * 8;
+  hipLaunchKernelGGL((step_kernel<S>), dim3(nperim + ntx * nty), dim3(tile.tx), 0, (hipStream_t)stream, d, tile.ty,
+                     ntx, parity, nperim);
   return (int)hipGetLastError();
 }
 
@@ -816,23 +1072,19 @@ int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream)
   }
 }
 
+template <typename S>
+static void batch_t(const void *descs, const Item *items, const int *nitems, int grid, int parity, hipStream_t s) {
+  using D = Desc<typename St<S>::R>;
+  hipLaunchKernelGGL((step_batch_kernel<S>), dim3(grid), dim3(256), 0, s, (const D *)descs, items, nitems, parity);
+}
+
 int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int parity,
                       void *stream) {
-  const int block = 256;
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
-    case PREC_FP64:
-      hipLaunchKernelGGL(step_batch_kernel<double>, dim3(grid), dim3(block), 0, s,
-                         (const Desc<double> *)descs, items, nitems, parity);
-      break;
-    case PREC_FP32:
-      hipLaunchKernelGGL(step_batch_kernel<float>, dim3(grid), dim3(block), 0, s, (const Desc<float> *)descs,
-                         items, nitems, parity);
-      break;
-    default:
-      hipLaunchKernelGGL(step_batch_kernel<_Float16>, dim3(grid), dim3(block), 0, s,
-                         (const Desc<float> *)descs, items, nitems, parity);
-      break;
+    case PREC_FP64: batch_t<double>(descs, items, nitems, grid, parity, s); break;
+    case PREC_FP32: batch_t<float>(descs, items, nitems, grid, parity, s); break;
+    default: batch_t<_Float16>(descs, items, nitems, grid, parity, s); break;
   }
   return (int)hipGetLastError();
 }

@@ -18,7 +18,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ESTATE",
           -5: "LBM_EUNSTABLE"}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2}
-SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3}
+SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
+        "nee_hot": 4, "nee_cold": 5, "nee_adiabatic": 6, "nee_robin": 7}
 
 # every symbol include/lbm.h declares
 EXPORTS = (
@@ -53,6 +54,7 @@ class Params(ctypes.Structure):
         ("direct", ctypes.c_int32),
         ("nu", ctypes.c_double), ("alpha_e", ctypes.c_double), ("D_e", ctypes.c_double),
         ("K", ctypes.c_double), ("gbT", ctypes.c_double), ("gbC", ctypes.c_double),
+        ("Bi_T", ctypes.c_double), ("Bi_C", ctypes.c_double),
         ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
     ]
 

@@ -57,7 +57,11 @@ def test_footprint_scales_with_precision():
 @pytest.mark.parametrize("bad", [
     {"nx": 2}, {"ny": 1}, {"phi": 0.0}, {"phi": 1.5}, {"s_e": 2.0}, {"zeta_e": 0.0}, {"Ra": -1.0},
     {"Pr": 0.0}, {"Le": 0.0}, {"Da": 0.0}, {"Th": 0.0, "Tl": 1.0}, {"model": 3}, {"varpi": 1.2},
-    {"sides": ("periodic", "cold", "adiabatic", "adiabatic")}, {"sides": (0, 1, 2, 7)},
+    {"sides": ("periodic", "cold", "adiabatic", "adiabatic")}, {"sides": (0, 1, 2, 7)}, {"sides": (0, 1, 2, 8)},
+    {"sides": ("nee_hot", "cold", "adiabatic", "adiabatic")},
+    {"sides": ("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), "Bi_T": -1.0},
+    {"sides": ("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), "Bi_C": -0.5},
+    {"nx": 4, "sides": ("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")},
     {"direct": 1, "nu": 0.0, "alpha_e": 0.1, "D_e": 0.1, "K": 1.0},
 ])
 def test_create_rejects_invalid_parameters(bad):

@@ -1,8 +1,8 @@
 """The GPU path against the numbers the paper prints (section 4): Table 1 (pure-fluid
-enclosure, the hot-path wall types) and Tables 4-5 (lid-driven porous cavity: moving-lid
-bounce-back, horizontal hot/cold walls, Re-based viscosity).  The paper's walls are
-non-equilibrium extrapolation; with half-way bounce-back the agreement is at the level of
-the discretisation, and the bars below are stated per case."""
+enclosure), Tables 2-3 (convective wall, walls through the nodes), Tables 4-5 (lid-driven
+porous cavity) with half-way walls and again with the paper's own extrapolation walls.  The
+agreement is at the level of the discretisation; the bar of each case is stated with the
+measured difference."""
 import json
 import os
 
@@ -28,13 +28,15 @@ def run_to_steady(s, chunk=5000, tol=1e-9, cap=400000, scalars=False):
     return ob, steps
 
 
-def lid_driven_params(N, phi=0.95, model=0, n=128, Gr=1e2, Re=100.0, Da=0.1, Pr=1.0, Le=1.0, U0=0.1):
+def lid_driven_params(N, phi=0.95, model=0, n=128, Gr=1e2, Re=100.0, Da=0.1, Pr=1.0, Le=1.0, U0=0.1, L=None):
     """Section 4.3: nu = U0 L/Re (1/s_v = 1/2 + J L U0/(c_s^2 Re)), alpha_e = nu/Pr,
-    D_e = alpha_e/Le, K = Da L^2, g beta_T dT = Gr nu^2/L^3, beta_C dC = N beta_T dT."""
-    nu = U0 * n / Re
-    gbT = Gr * nu * nu / n ** 3
+    D_e = alpha_e/Le, K = Da L^2, g beta_T dT = Gr nu^2/L^3, beta_C dC = N beta_T dT.  L is
+    the wall-to-wall distance: n with half-way walls, n - 1 with walls through the nodes."""
+    L = n if L is None else L
+    nu = U0 * L / Re
+    gbT = Gr * nu * nu / L ** 3
     return dict(nx=n, ny=n, sides=("adiabatic", "adiabatic", "cold", "hot"), direct=1, nu=nu, alpha_e=nu / Pr,
-                D_e=nu / Pr / Le, K=Da * n * n, gbT=gbT, gbC=N * gbT, phi=phi, model=model,
+                D_e=nu / Pr / Le, K=Da * L * L, gbT=gbT, gbC=N * gbT, phi=phi, model=model,
                 wall_u=(0.0, 0.0, 0.0, U0), Th=1.0, Tl=0.0, Ch=1.0, Cl=0.0)
 
 
@@ -85,3 +87,99 @@ def test_table5_present_vs_model_a():
         assert res[0][0] == pytest.approx(p_nu, rel=0.03)
         # Model-A's artificial coupling leaves Nu != Sh, by 1e-4 or more as in Table 5
         assert abs(res[1][0] - res[1][1]) > 1e-4 * abs(res[1][0])
+
+
+# ------------------------------------------------ walls through the nodes (section 3.3)
+
+def convective_wall_params(Bi_C, model=0, n=100):
+    """Section 4.2: Ra = 1e4, Da = 1e-2, Bi_T = 1, phi = 0.6, Pr = 1, Le = 1, N = 1 on 100 x 100;
+    hot left wall, convective right wall (Eq. 39), adiabatic top and bottom; the paper's
+    non-equilibrium extrapolation walls (Eqs. 33-37)."""
+    return dict(nx=n, ny=n, sides=("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), Ra=1e4, Da=1e-2,
+                Pr=1.0, Le=1.0, N=1.0, phi=0.6, Bi_T=1.0, Bi_C=Bi_C, model=model)
+
+
+def stream_function_max(F, alpha):
+    """max |psi| / alpha_e with psi(x, y) = integral of u_x dy from the bottom wall."""
+    ux = F["ux"]
+    psi = np.concatenate([np.zeros((1, ux.shape[1])), np.cumsum(0.5 * (ux[1:] + ux[:-1]), axis=0)])
+    return float(np.abs(psi).max() / alpha)
+
+
+@pytest.mark.parametrize("bi_c", [1.0, 200.0])
+def test_table2_convective_wall(bi_c):
+    from paper_1708_07525_amd import Solver
+    ref = json.load(open(os.path.join(GOLDEN, "table2_3_convective_wall.json")))["table2"][f"Bi_C={bi_c:g}"]
+    s = Solver(convective_wall_params(bi_c), T=0.5, C=0.5, precision="fp64")
+    ob, steps = run_to_steady(s, chunk=10000, tol=1e-12, cap=1500000, scalars=True)
+    F = s.fields()
+    got = dict(psi_max=stream_function_max(F, s.derived()["alpha_e"]), theta_min=float(F["T"].min()),
+               Phi_min=float(F["C"].min()))
+    print(f"table 2: Bi_C={bi_c} {got} paper={ref} steps={steps}", flush=True)
+    # measured: |psi|max 0.3% and theta_min 1.4e-3 below the paper's values
+    assert got["psi_max"] == pytest.approx(ref["psi_max"], rel=0.01)
+    assert got["theta_min"] == pytest.approx(ref["theta_min"], abs=2.5e-3)
+    assert got["Phi_min"] == pytest.approx(ref["Phi_min"], abs=2.5e-3)
+
+
+def test_table3_present_vs_model_a():
+    """Bi_C = 1, Le = 1: the present model's T and C fields coincide at steady state, so do
+    Nu and Sh; Model-A's artificial coupling separates them.  Converged to a per-step
+    residual of 1e-13: a residual r leaves the fields about r times the slowest decay time
+    (~1e5 steps here) from the steady state, which at 1e-10 would still show as a 1e-5
+    difference between T and C (their transients differ: sigma = 1, phi = 0.6)."""
+    from paper_1708_07525_amd import Solver
+    ref = json.load(open(os.path.join(GOLDEN, "table2_3_convective_wall.json")))
+    res = {}
+    for model in (0, 1):
+        s = Solver(convective_wall_params(1.0, model=model), T=0.5, C=0.5, precision="fp64")
+        ob, steps = run_to_steady(s, chunk=10000, tol=1e-13, cap=1500000, scalars=True)
+        F = s.fields()
+        res[model] = dict(theta_min=float(F["T"].min()), Phi_min=float(F["C"].min()), Nu=ob["Nu"][0], Sh=ob["Sh"][0],
+                          Nu_right=ob["Nu"][1])
+        print(f"table 3: model={model} {res[model]} steps={steps}", flush=True)
+        s.close()
+    p = ref["table3_present"]
+    assert res[0]["Nu"] == pytest.approx(res[0]["Sh"], rel=1e-7)
+    assert res[0]["theta_min"] == pytest.approx(res[0]["Phi_min"], abs=1e-8)
+    # against the paper: theta_min 1.4e-3 low; Nu at the left wall 1.1% high, while the heat
+    # leaving through the convective wall agrees with the paper's Nu to 0.1% (the node rule
+    # for a zero-flux wall passes a small first-order flux, so the two wall numbers differ)
+    assert res[0]["theta_min"] == pytest.approx(p["theta_min"], abs=2.5e-3)
+    assert res[0]["Nu"] == pytest.approx(p["Nu"], rel=0.015)
+    assert res[0]["Nu_right"] == pytest.approx(p["Nu"], rel=0.003)
+    assert abs(res[1]["Nu"] - res[1]["Sh"]) > 1e-4 * res[1]["Nu"]           # Model-A splits them
+    assert abs(res[1]["theta_min"] - res[1]["Phi_min"]) > 1e-5
+
+
+def test_table4_with_extrapolation_walls():
+    """Table 4 again with the paper's own wall scheme (Eqs. 33-37) on 129 x 129 nodes (wall
+    distance 128): moving top wall held hot, bottom cold, adiabatic sides.  The sweep
+    continues in N from N = 0, each run starting from the previous steady fields.  Measured:
+    1.0-4.8% below the paper (largest at N = 500); refining to 257 and 513 nodes moves the
+    values onto those of the half-way walls (about 1% below the paper), see the grid study in
+    the design notes.  For N <= -1000 the run at this resolution does not settle to a steady
+    state and is left out."""
+    from paper_1708_07525_amd import Solver
+    ref = json.load(open(os.path.join(GOLDEN, "table4_lid_driven.json")))
+    paper = dict(zip(ref["N"], ref["Nu_bottom"]))
+    rows = []
+    for branch in ([0, -100, -250, -500, -750], [100, 500]):
+        init = dict(T=0.5, C=0.5) if branch[0] == 0 else start
+        for N in branch:
+            p = lid_driven_params(N, n=129, L=128)
+            p["sides"] = ("nee_adiabatic", "nee_adiabatic", "nee_cold", "nee_hot")
+            s = Solver(p, precision="fp64", **init)
+            ob, steps = run_to_steady(s, chunk=5000, tol=1e-10, cap=600000, scalars=True)
+            F = s.fields()
+            init = dict(T=F["T"], C=F["C"], ux=F["ux"], uy=F["uy"])
+            if N == 0:
+                start = init
+            rows.append((N, ob["Nu"][2], ob["Sh"][2], steps))
+            print(f"table 4 (extrapolation walls): N={N} Nu={ob['Nu'][2]:.4f} Sh={ob['Sh'][2]:.4f} "
+                  f"paper={paper[N]} steps={steps}", flush=True)
+            s.close()
+    for N, Nu, Sh, steps in rows:
+        assert steps < 600000, N
+        assert Nu == pytest.approx(Sh, rel=1e-6), N
+        assert Nu == pytest.approx(paper[N], rel=0.05), N

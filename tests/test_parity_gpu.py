@@ -290,3 +290,98 @@ def test_autotuned_tile_is_cached_and_changes_nothing(tmp_path, monkeypatch):
     a.step(50)
     b.step(50)
     assert a.get_state() == b.get_state()
+
+
+# ------------------------------------------------------------ walls through the nodes
+
+# FP32 velocity bar of this case: the same cavity with half-way walls (hot, cold, adiabatic)
+# reaches 1.01e-5 of the largest speed after 1000 steps, growing linearly with the step
+# count (FP32 rounding of the stored T and C deviations, carried into u by the buoyancy
+# force); the node rules add about a quarter to that (1.25e-5).  T, C and rho keep the
+# 1e-5 bar.
+CONVECTIVE_FP32_U = 2e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("bi_c", [1.0, 200.0])
+def test_convective_wall_cavity(prec, bi_c):
+    p = workloads.cavity_params(nx=40, ny=36, sides=("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"),
+                                Ra=1e4, Da=1e-2, Le=1.5, N=1.0, phi=0.6, Bi_T=1.0, Bi_C=bi_c)
+    T, C = workloads.noise_fields(40, 36, 21)
+    gpu, ref, e = run_pair(p, 1000, prec, T=T, C=C)
+    print(prec, e, flush=True)
+    ubar = CONVECTIVE_FP32_U if prec == "fp32" else TOL[prec]
+    assert max(e["T"], e["C"], e["rho"]) <= TOL[prec], e
+    assert max(e["ux"], e["uy"]) <= ubar, e
+    a, b = gpu.observables(), ref.observables()
+    np.testing.assert_allclose(a["Nu"], b["Nu"], rtol=10 * TOL[prec], atol=1e-12)
+    np.testing.assert_allclose(a["Sh"], b["Sh"], rtol=10 * TOL[prec], atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_extrapolation_walls_lid_and_porosity_field(prec):
+    rng = np.random.default_rng(4)
+    phi = rng.uniform(0.5, 0.9, size=(30, 34))
+    p = workloads.cavity_params(nx=34, ny=30, sides=("nee_adiabatic", "nee_adiabatic", "nee_cold", "nee_hot"),
+                                Ra=2e4, Da=5e-2, Le=2.0, N=-0.5, phi=0.7, wall_u=(0.0, 0.0, 0.0, 0.04))
+    _, _, e = run_pair(p, 800, prec, phi=phi, T=0.5, C=0.5)
+    assert max(e.values()) <= TOL[prec], e
+
+
+def test_extrapolation_walls_periodic_channel():
+    p = dict(nx=21, ny=8, sides=("nee_hot", "nee_cold", "periodic", "periodic"), direct=1, nu=0.05, alpha_e=0.04,
+             D_e=0.02, K=30.0, gbT=1e-4, gbC=-5e-5, Fphi=0.5, phi=0.6, g_ext=(0.0, 1e-4))
+    _, _, e = run_pair(p, 600, "fp64", T=0.5, C=0.5)
+    assert max(e.values()) <= 1e-10, e
+
+
+def test_gpu_node_wall_pins():
+    eT, eC, Nu, exact = pins.nee_conduction(make_gpu("fp64"))
+    assert eT < 1e-12 and Nu == pytest.approx(exact, abs=1e-11)
+    eT, eC, Nu, exact = pins.nee_conduction(make_gpu("fp64"), robin_bi=1.0)
+    assert eT < 1e-11 and Nu == pytest.approx(exact, abs=1e-10)
+    assert pins.nee_poiseuille(make_gpu("fp64"), 33) < 3e-3
+    assert pins.cavity_symmetry(make_gpu("fp64"), sides=pins.NODE_CAVITY) < 1e-12
+
+
+@pytest.mark.skip(reason="a batched run with node-wall cavities went silent past the run limit and the cause "
+                         "is not found; lbm_batch_attach refuses node-wall contexts until it is")
+def test_batch_with_node_walls_alone_vs_mix():
+    from paper_1708_07525_amd import Batch
+    Solver = _solver()
+    specs = [(workloads.cavity_params(nx=48, ny=40, sides=("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"),
+                                      Bi_T=1.0, Bi_C=5.0), "fp32"),
+             (workloads.cavity_params(nx=64, ny=64), "fp32"),
+             (workloads.cavity_params(nx=50, ny=50, sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")),
+              "fp64")]
+    alone = []
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (9, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        s.step(230)
+        alone.append(s.get_state())
+    b = Batch(4, chunk=100)
+    mix = []
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (9, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        b.attach(s)
+        mix.append(s)
+    b.step(230)
+    for s, ref in zip(mix, alone):
+        assert s.get_state() == ref
+    b.close()
+
+
+def test_batch_refuses_node_walls():
+    from paper_1708_07525_amd import Batch
+    from paper_1708_07525_amd.lbm import LbmError
+    p = workloads.cavity_params(nx=24, ny=24, sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic"))
+    s = _solver()(p, T=0.5, C=0.5, precision="fp32")
+    b = Batch(2, chunk=10)
+    with pytest.raises(LbmError, match="not batched"):
+        b.attach(s)
+    assert len(b) == 0
+    s.step(10)                       # still advances on its own
+    assert np.isfinite(s.fields()["T"]).all()
+    b.close()
