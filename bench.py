@@ -422,6 +422,16 @@ def main():
             var[prec] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
                          "steps": a.variant_steps, "tile": list(vt)}
         out["precisions"] = var
+        # the same cavity with the walls through the boundary nodes (Eqs. 33-37): perimeter
+        # work-groups in the same launch; per-node bytes as above (the perimeter's second
+        # pull is 0.2% of the nodes)
+        nee = dict(case, params=dict(case["params"], sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
+        vms, _, vob, vt = timed_run(nee, a.precision, a.variant_steps, a.warmup)
+        v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
+        ach = BYTES_PER_LU[a.precision] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
+        out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
+                             "steps": a.variant_steps, "tile": list(vt), "precision": a.precision,
+                             "Nu_hot": vob["Nu"][0]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -176,7 +176,8 @@ lbm_status lbm_get_state(struct lbm_ctx *c, void *host, uint64_t bytes);
 lbm_status lbm_set_state(struct lbm_ctx *c, const void *host, uint64_t bytes);
 
 /* Launch shape of the step kernel: tile_x nodes along x (64, 128 or 256) by tile_y rows
- * (1, 2, 4 or 8) per work-group.  Results do not depend on it.  0, 0 restores the default. */
+ * (1, 2, 4 or 8) per work-group.  Results do not depend on it.  0, 0 restores the default:
+ * one row of the width (256, 128 or 64) that leaves the fewest idle lanes at the right edge. */
 lbm_status lbm_set_tile(struct lbm_ctx *c, int32_t tile_x, int32_t tile_y);
 lbm_status lbm_get_tile(const struct lbm_ctx *c, int32_t *tile_x, int32_t *tile_y);
 

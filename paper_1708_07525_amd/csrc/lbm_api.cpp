@@ -183,6 +183,17 @@ bool node_walls(const lbm_params *p) {
   return false;
 }
 
+// Default launch shape: one row of 256, 128 or 64 nodes, whichever wastes the fewest lanes
+// on the ragged right edge of the columns the tiles cover (ties go to the wider tile); with
+// walls through the nodes the last column belongs to the perimeter work.
+Tile default_tile(const lbm_params *p) {
+  const int w = p->nx - (node_walls(p) && p->side[LEFT] != SIDE_PERIODIC ? 1 : 0);
+  int tw = 256;
+  for (int cand : {128, 64})
+    if ((w + cand - 1) / cand * cand < (w + tw - 1) / tw * tw) tw = cand;
+  return Tile{tw, 1};
+}
+
 void map_params(const lbm_params *p, lbm_derived &d) {
   // cavity width: nx for walls half a spacing outside, nx - 1 for walls through the nodes
   d.L = node_walls(p) ? p->nx - 1 : p->nx;
@@ -406,6 +417,7 @@ LBM_API lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   c->stream = (hipStream_t)p->stream;
   c->lay = plan_layout(p->nx, p->ny, p->precision);
   map_params(p, c->dv);
+  c->tile = default_tile(p);
   std::string arch;
   if (hipGetDevice(&c->device) != hipSuccess || !arch_ok(c->device, arch)) {
     delete c;
@@ -721,8 +733,8 @@ static bool tile_supported(int tx, int ty) {
 LBM_API lbm_status lbm_set_tile(lbm_ctx *c, int32_t tx, int32_t ty) {
   if (!c) return LBM_EINVAL;
   if (tx == 0 && ty == 0) {
-    tx = 256;
-    ty = 1;
+    c->tile = default_tile(&c->p);
+    return LBM_OK;
   }
   if (!tile_supported(tx, ty)) return fail(c, LBM_EINVAL, "unsupported tile %dx%d", tx, ty);
   c->tile = Tile{tx, ty};

@@ -482,18 +482,24 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   using R = typename St<S>::R;
   const int dx = bx ? (x == 0 ? 1 : -1) : 0, dy = by ? (y == 0 ? 1 : -1) : 0;
   const int sx = x == 0 ? LEFT : RIGHT, sy = y == 0 ? BOTTOM : TOP;
+  // per-side values are picked with selects from uniform registers: indexing the descriptor
+  // with a per-lane side would turn each into a memory round trip
+  auto pick = [](auto a0, auto a1, auto a2, auto a3, int k) { return k == 0 ? a0 : k == 1 ? a1 : k == 2 ? a2 : a3; };
+  const int k0 = d.kind[0], k1 = d.kind[1], k2 = d.kind[2], k3 = d.kind[3];
   int side, kind;
   R ubx = R(0), uby = R(0);
   if (bx && by) {
-    const int kx = d.kind[sx], ky = d.kind[sy];
+    const int kx = pick(k0, k1, k2, k3, sx), ky = pick(k0, k1, k2, k3, sy);
     auto fixed = [](int k) { return k == SIDE_NEE_HOT || k == SIDE_NEE_COLD; };
     side = fixed(kx) ? sx : fixed(ky) ? sy : kx == SIDE_NEE_ROBIN ? sx : ky == SIDE_NEE_ROBIN ? sy : sx;
-    kind = (fixed(kx) || fixed(ky) || kx == SIDE_NEE_ROBIN || ky == SIDE_NEE_ROBIN) ? d.kind[side] : SIDE_NEE_ADIABATIC;
+    kind = (fixed(kx) || fixed(ky) || kx == SIDE_NEE_ROBIN || ky == SIDE_NEE_ROBIN) ? pick(k0, k1, k2, k3, side)
+                                                                                    : SIDE_NEE_ADIABATIC;
   } else {
     side = bx ? sx : sy;
-    kind = d.kind[side];
-    if (bx) uby = d.uw[side] * R(1.0 / 6.0);
-    else ubx = d.uw[side] * R(1.0 / 6.0);
+    kind = pick(k0, k1, k2, k3, side);
+    const R uw = pick(d.uw[0], d.uw[1], d.uw[2], d.uw[3], side) * R(1.0 / 6.0);
+    if (bx) uby = uw;
+    else ubx = uw;
   }
   const bool fixed_scalars = kind == SIDE_NEE_HOT || kind == SIDE_NEE_COLD;
   // loads: pre-collision state of f and ff (the pulls of this step), porosities, and the
@@ -517,12 +523,13 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   porous_coeffs(d, phif, af, bf);
   R drho, uxf, uyf, dTf, dCf;
   node_fields(d, phif, af, bf, ff, gf, hf, drho, uxf, uyf, dTf, dCf);
-  R dTb = d.Tfix[side], dCb = d.Cfix[side];
+  R dTb = pick(d.Tfix[0], d.Tfix[1], d.Tfix[2], d.Tfix[3], side);
+  R dCb = pick(d.Cfix[0], d.Cfix[1], d.Cfix[2], d.Cfix[3], side);
   if (!fixed_scalars) {
     const R dTff = (g2[0] + g2[1] + g2[2] + g2[3] + g2[4]) * d.inv_sigma;
     const R dCff = (h2[0] + h2[1] + h2[2] + h2[3] + h2[4]) / phiff;
-    const R bT = kind == SIDE_NEE_ROBIN ? d.betaT[side] : R(0);
-    const R bC = kind == SIDE_NEE_ROBIN ? d.betaC[side] : R(0);
+    const R bT = kind == SIDE_NEE_ROBIN ? pick(d.betaT[0], d.betaT[1], d.betaT[2], d.betaT[3], side) : R(0);
+    const R bC = kind == SIDE_NEE_ROBIN ? pick(d.betaC[0], d.betaC[1], d.betaC[2], d.betaC[3], side) : R(0);
     // Eq. (36) is linear, so it holds for the deviations T - T0 as well
     dTb = boundary_scalar(kind, dTb, bT, d.Tinf, dTf, dTff);
     dCb = boundary_scalar(kind, dCb, bC, d.Cinf, dCf, dCff);
