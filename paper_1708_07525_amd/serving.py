@@ -4,7 +4,8 @@ Requests (a problem statement, initial fields and a storage precision) arrive ov
 The loop admits a waiting request as soon as its device footprint fits the memory budget
 and a slot is free, keeps every admitted cavity resident in HBM, advances all of them
 together with one batched launch per precision per time step (replayed from a captured
-HIP graph), checks each cavity's steady-state residual every ``check_every`` steps, and
+HIP graph; a cavity with walls through the boundary nodes is stepped by its own launches
+beside the batch), checks each cavity's steady-state residual every ``check_every`` steps, and
 retires a cavity when it converges or reaches the step cap, freeing its memory for the
 next request.  Requests that arrive while others run join the batch at the next chunk
 boundary, so their work overlaps on the device.
@@ -51,6 +52,15 @@ class Result:
         return self.finished - self.arrival
 
 
+def node_walls(params: dict) -> bool:
+    """True when a side of the problem is a wall through the boundary nodes (side kinds 4-7,
+    by name or number); such cavities are not batched and advance with their own launches."""
+    for k in params.get("sides", ()):
+        if (isinstance(k, str) and k.startswith("nee_")) or (not isinstance(k, str) and int(k) >= 4):
+            return True
+    return False
+
+
 def converged(ob: dict, tol: float, quiet_speed: float) -> bool:
     """Steady state: the K-step velocity residual is below tol; in a fluid at rest (largest
     speed below quiet_speed) the scalar residuals decide instead."""
@@ -78,6 +88,7 @@ class Server:
         self.max_steps = int(max_steps)
         self.keep_fields = keep_fields
         self.batch = self.be.Batch(max_slots, chunk=chunk)
+        self.solo = set()     # ids of resident solvers that the batch does not take
         self.used = 0
         self.active = []      # (solver, request, admitted, bytes, steps)
         self.node_steps = 0
@@ -87,7 +98,10 @@ class Server:
         if len(self.active) >= self.max_slots or self.used + need > self.budget:
             return False
         s = self.be.Solver(req.params, phi=req.phi, T=req.T, C=req.C, precision=req.precision)
-        self.batch.attach(s)
+        if node_walls(req.params):
+            self.solo.add(id(s))           # walls through the nodes: stepped on its own
+        else:
+            self.batch.attach(s)
         self.active.append([s, req, now, need, 0])
         self.used += need
         return True
@@ -96,7 +110,10 @@ class Server:
         s, req, adm, need, steps = self.active.pop(i)
         fields = s.fields() if self.keep_fields else None
         nodes = s.nx * s.ny
-        self.batch.detach(s)
+        if id(s) in self.solo:
+            self.solo.discard(id(s))
+        else:
+            self.batch.detach(s)
         s.close()
         self.used -= need
         return Result(req.id, req.arrival, adm, now, steps, conv, nodes, req.precision, ob, fields)
@@ -122,8 +139,11 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(pending[0][0] - (clock() - t0), 0.01)))
                 continue
-            self.batch.step(self.chunk)
+            if len(self.solo) < len(self.active):
+                self.batch.step(self.chunk)
             for a in self.active:
+                if id(a[0]) in self.solo:
+                    a[0].step(self.chunk)
                 a[4] += self.chunk
                 self.node_steps += a[0].nx * a[0].ny * self.chunk
             batched_steps += self.chunk
@@ -157,7 +177,9 @@ class Server:
 
     def close(self):
         for a in list(self.active):
-            self.batch.detach(a[0])
+            if id(a[0]) not in self.solo:
+                self.batch.detach(a[0])
             a[0].close()
+        self.solo.clear()
         self.active = []
         self.batch.close()

@@ -16,6 +16,7 @@ class FakeSolver:
     def __init__(self, params, phi=None, T=None, C=None, precision="fp32"):
         self.nx, self.ny = params["nx"], params["ny"]
         self.rate = params["rate"]
+        self.node_walls = any(str(k).startswith("nee_") for k in params.get("sides", ()))
         self.u = 1.0
         self.step_n = 0
         self.snap_u = self.u
@@ -26,6 +27,9 @@ class FakeSolver:
     def advance(self, n):
         self.u *= (1 - self.rate) ** n
         self.step_n += n
+
+    def step(self, n):          # a cavity stepped outside the batch
+        self.advance(n)
 
     def observables(self):
         dn = self.step_n - self.snap_step
@@ -51,6 +55,7 @@ class FakeBatch:
 
     def attach(self, s):
         assert len(self.members) < self.cap
+        assert not s.node_walls, "cavities with walls through the nodes are not batched"
         self.members.append(s)
 
     def detach(self, s):
@@ -141,3 +146,25 @@ def test_oversized_request_waits_and_fifo_order():
 def test_chunk_must_divide_check_interval():
     with pytest.raises(ValueError):
         Server(1, chunk=30, check_every=100, backend=FakeBackend)
+
+
+def test_node_wall_cavities_step_beside_the_batch():
+    """A cavity with walls through the boundary nodes is never attached to the batch; it is
+    stepped by itself each chunk and stops at the same step as when served alone."""
+    from paper_1708_07525_amd.serving import node_walls
+    assert node_walls(dict(sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
+    assert node_walls(dict(sides=(4, 5, 6, 6)))
+    assert not node_walls(dict(sides=("hot", "cold", "adiabatic", "periodic")))
+    assert not node_walls(dict(nx=8))
+    reqs = requests(10, seed=3)
+    for r in reqs[::3]:
+        r.params["sides"] = ("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic")
+    srv = Server(10 ** 12, max_slots=16, chunk=10, check_every=50, tol=1e-6, max_steps=3000,
+                 backend=FakeBackend, keep_fields=True)
+    res = {r.id: r for r in srv.run(reqs, clock=iter(range(10 ** 9)).__next__)[0]}
+    assert sorted(res) == list(range(10)) and FakeSolver.live == 0 and not srv.solo
+    for req in reqs:
+        alone = Server(10 ** 12, max_slots=1, chunk=10, check_every=50, tol=1e-6, max_steps=3000,
+                       backend=FakeBackend, keep_fields=True)
+        (r,), _ = alone.run([Request(req.id, 0.0, req.params, req.precision)], clock=iter(range(10 ** 9)).__next__)
+        assert r.steps == res[req.id].steps and r.fields == res[req.id].fields

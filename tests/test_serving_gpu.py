@@ -9,7 +9,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 
-def _requests():
+def _requests(node_walls=False):
     from paper_1708_07525_amd.serving import Request
     rng = np.random.default_rng(12)
     out = []
@@ -18,14 +18,19 @@ def _requests():
         p = workloads.cavity_params(nx=side, ny=side, Ra=float(10 ** rng.uniform(3, 4.5)),
                                     Da=float(10 ** rng.uniform(-3, -1)), phi=float(rng.uniform(0.4, 0.9)),
                                     Le=float(rng.uniform(1, 5)), N=float(rng.uniform(-1, 1)))
+        if node_walls and i % 3 == 1:
+            p.update(sides=("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), Bi_T=1.0, Bi_C=2.0)
         T, C = workloads.noise_fields(side, side, (12, i))
         out.append(Request(i, 0.002 * i, p, "fp32" if i % 2 else "fp16s", None, T, C))
     return out
 
 
-def test_alone_equals_mixed():
+@pytest.mark.parametrize("node_walls", [False, True])
+def test_alone_equals_mixed(node_walls):
+    """With node_walls, two of the six requests have walls through the boundary nodes and are
+    stepped beside the batch."""
     from paper_1708_07525_amd.serving import Request, Server
-    reqs = _requests()
+    reqs = _requests(node_walls)
     mixed = Server(10 ** 10, max_slots=8, chunk=100, check_every=500, tol=1e-6, max_steps=3000, keep_fields=True)
     res_mix, summ = mixed.run(reqs)
     mixed.close()
