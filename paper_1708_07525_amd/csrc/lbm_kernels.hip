@@ -8,6 +8,9 @@
 //   explicit velocity (Eqs. 18-19) and the total force (Eq. 5), collide f in moment
 //   space (Eqs. 10, 13-15), collide g and h in moment space (Eqs. 21-25) with the source
 //   term of Eq. (27) (time derivative: one-step backward difference), and store.
+// Cavities whose walls pass through the boundary nodes (Eqs. 33-37, 39) have their
+// perimeter nodes rebuilt by non-equilibrium extrapolation in work-groups of their own at
+// the front of the same launch (nee_node); the tiles skip those nodes.
 // The 9x9 and 5x5 transforms are written out as sums with the integer / rational
 // coefficients of M, N and their inverses (the inverse of an orthogonal-row matrix is its
 // transpose over the squared row norms 9, 36, 36, 6, 12, 6, 12, 4, 4 and 5, 2, 2, 20, 4).
