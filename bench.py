@@ -74,13 +74,13 @@ def copy_probe(mib):
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_kernels.hip")
+KERNEL_HEADER = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_internal.h")
 
 
 def profiled_traffic(prec, n):
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when there is no
     summary for this workload or the kernel source has changed since the counters were taken."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"step_kernel_{prec}_cavity{n}.md")
     if not os.path.exists(path):
@@ -89,8 +89,18 @@ def profiled_traffic(prec, n):
     if not m:
         return None
     d = json.loads(m.group(1))
-    h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
-    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256_16") == h else None
+    return d["traffic_bytes_per_launch"] if d.get("kernel_code_sha256_16") == kernel_code_hash() else None
+
+
+def kernel_code_hash():
+    """sha256 (first 16 hex digits) of the kernel source and its header with comments and
+    whitespace removed: changes with the code, not with its comments."""
+    import hashlib
+    import re
+    src = "".join(open(f).read() for f in (KERNEL_SOURCE, KERNEL_HEADER))
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
 
 
 def stream_probe(n, reps=200):
