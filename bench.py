@@ -34,7 +34,10 @@ def parse():
                     help="steps for the FP64 and FP16-storage side measurements (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tile", default="", help="tile_x,tile_y (default: library default)")
+    ap.add_argument("--tile", default="auto",
+                    help="tile_x,tile_y, 'default' (library rule) or 'auto' (time every tile shape and cache "
+                         "policy on the workload before the timed region; default)")
+    ap.add_argument("--policy", type=int, default=-1, help="cache policy 0/1/2 with an explicit --tile (-1: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
@@ -123,11 +126,16 @@ def stream_probe(n, reps=200):
     print(json.dumps(out), flush=True)
 
 
-def timed_run(case, prec, steps, warmup, tile=None):
+def timed_run(case, prec, steps, warmup, tile="auto", policy=None):
     import torch
     from paper_1708_07525_amd import Solver
 
-    s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec, tile=tile)
+    s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec,
+               tile=None if tile in ("auto", "default") else tile)
+    if tile == "auto":
+        s.autotune(20)                 # restores the state it started from
+    elif policy is not None:
+        s.set_cache_policy(policy)
     stream = torch.cuda.current_stream()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -140,7 +148,7 @@ def timed_run(case, prec, steps, warmup, tile=None):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     ob = s.observables()
-    tile_used = s.get_tile()
+    tile_used = list(s.get_tile()) + [s.get_cache_policy()]
     s.close()
     return ms, wall, ob, tile_used
 
@@ -393,8 +401,9 @@ def main():
         return
     case = workloads.band_cavity(seed=2, n=a.n)
     nodes = a.n * a.n
-    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
-    ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile)
+    tile = a.tile if a.tile in ("auto", "default") else tuple(int(v) for v in a.tile.split(","))
+    ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile,
+                                        a.policy if a.policy >= 0 else None)
     mlups = nodes * a.steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_LU[a.precision] * nodes / (ms * 1e-3 / a.steps) / 1e9
     out = {
@@ -412,7 +421,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"porous cavity {a.n}x{a.n}, 8 porosity bands U[0.35,0.9] (seed 2), Ra=1e7, "
                                f"Da=1e-4, Pr=0.7, Le=10, N=2, D2Q9+2xD2Q5 MRT, {a.precision} population storage",
-                   "nx": a.n, "ny": a.n, "precision": a.precision, "tile": list(tile_used)},
+                   "nx": a.n, "ny": a.n, "precision": a.precision, "tile": tile_used[:2],
+                   "cache_policy": tile_used[2], "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": profiled_traffic(a.precision, a.n), "traffic_unit": "bytes/launch",
@@ -426,21 +436,21 @@ def main():
         for prec in ("fp64", "fp32", "fp16s"):
             if prec == a.precision:
                 continue
-            vms, _, vob, vt = timed_run(case, prec, a.variant_steps, a.warmup)
+            vms, _, vob, vt = timed_run(case, prec, a.variant_steps, a.warmup, tile)
             v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
             ach = BYTES_PER_LU[prec] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
             var[prec] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                         "steps": a.variant_steps, "tile": list(vt)}
+                         "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2]}
         out["precisions"] = var
         # the same cavity with the walls through the boundary nodes (Eqs. 33-37): perimeter
         # work-groups in the same launch; per-node bytes as above (the perimeter's second
         # pull is 0.2% of the nodes)
         nee = dict(case, params=dict(case["params"], sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
-        vms, _, vob, vt = timed_run(nee, a.precision, a.variant_steps, a.warmup)
+        vms, _, vob, vt = timed_run(nee, a.precision, a.variant_steps, a.warmup, tile)
         v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
         ach = BYTES_PER_LU[a.precision] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
         out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                             "steps": a.variant_steps, "tile": list(vt), "precision": a.precision,
+                             "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "precision": a.precision,
                              "Nu_hot": vob["Nu"][0]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)

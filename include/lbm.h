@@ -185,9 +185,19 @@ lbm_status lbm_get_tile(const struct lbm_ctx *c, int32_t *tile_x, int32_t *tile_
  * kernel launch per step (default 64).  Results do not depend on it. */
 lbm_status lbm_set_graph_chunk(struct lbm_ctx *c, int32_t chunk);
 
-/* Times every supported launch shape on this context for `steps` steps each (HIP events),
- * keeps the fastest, restores the state it started from, and reports the choice and its
- * time per step.  Synchronises. */
+/* Cache policy of the step launch: 0 tuned per storage type on the 2048^2 cavity (FP32:
+ * non-temporal loads, plain stores), 1 streaming (plain loads, non-temporal stores), 2
+ * resident (plain loads and stores: a step's data stays in the 256 MB Infinity Cache), or -1
+ * for the default rule: resident when a step touches at most 400 MB (nx ny times 376, 188 or
+ * 112 B), else streaming for FP32 and tuned for FP64 and FP16.  Results do not depend on it.
+ * lbm_get_cache_policy returns the policy in effect (-1 for a NULL context). */
+lbm_status lbm_set_cache_policy(struct lbm_ctx *c, int32_t policy);
+int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
+
+/* Times every supported launch shape and cache policy on this context for `steps` steps
+ * each (HIP events), keeps the fastest (read the policy with lbm_get_cache_policy),
+ * restores the state it started from, and reports the tile and its time per step.
+ * Synchronises. */
 lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32_t *tile_y,
                         double *ms_per_step);
 
@@ -198,12 +208,17 @@ const char *lbm_last_error(const struct lbm_ctx *c);
 void lbm_destroy(struct lbm_ctx *c);
 
 /* ---- batched stepping of many independent cavities --------------------------------
- * A batch advances every attached context (any size, parameters and precision) with one
- * kernel launch per precision per time step.  The launches use a fixed grid that walks a
- * device-side table of (cavity, tile) work items, and are replayed from a captured HIP
- * graph of `chunk` steps, so that attaching or detaching contexts only rewrites the table
- * between replays.  Per-node arithmetic is the same code as lbm_step: a cavity's state
- * after n batched steps is bitwise the state after lbm_step(c, n). */
+ * A batch advances every attached context (any size, parameters and precision).  The
+ * attached contexts are split, in attach order and per precision, into groups whose step
+ * touches at most 200 MB together (a larger context is a group of its own); each group
+ * advances `chunk` steps with one kernel launch per step before the next group starts, so
+ * its data stays in the 256 MB Infinity Cache from step to step.  Each group's launch takes
+ * the default cache-policy rule of lbm_set_cache_policy for the group's bytes.  The launches
+ * use a fixed grid that walks a device-side table of (cavity, tile) work items and are
+ * replayed from a captured HIP graph; attaching or detaching contexts rewrites the tables
+ * between replays and re-captures only when the groups' number, precisions or policies
+ * change.  Per-node arithmetic is the same code as lbm_step: a cavity's state after n
+ * batched steps is bitwise the state after lbm_step(c, n). */
 typedef struct lbm_batch lbm_batch;
 
 /* max_cavities: capacity of the table; chunk: steps per graph replay (even, >= 2);

@@ -1,10 +1,11 @@
 """Launch-shape autotuning with a persistent cache.
 
-``lbm_autotune`` (C ABI) times every supported tile shape of the step kernel on a context,
-keeps the fastest and restores the state it started from.  This module keys the winner by
-GPU, storage precision, lattice size class and porosity kind, stores it in a JSON file, and
-applies the cached shape to later contexts of the same class without re-timing.  Results never
-depend on the tile shape (the per-node arithmetic is one function), only the speed does.
+``lbm_autotune`` (C ABI) times every supported tile shape and cache policy of the step kernel
+on a context, keeps the fastest and restores the state it started from.  This module keys the
+winner by GPU, storage precision, lattice size class and porosity kind, stores it in a JSON
+file, and applies the cached choice to later contexts of the same class without re-timing.
+Results never depend on the tile shape or the cache policy (the per-node arithmetic is one
+function), only the speed does.
 """
 from __future__ import annotations
 
@@ -51,16 +52,18 @@ def store(entries: dict, path: str | None = None) -> None:
 
 def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: str | None = None,
          force: bool = False):
-    """Apply the cached tile shape for this solver's class, or time all shapes and cache the
-    fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
+    """Apply the cached tile shape and cache policy for this solver's class, or time all of them
+    and cache the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the
+    cache)."""
     k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field)
     entries = load(path)
     if not force and k in entries:
         tx, ty = entries[k]["tile"]
         solver.set_tile(tx, ty)
+        solver.set_cache_policy(int(entries[k].get("policy", -1)))
         return (tx, ty), None
     (tx, ty), ms = solver.autotune(steps)
     entries = load(path)          # re-read: another process may have added entries
-    entries[k] = {"tile": [tx, ty], "ms_per_step": ms, "steps": steps}
+    entries[k] = {"tile": [tx, ty], "policy": solver.get_cache_policy(), "ms_per_step": ms, "steps": steps}
     store(entries, path)
     return (tx, ty), ms

@@ -86,6 +86,7 @@ struct lbm_ctx {
   int64_t step = 0;
   int64_t snap_step = 0;
   Tile tile{256, 1};
+  int cache_policy = -1;     // CP_* or -1: chosen by the bytes a step touches
   lbm_derived dv{};
   bool phi_field = false;
   Desc<double> d64{};
@@ -96,6 +97,7 @@ struct lbm_ctx {
   hipGraphExec_t graph = nullptr;
   int graph_cur = -1;
   Tile graph_tile{0, 0};
+  int graph_cp = -1;
   int graph_chunk = kGraphChunk;   // 0: plain launches only
 
   void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
@@ -192,6 +194,19 @@ Tile default_tile(const lbm_params *p) {
   for (int cand : {128, 64})
     if ((w + cand - 1) / cand * cand < (w + tw - 1) / tw * tw) tw = cand;
   return Tile{tw, 1};
+}
+
+// algorithmic bytes of one node update (19 population loads and stores, 4 + 4 field
+// accesses, 1 porosity load)
+double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC_FP32 ? 188.0 : 112.0); }
+
+// Cache policy when none is set: a step that touches less than 400 MB keeps its data in the
+// 256 MB Infinity Cache between steps for the most part, so plain loads and stores win
+// (CP_RESIDENT); above that FP32 streams with non-temporal stores (CP_STREAM), FP16 and
+// FP64 with their tuned policy (measured on 256^2 to 4096^2 lattices).
+int default_policy(int prec, double nodes) {
+  if (nodes * bytes_per_lu(prec) <= 400e6) return CP_RESIDENT;
+  return prec == PREC_FP32 ? CP_STREAM : CP_TUNED;
 }
 
 void map_params(const lbm_params *p, lbm_derived &d) {
@@ -530,10 +545,15 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   return LBM_OK;
 }
 
+static int ctx_policy(const lbm_ctx *c) {
+  return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny);
+}
+
 static lbm_status step_plain(lbm_ctx *c, int64_t n) {
+  const int cp = ctx_policy(c);
   for (int64_t k = 0; k < n; ++k) {
     set_parity(c, c->cur);
-    int e = launch_step(c->prec, c->desc(), c->tile, 0, c->stream);
+    int e = launch_step(c->prec, c->desc(), c->tile, cp, 0, c->stream);
     if (e) return hip_fail(c, (hipError_t)e, "step kernel launch");
     c->cur ^= 1;
   }
@@ -541,7 +561,9 @@ static lbm_status step_plain(lbm_ctx *c, int64_t n) {
 }
 
 static lbm_status ensure_graph(lbm_ctx *c) {
-  if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty)
+  const int cp = ctx_policy(c);
+  if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty &&
+      c->graph_cp == cp)
     return LBM_OK;
   drop_graph(c);
   hipStream_t cs;
@@ -553,7 +575,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
     int cur = start;
     for (int k = 0; k < c->graph_chunk && e == hipSuccess; ++k) {
       set_parity(c, cur);
-      e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, 0, cs);
+      e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, cp, 0, cs);
       cur ^= 1;
     }
     hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -569,6 +591,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   }
   c->graph_cur = start;
   c->graph_tile = c->tile;
+  c->graph_cp = cp;
   return LBM_OK;
 }
 
@@ -756,6 +779,15 @@ LBM_API lbm_status lbm_get_tile(const lbm_ctx *c, int32_t *tx, int32_t *ty) {
   return LBM_OK;
 }
 
+LBM_API lbm_status lbm_set_cache_policy(lbm_ctx *c, int32_t policy) {
+  if (!c) return LBM_EINVAL;
+  if (policy < -1 || policy >= CP_COUNT) return fail(c, LBM_EINVAL, "unknown cache policy %d", policy);
+  c->cache_policy = policy;
+  return LBM_OK;
+}
+
+LBM_API int32_t lbm_get_cache_policy(const lbm_ctx *c) { return c ? ctx_policy(c) : -1; }
+
 LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int32_t *ty_out, double *ms_out) {
   if (!c || steps < 2) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_set_fields");
@@ -768,6 +800,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   const int cur0 = c->cur;
   const int64_t step0 = c->step;
   const Tile tile0 = c->tile;
+  const int cp0 = c->cache_policy;
   hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -777,24 +810,28 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   if (e == hipSuccess) e = hipEventCreate(&t1);
   double best = 1e300;
   Tile best_tile = tile0;
+  int best_cp = ctx_policy(c);
   const int txs[] = {64, 128, 256};
   const int tys[] = {1, 2, 4, 8};
-  for (int tx : txs)
-    for (int ty : tys) {
-      if (e != hipSuccess) break;
-      c->tile = Tile{tx, ty};
-      if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
-      e = hipEventRecord(t0, c->stream);
-      if (e == hipSuccess && step_plain(c, steps) != LBM_OK) e = hipErrorUnknown;
-      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(t1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-      if (e == hipSuccess && ms / steps < best) {
-        best = ms / steps;
-        best_tile = c->tile;
+  for (int cp = 0; cp < CP_COUNT; ++cp)
+    for (int tx : txs)
+      for (int ty : tys) {
+        if (e != hipSuccess) break;
+        c->tile = Tile{tx, ty};
+        c->cache_policy = cp;
+        if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
+        e = hipEventRecord(t0, c->stream);
+        if (e == hipSuccess && step_plain(c, steps) != LBM_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e == hipSuccess && ms / steps < best) {
+          best = ms / steps;
+          best_tile = c->tile;
+          best_cp = cp;
+        }
       }
-    }
   // restore
   c->cur = cur0;
   set_parity(c, cur0);
@@ -809,9 +846,11 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   c->step = step0;
   if (e != hipSuccess) {
     c->tile = tile0;
+    c->cache_policy = cp0;
     return hip_fail(c, e, "autotune");
   }
   c->tile = best_tile;
+  c->cache_policy = best_cp;
   drop_graph(c);
   if (tx_out) *tx_out = best_tile.tx;
   if (ty_out) *ty_out = best_tile.ty;
@@ -820,35 +859,63 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
 }
 
 // ================================================================== batch
+// A group: cavities of one precision whose step touches at most kGroupBytes together, so
+// that they stay in the Infinity Cache while the group advances a chunk of steps; items
+// [first, first + count) of the precision's item table.
+struct BatchGroup {
+  int prec, cp, first, count;
+};
+
 struct lbm_batch {
   int cap = 0;
   int chunk = 2;
   hipStream_t stream = nullptr;
   std::vector<lbm_ctx *> ctx;
-  // per precision: descriptor table, item table, item count (device)
+  // per precision: descriptor table and item table (device)
   void *descs[3] = {nullptr, nullptr, nullptr};
   Item *items[3] = {nullptr, nullptr, nullptr};
-  int *nitems[3] = {nullptr, nullptr, nullptr};
   int item_cap[3] = {0, 0, 0};
+  std::vector<BatchGroup> groups;
+  int *ranges = nullptr;     // device: {first, count} per group
+  int range_cap = 0;
   int grid = 2048;
   hipGraphExec_t graph = nullptr;
-  unsigned graph_mask = 0;   // precisions present when the graph was captured
+  std::vector<int> graph_key;   // (precision, cache policy) of each group when the graph was captured
   bool dirty = true;
 };
 
 namespace {
 
+constexpr double kGroupBytes = 200e6;   // per-step bytes of one group (Infinity Cache: 256 MB)
+
+void drop_batch_graph(lbm_batch *b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_key.clear();
+}
+
 lbm_status batch_upload(lbm_batch *b) {
+  b->groups.clear();
   for (int prec = 0; prec < 3; ++prec) {
     std::vector<Item> items;
     std::vector<Desc<double>> d64;
     std::vector<Desc<float>> d32;
+    double gnodes = 0;
     for (lbm_ctx *c : b->ctx) {
       if (c->prec != prec) continue;
       const int idx = prec == PREC_FP64 ? (int)d64.size() : (int)d32.size();
       set_parity(c, c->cur);
       if (prec == PREC_FP64) d64.push_back(c->d64);
       else d32.push_back(c->d32);
+      // groups in attach order, closed when the next cavity would take the group past
+      // kGroupBytes (a larger cavity is a group of its own)
+      const double nodes = (double)c->p.nx * c->p.ny;
+      if (b->groups.empty() || b->groups.back().prec != prec ||
+          (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
+        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0});
+        gnodes = 0;
+      }
+      gnodes += nodes;
       // 256-thread tiles of tw x (256/tw) nodes; tw in {256, 128, 64} wastes the fewest
       // lanes on the ragged right edge (ties go to the wider tile)
       int tw = 256;
@@ -858,14 +925,14 @@ lbm_status batch_upload(lbm_batch *b) {
       const int ntx = (c->p.nx + tw - 1) / tw, nty = (c->p.ny + rows - 1) / rows;
       for (int ty = 0; ty < nty; ++ty)
         for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * tw, ty * rows, tw});
+      BatchGroup &g = b->groups.back();
+      g.count = (int)items.size() - g.first;
+      g.cp = default_policy(prec, gnodes);
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {
       // grow the item table; the graph references the old pointer, so drop it
-      if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-      }
+      drop_batch_graph(b);
       if (b->items[prec]) (void)hipFree(b->items[prec]);
       int cap = std::max(n, 2 * b->item_cap[prec]);
       if (hipMalloc((void **)&b->items[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
@@ -879,27 +946,50 @@ lbm_status batch_upload(lbm_batch *b) {
       if (hipMemcpyAsync(b->descs[prec], src, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_EDEVICE;
     }
-    if (hipMemcpyAsync(b->nitems[prec], &n, sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess)
-      return LBM_EDEVICE;
+    // the host copies read host vectors that die at the end of this iteration: wait for them
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
   }
-  // the host copies above read host vectors that die here: wait for them
+  const int ng = (int)b->groups.size();
+  if (ng > b->range_cap) {
+    drop_batch_graph(b);   // the graph references the old ranges
+    if (b->ranges) (void)hipFree(b->ranges);
+    b->ranges = nullptr;
+    const int cap = std::max(ng, 2 * b->range_cap);
+    if (hipMalloc((void **)&b->ranges, (size_t)cap * 2 * sizeof(int)) != hipSuccess) return LBM_ENOMEM;
+    b->range_cap = cap;
+  }
+  std::vector<int> r;
+  for (const BatchGroup &g : b->groups) {
+    r.push_back(g.first);
+    r.push_back(g.count);
+  }
+  if (ng && hipMemcpyAsync(b->ranges, r.data(), r.size() * sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return LBM_EDEVICE;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
   b->dirty = false;
   return LBM_OK;
 }
 
-// bit prec: some cavity of that precision is attached
-unsigned batch_mask(const lbm_batch *b) {
-  unsigned m = 0;
-  for (lbm_ctx *c : b->ctx) m |= 1u << c->prec;
-  return m;
+// (precision, cache policy) of each group: a captured graph stays valid while this is unchanged
+std::vector<int> batch_key(const lbm_batch *b) {
+  std::vector<int> k;
+  for (const BatchGroup &g : b->groups) {
+    k.push_back(g.prec);
+    k.push_back(g.cp);
+  }
+  return k;
 }
 
-hipError_t batch_launch_step(lbm_batch *b, unsigned mask, int parity, hipStream_t s) {
-  for (int prec = 0; prec < 3; ++prec) {
-    if (!(mask & (1u << prec))) continue;
-    int e = launch_step_batch(prec, b->descs[prec], b->items[prec], b->nitems[prec], b->grid, parity, s);
-    if (e) return (hipError_t)e;
+// n steps of every group, group after group (a group's cavities stay cache resident while
+// it advances; groups are independent, so the order changes no result)
+hipError_t batch_launch_steps(lbm_batch *b, int64_t n, hipStream_t s) {
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const BatchGroup &g = b->groups[gi];
+    for (int64_t k = 0; k < n; ++k) {
+      int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], b->ranges + 2 * gi, b->grid,
+                                (int)(k & 1), s);
+      if (e) return (hipError_t)e;
+    }
   }
   return hipSuccess;
 }
@@ -924,8 +1014,7 @@ LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *s
   bool ok = true;
   for (int prec = 0; prec < 3 && ok; ++prec) {
     const size_t dsz = prec == PREC_FP64 ? sizeof(Desc<double>) : sizeof(Desc<float>);
-    ok = hipMalloc(&b->descs[prec], dsz * max_cavities) == hipSuccess &&
-         hipMalloc((void **)&b->nitems[prec], sizeof(int)) == hipSuccess;
+    ok = hipMalloc(&b->descs[prec], dsz * max_cavities) == hipSuccess;
   }
   if (!ok) {
     lbm_batch_destroy(b);
@@ -945,8 +1034,8 @@ LBM_API void lbm_batch_destroy(lbm_batch *b) {
   for (int prec = 0; prec < 3; ++prec) {
     if (b->descs[prec]) (void)hipFree(b->descs[prec]);
     if (b->items[prec]) (void)hipFree(b->items[prec]);
-    if (b->nitems[prec]) (void)hipFree(b->nitems[prec]);
   }
+  if (b->ranges) (void)hipFree(b->ranges);
   delete b;
 }
 
@@ -987,17 +1076,16 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     lbm_status s = batch_upload(b);
     if (s != LBM_OK) return s;
   }
-  const unsigned mask = batch_mask(b);
+  const std::vector<int> key = batch_key(b);
   int64_t left = nsteps;
   if (left >= b->chunk) {
-    if (!b->graph || b->graph_mask != mask) {
-      if (b->graph) (void)hipGraphExecDestroy(b->graph);
-      b->graph = nullptr;
+    if (!b->graph || b->graph_key != key) {
+      drop_batch_graph(b);
       hipStream_t cs;
       if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LBM_EDEVICE;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-      for (int k = 0; k < b->chunk && e == hipSuccess; ++k) e = batch_launch_step(b, mask, k & 1, cs);
+      if (e == hipSuccess) e = batch_launch_steps(b, b->chunk, cs);
       hipError_t e2 = hipStreamEndCapture(cs, &g);
       if (e == hipSuccess) e = e2;
       if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
@@ -1007,15 +1095,14 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
         b->graph = nullptr;
         return LBM_EDEVICE;
       }
-      b->graph_mask = mask;
+      b->graph_key = key;
     }
     while (left >= b->chunk) {
       if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return LBM_EDEVICE;
       left -= b->chunk;   // even chunk: every cavity's current buffer is unchanged
     }
   }
-  for (int64_t k = 0; k < left; ++k)
-    if (batch_launch_step(b, mask, (int)(k & 1), b->stream) != hipSuccess) return LBM_EDEVICE;
+  if (left > 0 && batch_launch_steps(b, left, b->stream) != hipSuccess) return LBM_EDEVICE;
   for (lbm_ctx *c : b->ctx) {
     c->step += nsteps;
     if (left & 1) c->cur ^= 1;

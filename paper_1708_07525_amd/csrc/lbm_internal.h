@@ -21,6 +21,8 @@ enum { SIDE_HOT = 0, SIDE_COLD = 1, SIDE_ADIABATIC = 2, SIDE_PERIODIC = 3,
        SIDE_NEE_HOT = 4, SIDE_NEE_COLD = 5, SIDE_NEE_ADIABATIC = 6, SIDE_NEE_ROBIN = 7 };
 enum { LEFT = 0, RIGHT = 1, BOTTOM = 2, TOP = 3 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
+// cache policies of the step launch (see the kernels for what each sets)
+enum { CP_TUNED = 0, CP_STREAM = 1, CP_RESIDENT = 2, CP_COUNT = 3 };
 constexpr int NPOP = 19;       // 9 + 5 + 5 planes
 constexpr int ND4 = 4;
 
@@ -70,8 +72,10 @@ struct Tile {
 // All take a hipStream_t as void*; return a hipError_t as int.
 int launch_init(int prec, const void *desc, const double *T, const double *C, const double *ux,
                 const double *uy, void *stream);
-int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream);
-int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int parity,
+// cp: cache policy CP_*
+int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream);
+// range: device pointer to {first item, item count} of the group to step
+int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream);
 // observables: partial sums per block, then a final fixed-order reduction.
 // out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)

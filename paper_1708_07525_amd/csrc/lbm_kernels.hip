@@ -233,65 +233,87 @@ __device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &
 // by the hardware range check (loads return 0).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit dwords (gfx9 family)
-// Cache policy of the step kernel's buffer loads and stores (gfx9 buffer instruction bits:
-// 2 = nt, non-temporal) and whether tiles are spread over the XCDs by row band, per storage
-// type.  Chosen by measurement on the 2048^2 cavity (all eight combinations timed twice):
-//   FP32: plain stores, non-temporal loads, XCD bands      5.89 TB/s (5.69 with nt stores)
-//   FP16: non-temporal stores, plain loads, XCD bands      5.77 TB/s
-//   FP64: non-temporal stores and loads, dispatch order    5.56 TB/s (5.24 with XCD bands)
-template <typename S>
-struct Policy;
+// Cache policies of the step (gfx9 buffer instruction bit 2 = nt, non-temporal) for the
+// population and the field accesses, and whether tiles are spread over the XCDs by row band.
+// All three are compiled; the host picks one per launch by the bytes a step touches, the
+// autotuner by timing:
+//   CP_TUNED     per storage type, chosen on the 2048^2 cavity: FP32 nt loads, plain stores,
+//                bands (5.89 TB/s there; 5.69 with nt stores); FP16 nt population stores,
+//                plain population loads, bands (5.77); FP64 nt loads and stores in dispatch
+//                order (5.56; 5.24 with bands).
+//   CP_STREAM    plain loads, nt stores, bands: FP32 at other sizes (2049x2048 29.7 against
+//                23.7 GLUPS with CP_TUNED, 4096^2 28.5 against 26.7).
+//   CP_RESIDENT  plain loads and stores, bands: when a step touches less than the Infinity
+//                Cache (256 MB) holds, the next step's reads are served from it (FP32 1024^2
+//                36.0 against 27.4 GLUPS, FP64 512^2 15.6 against 13.2).
+template <typename S, int CP>
+struct Pol;
 template <>
-struct Policy<float> {
-  static constexpr int load_aux = 2, store_aux = 0;
+struct Pol<float, CP_TUNED> {
+  static constexpr int load_aux = 2, store_aux = 0, fload_aux = 2, fstore_aux = 0;
   static constexpr bool xcd_bands = true;
 };
 template <>
-struct Policy<_Float16> {
-  static constexpr int load_aux = 0, store_aux = 2;
+struct Pol<_Float16, CP_TUNED> {
+  static constexpr int load_aux = 0, store_aux = 2, fload_aux = 2, fstore_aux = 0;
   static constexpr bool xcd_bands = true;
 };
 template <>
-struct Policy<double> {
-  static constexpr int load_aux = 2, store_aux = 2;
+struct Pol<double, CP_TUNED> {
+  static constexpr int load_aux = 2, store_aux = 2, fload_aux = 2, fstore_aux = 2;
   static constexpr bool xcd_bands = false;
+};
+template <typename S>
+struct Pol<S, CP_STREAM> {
+  static constexpr int load_aux = 0, store_aux = 2, fload_aux = 0, fstore_aux = 2;
+  static constexpr bool xcd_bands = true;
+};
+template <typename S>
+struct Pol<S, CP_RESIDENT> {
+  static constexpr int load_aux = 0, store_aux = 0, fload_aux = 0, fstore_aux = 0;
+  static constexpr bool xcd_bands = true;
 };
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <typename S>
+// buffer loads and stores of one element type with the cache bits LA (loads), SA (stores)
+template <typename T, int LA, int SA>
 struct BufIO;
-template <>
-struct BufIO<float> {
+template <int LA, int SA>
+struct BufIO<float, LA, SA> {
   static __device__ __forceinline__ float ld(rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, Policy<float>::load_aux));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LA));
   }
   static __device__ __forceinline__ void st(float x, rsrc_t r, uint32_t v, uint32_t s) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, Policy<float>::store_aux);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, SA);
   }
 };
-template <>
-struct BufIO<double> {
+template <int LA, int SA>
+struct BufIO<double, LA, SA> {
   typedef unsigned int V2 __attribute__((ext_vector_type(2)));
   static __device__ __forceinline__ double ld(rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, Policy<double>::load_aux));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, LA));
   }
   static __device__ __forceinline__ void st(double x, rsrc_t r, uint32_t v, uint32_t s) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, Policy<double>::store_aux);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, SA);
   }
 };
-template <>
-struct BufIO<_Float16> {
+template <int LA, int SA>
+struct BufIO<_Float16, LA, SA> {
   static __device__ __forceinline__ _Float16 ld(rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, Policy<_Float16>::load_aux));
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LA));
   }
   static __device__ __forceinline__ void st(_Float16 x, rsrc_t r, uint32_t v, uint32_t s) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s,
-                                          Policy<_Float16>::store_aux);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, SA);
   }
 };
+// population and field accessors of storage type S under policy CP
+template <typename S, int CP>
+using PopIO = BufIO<S, Pol<S, CP>::load_aux, Pol<S, CP>::store_aux>;
+template <typename S, int CP>
+using FieldIO = BufIO<typename St<S>::R, Pol<S, CP>::fload_aux, Pol<S, CP>::fstore_aux>;
 
 template <typename S>
 __device__ __forceinline__ typename St<S>::R to_real(S v, typename St<S>::R inv_scale);
@@ -371,14 +393,14 @@ __device__ __forceinline__ StepRes step_resources(const Desc<typename St<S>::R> 
   return r;
 }
 
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void store_pop(typename St<S>::R v, typename St<S>::R scale, rsrc_t r, uint32_t voff,
                                           uint32_t soff, Dither &dz) {
   if constexpr (__is_same(S, _Float16)) {
-    BufIO<S>::st(half_stochastic(v * scale, dz.next13()), r, voff, soff);
+    PopIO<S, CP>::st(half_stochastic(v * scale, dz.next13()), r, voff, soff);
   } else {
     (void)dz;
-    BufIO<S>::st(from_real<S>(v, scale), r, voff, soff);
+    PopIO<S, CP>::st(from_real<S>(v, scale), r, voff, soff);
   }
 }
 
@@ -396,11 +418,11 @@ __device__ __forceinline__ void store_pop(typename St<S>::R v, typename St<S>::R
 // occupancy of the plain update.  A corner takes the rule of one of
 // its sides: fixed left/right, fixed bottom/top, convective left/right, convective
 // bottom/top, else zero gradient; its wall velocity is zero.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void pull_inner(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
                                            typename St<S>::R *fd, typename St<S>::R *gd, typename St<S>::R *hd) {
   using R = typename St<S>::R;
-  using IO = BufIO<S>;
+  using IO = PopIO<S, CP>;
   constexpr uint32_t ES = sizeof(S);
   const uint32_t PB = (uint32_t)d.plane * ES;
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -478,7 +500,7 @@ __device__ __forceinline__ R boundary_scalar(int kind, R fixed, R beta, R amb, R
 // The boundary update of node (x, y): bx / by mark a wall through the node in x / y.  Every
 // load it needs (the pulls of f and ff, the porosities, the previous-step fields of the
 // node) is issued before any arithmetic, so a boundary thread waits for memory once.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y, bool bx,
                                           bool by, typename St<S>::R *fd, typename St<S>::R *gd,
                                           typename St<S>::R *hd, typename St<S>::R *prev, typename St<S>::R &phib) {
@@ -511,17 +533,17 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   const uint32_t RS = sizeof(R), PR = (uint32_t)d.plane * RS;
   const uint32_t cb = ((uint32_t)y * d.pitch + x) * RS;
   R ff[9], gf[5], hf[5], f2[9], g2[5], h2[5];
-  pull_inner<S>(d, rs, xf, yf, ff, gf, hf);
-  pull_inner<S>(d, rs, xff, yff, f2, g2, h2);
+  pull_inner<S, CP>(d, rs, xf, yf, ff, gf, hf);
+  pull_inner<S, CP>(d, rs, xff, yff, f2, g2, h2);
   R phif = d.phi_u, phiff = d.phi_u;
   phib = d.phi_u;
   if (d.phi_field) {
-    phib = BufIO<R>::ld(rs.phi, cb, 0);
-    phif = BufIO<R>::ld(rs.phi, ((uint32_t)yf * d.pitch + xf) * RS, 0);
-    phiff = BufIO<R>::ld(rs.phi, ((uint32_t)yff * d.pitch + xff) * RS, 0);
+    phib = FieldIO<S, CP>::ld(rs.phi, cb, 0);
+    phif = FieldIO<S, CP>::ld(rs.phi, ((uint32_t)yf * d.pitch + xf) * RS, 0);
+    phiff = FieldIO<S, CP>::ld(rs.phi, ((uint32_t)yff * d.pitch + xff) * RS, 0);
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) prev[k] = BufIO<R>::ld(rs.d4, cb, (uint32_t)k * PR);
+  for (int k = 0; k < 4; ++k) prev[k] = FieldIO<S, CP>::ld(rs.d4, cb, (uint32_t)k * PR);
   R af, bf;
   porous_coeffs(d, phif, af, bf);
   R drho, uxf, uyf, dTf, dCf;
@@ -557,7 +579,7 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
 
 // Second half of a node update: collision (moment space) with the previous-step fields
 // `prev`, then the stores.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
                                               uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
                                               typename St<S>::R *gd, typename St<S>::R *hd, typename St<S>::R *prev) {
@@ -573,20 +595,21 @@ __device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, 
   const uint32_t co = c * ES;
   Dither dz(c, step);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) store_pop<S>(fd[i], sc, rs.dst, co, (uint32_t)i * PB, dz);
+  for (int i = 0; i < 9; ++i) store_pop<S, CP>(fd[i], sc, rs.dst, co, (uint32_t)i * PB, dz);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) store_pop<S>(gd[i], sc, rs.dst, co, (uint32_t)(9 + i) * PB, dz);
+  for (int i = 0; i < 5; ++i) store_pop<S, CP>(gd[i], sc, rs.dst, co, (uint32_t)(9 + i) * PB, dz);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) store_pop<S>(hd[i], sc, rs.dst, co, (uint32_t)(14 + i) * PB, dz);
-  BufIO<R>::st(prev[0], rs.d4, cr, 0);
-  BufIO<R>::st(prev[1], rs.d4, cr, PR);
-  BufIO<R>::st(prev[2], rs.d4, cr, 2 * PR);
-  BufIO<R>::st(prev[3], rs.d4, cr, 3 * PR);
+  for (int i = 0; i < 5; ++i) store_pop<S, CP>(hd[i], sc, rs.dst, co, (uint32_t)(14 + i) * PB, dz);
+  using FIO = FieldIO<S, CP>;
+  FIO::st(prev[0], rs.d4, cr, 0);
+  FIO::st(prev[1], rs.d4, cr, PR);
+  FIO::st(prev[2], rs.d4, cr, 2 * PR);
+  FIO::st(prev[3], rs.d4, cr, 3 * PR);
 }
 
 // Second half of an interior or half-way-wall node update: previous-step fields, then
 // collide_store.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void finish_node(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
                                             uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
                                             typename St<S>::R *gd, typename St<S>::R *hd) {
@@ -594,20 +617,21 @@ __device__ __forceinline__ void finish_node(const Desc<typename St<S>::R> &d, co
   const uint32_t PR = (uint32_t)d.plane * (uint32_t)sizeof(R);
   const uint32_t cr = c * (uint32_t)sizeof(R);
   R prev[4];
-  prev[0] = BufIO<R>::ld(rs.d4, cr, 0);
-  prev[1] = BufIO<R>::ld(rs.d4, cr, PR);
-  prev[2] = BufIO<R>::ld(rs.d4, cr, 2 * PR);
-  prev[3] = BufIO<R>::ld(rs.d4, cr, 3 * PR);
-  collide_store<S>(d, rs, c, step, phi, fd, gd, hd, prev);
+  using FIO = FieldIO<S, CP>;
+  prev[0] = FIO::ld(rs.d4, cr, 0);
+  prev[1] = FIO::ld(rs.d4, cr, PR);
+  prev[2] = FIO::ld(rs.d4, cr, 2 * PR);
+  prev[3] = FIO::ld(rs.d4, cr, 3 * PR);
+  collide_store<S, CP>(d, rs, c, step, phi, fd, gd, hd, prev);
 }
 
 // ---------------------------------------------------------------- one node of a step
 // INTERIOR: every upstream node of the tile lies inside the domain (no wall link, no wrap).
-template <typename S, bool INTERIOR>
+template <typename S, int CP, bool INTERIOR>
 __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
                                           uint32_t step) {
   using R = typename St<S>::R;
-  using IO = BufIO<S>;
+  using IO = PopIO<S, CP>;
   constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
   const uint32_t PB = (uint32_t)d.plane * ES;        // plane stride in bytes (populations)
   const int pitch = d.pitch, nx = d.nx, ny = d.ny;
@@ -639,7 +663,7 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   const R is = d.inv_scale;
   R fd[9], gd[5], hd[5];
   R phi = d.phi_u;
-  if (d.phi_field) phi = BufIO<R>::ld(rs.phi, c * RS, 0);
+  if (d.phi_field) phi = FieldIO<S, CP>::ld(rs.phi, c * RS, 0);
   if (!INTERIOR && d.nee) {
     // walls through the nodes: the perimeter work-groups update the boundary nodes
     if ((!d.perx && (x == 0 || x == nx - 1)) || (!d.pery && (y == 0 || y == ny - 1))) return;
@@ -698,7 +722,7 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
     }
   }
   }
-  finish_node<S>(d, rs, c, step, phi, fd, gd, hd);
+  finish_node<S, CP>(d, rs, c, step, phi, fd, gd, hd);
 }
 
 // tile index -> (x0, y0), spreading consecutive row bands over the 8 XCDs so that the
@@ -714,7 +738,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // The tile at the origin also advances the step counter: it reads counter[cur] (the count
 // of the state being read) and writes counter[cur ^ 1] (the count of the state being
 // written); no other thread writes either word during the launch.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int x0,
                                           int y0, int tile_y) {
   const int x = x0 + threadIdx.x;
@@ -724,16 +748,16 @@ __device__ __forceinline__ void step_tile(const Desc<typename St<S>::R> &d, cons
   if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 1u;
   if (x >= d.nx) return;
   if (interior) {
-    for (int y = y0; y < y1; ++y) step_node<S, true>(d, rs, x, y, step);
+    for (int y = y0; y < y1; ++y) step_node<S, CP, true>(d, rs, x, y, step);
   } else {
-    for (int y = y0; y < y1; ++y) step_node<S, false>(d, rs, x, y, step);
+    for (int y = y0; y < y1; ++y) step_node<S, CP, false>(d, rs, x, y, step);
   }
 }
 
 // Boundary node k of a cavity with walls through the nodes (Eqs. 33-37, 39): the perimeter
 // is numbered bottom and top rows first (when y is not periodic), then the left and right
 // columns without the corners (when x is not periodic).
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void nee_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int k) {
   using R = typename St<S>::R;
   const int nx = d.nx, ny = d.ny;
@@ -752,8 +776,9 @@ __device__ __forceinline__ void nee_node(const Desc<typename St<S>::R> &d, const
   }
   const uint32_t step = d.counter[cur];
   R fd[9], gd[5], hd[5], prev[4], phi;
-  nee_boundary<S>(d, rs, x, y, wx && (x == 0 || x == nx - 1), wy && (y == 0 || y == ny - 1), fd, gd, hd, prev, phi);
-  collide_store<S>(d, rs, (uint32_t)y * d.pitch + x, step, phi, fd, gd, hd, prev);
+  nee_boundary<S, CP>(d, rs, x, y, wx && (x == 0 || x == nx - 1), wy && (y == 0 || y == ny - 1), fd, gd, hd, prev,
+                      phi);
+  collide_store<S, CP>(d, rs, (uint32_t)y * d.pitch + x, step, phi, fd, gd, hd, prev);
 }
 
 // number of perimeter nodes nee_node covers
@@ -765,23 +790,23 @@ __host__ __device__ inline int nee_nodes(int nx, int ny, bool perx, bool pery) {
 // has walls through the nodes) update the perimeter nodes, which the tiles skip; the rest
 // are the tiles.  Both read only the previous level and write disjoint nodes, so the
 // perimeter work overlaps the tiles within the one launch.
-template <typename S>
+template <typename S, int CP>
 __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity,
                                                    int nperim) {
   const int cur = (d.base_parity ^ parity) & 1;
   const StepRes rs = step_resources<S>(d, cur);
   if ((int)blockIdx.x < nperim) {
-    nee_node<S>(d, rs, cur, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+    nee_node<S, CP>(d, rs, cur, (int)(blockIdx.x * blockDim.x + threadIdx.x));
     return;
   }
   const int b = (int)blockIdx.x - nperim, nb = (int)gridDim.x - nperim;
-  const int t = Policy<S>::xcd_bands ? xcd_remap(b, nb) : b;
-  step_tile<S>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
+  const int t = Pol<S, CP>::xcd_bands ? xcd_remap(b, nb) : b;
+  step_tile<S, CP>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
 // keep every lane busy.
-template <typename S>
+template <typename S, int CP>
 __device__ __forceinline__ void step_tile2d(const Desc<typename St<S>::R> &d, const StepRes &rs, int cur, int x0,
                                             int y0, int tw) {
   const int rows = (int)blockDim.x / tw;
@@ -792,31 +817,32 @@ __device__ __forceinline__ void step_tile2d(const Desc<typename St<S>::R> &d, co
   if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 1u;
   if (x >= d.nx || y >= d.ny) return;
   if (interior)
-    step_node<S, true>(d, rs, x, y, step);
+    step_node<S, CP, true>(d, rs, x, y, step);
   else
-    step_node<S, false>(d, rs, x, y, step);
+    step_node<S, CP, false>(d, rs, x, y, step);
 }
 
-// Batched step: a fixed grid walks the (cavity, tile) work items of every attached
-// cavity; the item count lives in device memory so the host can change the batch between
-// graph replays without re-capturing.  Each work-group takes a contiguous run of items
+// Batched step: a fixed grid walks the (cavity, tile) work items of one group of attached
+// cavities, items [range[0], range[0] + range[1]) of the table; the range lives in device
+// memory so the host can change the batch between graph replays without re-capturing.
+// Each work-group takes a contiguous run of items
 // (neighbouring tiles of one cavity, so shared halo lines stay in its L2), and runs are
 // laid out over the XCDs in bands as in the single-cavity kernel.  Cavities with walls
 // through the boundary nodes are not batched (the host refuses to attach them).
-template <typename S>
+template <typename S, int CP>
 __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs,
                                                          const Item *__restrict__ items,
-                                                         const int *__restrict__ nitems, int parity) {
-  const int n = *nitems;
+                                                         const int *__restrict__ range, int parity) {
+  const int first = range[0], n = range[1];
   const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-  const int b = Policy<S>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int end = min(n, (b + 1) * per);
   for (int it = b * per; it < end; ++it) {
-    const Item item = items[it];
+    const Item item = items[first + it];
     const Desc<typename St<S>::R> d = descs[item.cavity];
     const int cur = (d.base_parity ^ parity) & 1;
     const StepRes rs = step_resources<S>(d, cur);
-    step_tile2d<S>(d, rs, cur, item.x0, item.y0, item.tw);
+    step_tile2d<S, CP>(d, rs, cur, item.x0, item.y0, item.tw);
   }
 }
 
@@ -1059,9 +1085,8 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
   }
 }
 
-template <typename S>
-static int step_t(const void *desc, Tile tile, int parity, void *stream) {
-  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+template <typename S, int CP>
+static void step_cp(const Desc<typename St<S>::R> &d, Tile tile, int parity, hipStream_t stream) {
   // with walls through the nodes the last column / row is perimeter work: the tiles need
   // only cover [0, n - 1) (node 0 is skipped inside its tile)
   const int ex = d.nee && !d.perx ? 1 : 0, ey = d.nee && !d.pery ? 1 : 0;
@@ -1069,32 +1094,55 @@ static int step_t(const void *desc, Tile tile, int parity, void *stream) {
   const int nty = (d.ny - ey + tile.ty - 1) / tile.ty;
   int nperim = 0;
   if (d.nee) nperim = ((nee_nodes(d.nx, d.ny, d.perx != 0, d.pery != 0) + tile.tx - 1) / tile.tx + 7) / 8 * 8;
-  hipLaunchKernelGGL((step_kernel<S>), dim3(nperim + ntx * nty), dim3(tile.tx), 0, (hipStream_t)stream, d, tile.ty,
-                     ntx, parity, nperim);
+  hipLaunchKernelGGL((step_kernel<S, CP>), dim3(nperim + ntx * nty), dim3(tile.tx), 0, stream, d, tile.ty, ntx,
+                     parity, nperim);
+}
+
+template <typename S>
+static int step_t(const void *desc, Tile tile, int cp, int parity, void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  hipStream_t s = (hipStream_t)stream;
+  switch (cp) {
+    case CP_STREAM: step_cp<S, CP_STREAM>(d, tile, parity, s); break;
+    case CP_RESIDENT: step_cp<S, CP_RESIDENT>(d, tile, parity, s); break;
+    default: step_cp<S, CP_TUNED>(d, tile, parity, s); break;
+  }
   return (int)hipGetLastError();
 }
 
-int launch_step(int prec, const void *desc, Tile tile, int parity, void *stream) {
+int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream) {
   switch (prec) {
-    case PREC_FP64: return step_t<double>(desc, tile, parity, stream);
-    case PREC_FP32: return step_t<float>(desc, tile, parity, stream);
-    default: return step_t<_Float16>(desc, tile, parity, stream);
+    case PREC_FP64: return step_t<double>(desc, tile, cp, parity, stream);
+    case PREC_FP32: return step_t<float>(desc, tile, cp, parity, stream);
+    default: return step_t<_Float16>(desc, tile, cp, parity, stream);
   }
 }
 
 template <typename S>
-static void batch_t(const void *descs, const Item *items, const int *nitems, int grid, int parity, hipStream_t s) {
+static void batch_t(int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
+                    hipStream_t s) {
   using D = Desc<typename St<S>::R>;
-  hipLaunchKernelGGL((step_batch_kernel<S>), dim3(grid), dim3(256), 0, s, (const D *)descs, items, nitems, parity);
+  const D *dd = (const D *)descs;
+  switch (cp) {
+    case CP_STREAM:
+      hipLaunchKernelGGL((step_batch_kernel<S, CP_STREAM>), dim3(grid), dim3(256), 0, s, dd, items, range, parity);
+      break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step_batch_kernel<S, CP_RESIDENT>), dim3(grid), dim3(256), 0, s, dd, items, range, parity);
+      break;
+    default:
+      hipLaunchKernelGGL((step_batch_kernel<S, CP_TUNED>), dim3(grid), dim3(256), 0, s, dd, items, range, parity);
+      break;
+  }
 }
 
-int launch_step_batch(int prec, const void *descs, const Item *items, const int *nitems, int grid, int parity,
+int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream) {
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
-    case PREC_FP64: batch_t<double>(descs, items, nitems, grid, parity, s); break;
-    case PREC_FP32: batch_t<float>(descs, items, nitems, grid, parity, s); break;
-    default: batch_t<_Float16>(descs, items, nitems, grid, parity, s); break;
+    case PREC_FP64: batch_t<double>(cp, descs, items, range, grid, parity, s); break;
+    case PREC_FP32: batch_t<float>(cp, descs, items, range, grid, parity, s); break;
+    default: batch_t<_Float16>(cp, descs, items, range, grid, parity, s); break;
   }
   return (int)hipGetLastError();
 }

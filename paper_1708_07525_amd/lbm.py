@@ -25,7 +25,8 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
     "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-    "lbm_set_tile", "lbm_get_tile", "lbm_set_graph_chunk", "lbm_autotune", "lbm_last_error", "lbm_destroy",
+    "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_graph_chunk",
+    "lbm_autotune", "lbm_last_error", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_size",
     "lbm_batch_destroy",
 )
@@ -99,6 +100,10 @@ def lib():
         L.lbm_state_bytes.restype = ctypes.c_uint64
         L.lbm_get_state.argtypes = [_VP, _VP, ctypes.c_uint64]
         L.lbm_set_state.argtypes = [_VP, _VP, ctypes.c_uint64]
+        L.lbm_set_cache_policy.argtypes = [_VP, ctypes.c_int32]
+        L.lbm_set_cache_policy.restype = ctypes.c_int
+        L.lbm_get_cache_policy.argtypes = [_VP]
+        L.lbm_get_cache_policy.restype = ctypes.c_int32
         L.lbm_set_tile.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
         L.lbm_set_graph_chunk.argtypes = [_VP, ctypes.c_int32]
         L.lbm_get_tile.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -244,6 +249,13 @@ class Solver:
 
     def set_graph_chunk(self, chunk: int):
         _check(lib().lbm_set_graph_chunk(self._h, int(chunk)), self._h, "lbm_set_graph_chunk")
+
+    def set_cache_policy(self, policy: int):
+        """0 tuned, 1 streaming, 2 resident, -1 the default rule (see include/lbm.h)."""
+        _check(lib().lbm_set_cache_policy(self._h, int(policy)), self._h, "lbm_set_cache_policy")
+
+    def get_cache_policy(self) -> int:
+        return int(lib().lbm_get_cache_policy(self._h))
 
     def get_tile(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

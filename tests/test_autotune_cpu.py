@@ -6,15 +6,23 @@ class FakeSolver:
     def __init__(self, nx, ny, precision="fp32"):
         self.nx, self.ny, self.precision = nx, ny, precision
         self.tile = (256, 1)
+        self.policy = -1
         self.timed = 0
 
     def autotune(self, steps):
         self.timed += 1
         self.tile = (128, 2)
+        self.policy = 1
         return self.tile, 0.25
 
     def set_tile(self, tx, ty):
         self.tile = (tx, ty)
+
+    def set_cache_policy(self, p):
+        self.policy = p
+
+    def get_cache_policy(self):
+        return self.policy
 
 
 def test_size_class_and_key():
@@ -30,7 +38,7 @@ def test_tune_times_once_per_class(tmp_path):
     b = FakeSolver(120, 90)          # same class: 128x128, uniform, fp32
     b.tile = (64, 8)
     assert autotune.tune(b, "gpu", False, path=path) == ((128, 2), None)
-    assert b.timed == 0 and b.tile == (128, 2)
+    assert b.timed == 0 and b.tile == (128, 2) and b.policy == 1
     c = FakeSolver(120, 90, "fp16s")  # other precision: timed again
     autotune.tune(c, "gpu", False, path=path)
     assert c.timed == 1

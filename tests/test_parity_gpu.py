@@ -210,6 +210,21 @@ def test_results_do_not_depend_on_tile():
         assert _state_after(50, tile) == ref, tile
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "fp64"])
+def test_results_do_not_depend_on_cache_policy(prec):
+    Solver = _solver()
+    case = workloads.grf_cavity(seed=1, n=96)
+    states = []
+    for policy in (-1, 0, 1, 2):
+        s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec)
+        s.set_cache_policy(policy)
+        assert s.get_cache_policy() == (2 if policy == -1 else policy)   # 96^2 fits the cache: resident
+        s.step(130)
+        states.append(s.get_state())
+        s.close()
+    assert all(st == states[0] for st in states[1:])
+
+
 def test_graph_replays_match_plain_launches():
     """lbm_step uses a captured graph for chunks of 64 steps; replays interleaved with other
     work must give the same state as one launch per step."""
