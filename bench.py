@@ -80,10 +80,11 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_kernels.
 KERNEL_HEADER = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_internal.h")
 
 
-def profiled_traffic(prec, n):
+def profiled_traffic(prec, n, launch):
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when there is no
-    summary for this workload or the kernel source has changed since the counters were taken."""
+    summary for this workload, the kernel code has changed since the counters were taken, or
+    the launch shape and cache policy [tile_x, tile_y, policy] differ from the profiled ones."""
     import re
     path = os.path.join(ROOT, "profiles", f"step_kernel_{prec}_cavity{n}.md")
     if not os.path.exists(path):
@@ -92,7 +93,8 @@ def profiled_traffic(prec, n):
     if not m:
         return None
     d = json.loads(m.group(1))
-    return d["traffic_bytes_per_launch"] if d.get("kernel_code_sha256_16") == kernel_code_hash() else None
+    same = d.get("kernel_code_sha256_16") == kernel_code_hash() and d.get("launch") == list(launch)
+    return d["traffic_bytes_per_launch"] if same else None
 
 
 def kernel_code_hash():
@@ -425,7 +427,7 @@ def main():
                    "cache_policy": tile_used[2], "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": profiled_traffic(a.precision, a.n), "traffic_unit": "bytes/launch",
+                     "traffic": profiled_traffic(a.precision, a.n, tile_used), "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes,
                      "bytes_per_lu": BYTES_PER_LU[a.precision], "kernel": "step_kernel"},
         "wall_s": round(wall, 3),
