@@ -157,20 +157,49 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None):
 
 def cpu_baseline(case, target_s):
     """The FP64 oracle (plain, untuned) on the host cores, on a bounded sample of the same
-    workload: the full lattice for as many steps as fit in about target_s seconds."""
+    workload: the full lattice for as many steps as fit in about target_s seconds.  Also the
+    same lattice on one thread (a few steps), and the 64^2 and 512^2 cavities of the parity
+    tests, all threads."""
     import oracle
-    o = oracle.Oracle(case["params"], phi=case["phi"], T=case["T"], C=case["C"])
-    nodes = case["params"]["nx"] * case["params"]["ny"]
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    steps = max(1, int(target_s / max(one, 1e-6)) - 1)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=round(nodes * steps / dt / 1e6, 3), unit="MLUPS", cores=oracle.threads(), kind="oracle",
-                sample=f"{case['params']['nx']}x{case['params']['ny']} lattice, {steps} steps (after 1 untimed), "
-                       f"FP64 oracle, OpenMP over rows")
+    import workloads
+
+    def rate(params, phi, T, C, seconds, threads=None):
+        o = oracle.Oracle(params, phi=phi, T=T, C=C)
+        nodes = params["nx"] * params["ny"]
+        if threads:
+            oracle.set_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            o.step(1)
+            one = time.perf_counter() - t0
+            steps = max(1, int(seconds / max(one, 1e-6)) - 1)
+            t0 = time.perf_counter()
+            o.step(steps)
+            dt = time.perf_counter() - t0
+        finally:
+            if threads:
+                oracle.set_threads(0)
+        return nodes * steps / dt / 1e6, steps
+
+    p = case["params"]
+    ml, steps = rate(p, case["phi"], case["T"], case["C"], target_s)
+    out = dict(value=round(ml, 3), unit="MLUPS", cores=oracle.threads(), kind="oracle",
+               sample=f"{p['nx']}x{p['ny']} lattice, {steps} steps (after 1 untimed), FP64 oracle, OpenMP over rows")
+    ml1, steps1 = rate(p, case["phi"], case["T"], case["C"], max(2.0, target_s / 4), threads=1)
+    out["one_thread"] = {"MLUPS": round(ml1, 3), "steps": steps1}
+    small = workloads.small_cavity(seed=0)
+    grf = workloads.grf_cavity(seed=1, n=512)
+    out["other_samples"] = {
+        name: {"MLUPS": round(m, 3), "steps": k}
+        for name, (m, k) in (("cavity64", rate(small["params"], None, small["T"], small["C"], 1.0)),
+                             ("grf512", rate(grf["params"], grf["phi"], grf["T"], grf["C"], 2.0)))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            out["cpu_model"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    out["nproc"] = os.cpu_count()
+    return out
 
 
 def sweep(a):

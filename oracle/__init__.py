@@ -102,6 +102,8 @@ def lib():
         L.orc_source5.argtypes = [ctypes.c_double] * 3 + [_D]
         L.orc_velocity.argtypes = [ctypes.c_double] * 4 + [_D, _D]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -260,3 +262,8 @@ def velocity(vx, vy, l0, l1):
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the following steps: n > 0 sets n, 0 restores the default."""
+    lib().orc_set_threads(int(n))

@@ -871,3 +871,13 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+/* threads for the following steps: n > 0 sets n, 0 restores the count at the first call */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  static int initial = -1;
+  if (initial < 0) initial = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : initial);
+#else
+  (void)n;
+#endif
+}

@@ -106,6 +106,7 @@ void orc_source5(double ax, double ay, double varpi, double *S5tilde);
 /* one velocity solve, Eqs. (18)-(19): v in, u out */
 void orc_velocity(double vx, double vy, double l0, double l1, double *ux, double *uy);
 int orc_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

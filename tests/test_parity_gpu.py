@@ -350,6 +350,18 @@ def test_extrapolation_walls_periodic_channel():
     assert max(e.values()) <= 1e-10, e
 
 
+def test_fp16s_error_bound_node_walls():
+    """The binary16 random-walk bound of test_fp16s_error_bound, on the convective-wall cavity
+    with walls through the nodes (the boundary rebuild adds roundings of the same size)."""
+    p = workloads.cavity_params(nx=40, ny=36, sides=("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"),
+                                Ra=1e4, Da=1e-2, Le=1.5, N=1.0, phi=0.6, Bi_T=1.0, Bi_C=2.0)
+    T, C = workloads.noise_fields(40, 36, 21)
+    _, _, e = run_pair(p, 1000, "fp16s", T=T, C=C)
+    print("fp16s node walls", e, flush=True)
+    bound = np.sqrt(1000) * 2.0 ** -11 / 2
+    assert e["T"] < bound and e["C"] < bound and e["ux"] < 2e-2 and e["uy"] < 2e-2 and e["rho"] < 1e-3, e
+
+
 def test_gpu_node_wall_pins():
     eT, eC, Nu, exact = pins.nee_conduction(make_gpu("fp64"))
     assert eT < 1e-12 and Nu == pytest.approx(exact, abs=1e-11)
