@@ -393,12 +393,13 @@ def serve(a):
         import oracle
         by_id = {r.id: r for r in reqs}
         errs = []
-        for res in [r for r in results if r.nodes == 128 * 128][:a.oracle_samples]:
+        picks = sorted((r for r in results if r.nodes <= 256 * 256), key=lambda r: (r.nodes, r.id))
+        for res in picks[:a.oracle_samples]:
             req = by_id[res.id]
             o = oracle.Oracle(req.params, T=req.T, C=req.C)
             o.step(res.steps)
             ob = o.observables()
-            errs.append({"id": res.id, "precision": res.precision, "steps": res.steps,
+            errs.append({"id": res.id, "precision": res.precision, "steps": res.steps, "nodes": res.nodes,
                          "Nu_rel_err": abs(res.obs["Nu"][0] - ob["Nu"][0]) / abs(ob["Nu"][0]),
                          "Sh_rel_err": abs(res.obs["Sh"][0] - ob["Sh"][0]) / abs(ob["Sh"][0])})
         out["oracle_samples"] = errs
