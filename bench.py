@@ -38,6 +38,7 @@ def parse():
                     help="tile_x,tile_y, 'default' (library rule) or 'auto' (time every tile shape and cache "
                          "policy on the workload before the timed region; default)")
     ap.add_argument("--policy", type=int, default=-1, help="cache policy 0/1/2 with an explicit --tile (-1: rule)")
+    ap.add_argument("--spl", type=int, default=0, help="steps per launch 1/2 with an explicit --tile (0: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
@@ -128,7 +129,7 @@ def stream_probe(n, reps=200):
     print(json.dumps(out), flush=True)
 
 
-def timed_run(case, prec, steps, warmup, tile="auto", policy=None):
+def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0):
     import torch
     from paper_1708_07525_amd import Solver
 
@@ -136,8 +137,10 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None):
                tile=None if tile in ("auto", "default") else tile)
     if tile == "auto":
         s.autotune(20)                 # restores the state it started from
-    elif policy is not None:
-        s.set_cache_policy(policy)
+    else:
+        if policy is not None:
+            s.set_cache_policy(policy)
+        s.set_steps_per_launch(spl)
     stream = torch.cuda.current_stream()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -150,7 +153,7 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     ob = s.observables()
-    tile_used = list(s.get_tile()) + [s.get_cache_policy()]
+    tile_used = list(s.get_tile()) + [s.get_cache_policy(), s.get_steps_per_launch()]
     s.close()
     return ms, wall, ob, tile_used
 
@@ -435,7 +438,7 @@ def main():
     nodes = a.n * a.n
     tile = a.tile if a.tile in ("auto", "default") else tuple(int(v) for v in a.tile.split(","))
     ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile,
-                                        a.policy if a.policy >= 0 else None)
+                                        a.policy if a.policy >= 0 else None, a.spl)
     mlups = nodes * a.steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_LU[a.precision] * nodes / (ms * 1e-3 / a.steps) / 1e9
     out = {
@@ -454,7 +457,8 @@ def main():
         "config": {"workload": f"porous cavity {a.n}x{a.n}, 8 porosity bands U[0.35,0.9] (seed 2), Ra=1e7, "
                                f"Da=1e-4, Pr=0.7, Le=10, N=2, D2Q9+2xD2Q5 MRT, {a.precision} population storage",
                    "nx": a.n, "ny": a.n, "precision": a.precision, "tile": tile_used[:2],
-                   "cache_policy": tile_used[2], "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
+                   "cache_policy": tile_used[2], "steps_per_launch": tile_used[3],
+                   "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": profiled_traffic(a.precision, a.n, tile_used), "traffic_unit": "bytes/launch",
@@ -472,7 +476,7 @@ def main():
             v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
             ach = BYTES_PER_LU[prec] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
             var[prec] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                         "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2]}
+                         "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3]}
         out["precisions"] = var
         # the same cavity with the walls through the boundary nodes (Eqs. 33-37): perimeter
         # work-groups in the same launch; per-node bytes as above (the perimeter's second
@@ -482,7 +486,7 @@ def main():
         v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
         ach = BYTES_PER_LU[a.precision] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
         out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                             "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "precision": a.precision,
+                             "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "precision": a.precision,
                              "Nu_hot": vob["Nu"][0]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)

@@ -185,19 +185,28 @@ lbm_status lbm_get_tile(const struct lbm_ctx *c, int32_t *tile_x, int32_t *tile_
  * kernel launch per step (default 64).  Results do not depend on it. */
 lbm_status lbm_set_graph_chunk(struct lbm_ctx *c, int32_t chunk);
 
-/* Cache policy of the step launch: 0 tuned per storage type on the 2048^2 cavity (FP32:
- * non-temporal loads, plain stores), 1 streaming (plain loads, non-temporal stores), 2
- * resident (plain loads and stores: a step's data stays in the 256 MB Infinity Cache), or -1
- * for the default rule: resident when a step touches at most 400 MB (nx ny times 376, 188 or
- * 112 B), else streaming for FP32 and tuned for FP64 and FP16.  Results do not depend on it.
- * lbm_get_cache_policy returns the policy in effect (-1 for a NULL context). */
+/* Cache policy of the step launch: 0 tuned per storage type on the 2048^2 cavity with one
+ * step per launch (FP32: non-temporal loads, plain stores), 1 streaming (plain loads,
+ * non-temporal stores), 2 resident (plain loads and stores: a step's data stays in the 256 MB
+ * Infinity Cache), or -1 for the default rule: resident when a step touches at most 400 MB
+ * (nx ny times 376, 188 or 112 B), else streaming, except tuned for one-step FP64 and FP16
+ * launches.  Results do not depend on it.  lbm_get_cache_policy returns the policy in effect
+ * (-1 for a NULL context). */
 lbm_status lbm_set_cache_policy(struct lbm_ctx *c, int32_t policy);
 int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 
-/* Times every supported launch shape and cache policy on this context for `steps` steps
- * each (HIP events), keeps the fastest (read the policy with lbm_get_cache_policy),
- * restores the state it started from, and reports the tile and its time per step.
- * Synchronises. */
+/* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 32 x 16 tiles and a
+ * one-node halo staged in LDS, so the global loads of the second step are saved), or 0 for
+ * the default (2 unless the cavity has walls through the nodes, which always take 1).  An odd
+ * remaining step runs alone.  Results do not depend on it.  lbm_get_steps_per_launch returns
+ * the count in effect (0 for a NULL context). */
+lbm_status lbm_set_steps_per_launch(struct lbm_ctx *c, int32_t n);
+int32_t lbm_get_steps_per_launch(const struct lbm_ctx *c);
+
+/* Times every supported launch shape, cache policy and steps-per-launch count on this
+ * context for `steps` steps each (HIP events), keeps the fastest (read the policy and the
+ * count with lbm_get_cache_policy, lbm_get_steps_per_launch), restores the state it started
+ * from, and reports the tile and its time per step.  Synchronises. */
 lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32_t *tile_y,
                         double *ms_per_step);
 

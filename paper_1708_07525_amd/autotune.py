@@ -1,6 +1,7 @@
 """Launch-shape autotuning with a persistent cache.
 
-``lbm_autotune`` (C ABI) times every supported tile shape and cache policy of the step kernel
+``lbm_autotune`` (C ABI) times every supported tile shape, cache policy and steps-per-launch
+count of the step kernels
 on a context, keeps the fastest and restores the state it started from.  This module keys the
 winner by GPU, storage precision, lattice size class and porosity kind, stores it in a JSON
 file, and applies the cached choice to later contexts of the same class without re-timing.
@@ -61,9 +62,11 @@ def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: 
         tx, ty = entries[k]["tile"]
         solver.set_tile(tx, ty)
         solver.set_cache_policy(int(entries[k].get("policy", -1)))
+        solver.set_steps_per_launch(int(entries[k].get("steps_per_launch", 0)))
         return (tx, ty), None
     (tx, ty), ms = solver.autotune(steps)
     entries = load(path)          # re-read: another process may have added entries
-    entries[k] = {"tile": [tx, ty], "policy": solver.get_cache_policy(), "ms_per_step": ms, "steps": steps}
+    entries[k] = {"tile": [tx, ty], "policy": solver.get_cache_policy(),
+                  "steps_per_launch": solver.get_steps_per_launch(), "ms_per_step": ms, "steps": steps}
     store(entries, path)
     return (tx, ty), ms

@@ -39,7 +39,7 @@ size_t real_size(int prec) { return prec == PREC_FP64 ? 8 : 4; }
 struct Layout {
   int pitch;
   long long plane;
-  size_t off_pop0, off_pop1, off_d4, off_phi, off_snap, off_counter, off_small, total;
+  size_t off_pop0, off_pop1, off_d4, off_d4b, off_phi, off_snap, off_counter, off_small, total;
   int nblocks_obs;
 };
 
@@ -61,6 +61,7 @@ Layout plan_layout(int nx, int ny, int prec) {
   L.off_pop0 = take((size_t)NPOP * L.plane * es);
   L.off_pop1 = take((size_t)NPOP * L.plane * es);
   L.off_d4 = take((size_t)ND4 * L.plane * rs);
+  L.off_d4b = take((size_t)ND4 * L.plane * rs);   // second field buffer of the two-step launch
   L.off_phi = take((size_t)L.plane * rs);
   L.off_snap = take((size_t)ND4 * L.plane * rs);
   L.off_counter = take(2 * sizeof(unsigned));
@@ -83,6 +84,8 @@ struct lbm_ctx {
   bool ready = false;
   bool in_batch = false;
   int cur = 0;               // buffer holding the post-collision state of the current level
+  int d4cur = 0;             // field buffer (d4 or d4b) holding the fields of the current level
+  int steps_per_launch = 0;  // 1, 2, or 0: chosen by the default rule
   int64_t step = 0;
   int64_t snap_step = 0;
   Tile tile{256, 1};
@@ -98,10 +101,12 @@ struct lbm_ctx {
   int graph_cur = -1;
   Tile graph_tile{0, 0};
   int graph_cp = -1;
+  int graph_d4 = -1, graph_spl = 0;
   int graph_chunk = kGraphChunk;   // 0: plain launches only
 
   void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
-  void *d4() const { return base + lay.off_d4; }
+  void *d4() const { return base + (d4cur ? lay.off_d4b : lay.off_d4); }
+  void *d4other() const { return base + (d4cur ? lay.off_d4 : lay.off_d4b); }
   void *phi() const { return base + lay.off_phi; }
   void *snap() const { return base + lay.off_snap; }
   unsigned *counter() const { return (unsigned *)(base + lay.off_counter); }
@@ -200,13 +205,22 @@ Tile default_tile(const lbm_params *p) {
 // accesses, 1 porosity load)
 double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC_FP32 ? 188.0 : 112.0); }
 
-// Cache policy when none is set: a step that touches less than 400 MB keeps its data in the
+// Steps per launch when none is set (cavities without walls through the nodes): the
+// two-step kernel at every measured size and storage type.
+int default_spl(int prec, double nodes) {
+  (void)prec;
+  (void)nodes;
+  return 2;
+}
+
+// Cache policy when none is set: a step that touches at most 400 MB keeps its data in the
 // 256 MB Infinity Cache between steps for the most part, so plain loads and stores win
-// (CP_RESIDENT); above that FP32 streams with non-temporal stores (CP_STREAM), FP16 and
-// FP64 with their tuned policy (measured on 256^2 to 4096^2 lattices).
-int default_policy(int prec, double nodes) {
+// (CP_RESIDENT); above that the two-step kernel streams with non-temporal stores
+// (CP_STREAM), and so does the one-step FP32 kernel, while the one-step FP16 and FP64
+// kernels keep their tuned policy (measured on 512^2 to 4096^2 lattices).
+int default_policy(int prec, double nodes, int spl) {
   if (nodes * bytes_per_lu(prec) <= 400e6) return CP_RESIDENT;
-  return prec == PREC_FP32 ? CP_STREAM : CP_TUNED;
+  return (spl == 2 || prec == PREC_FP32) ? CP_STREAM : CP_TUNED;
 }
 
 void map_params(const lbm_params *p, lbm_derived &d) {
@@ -283,6 +297,7 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     D.pop0 = c->pop(0);
     D.pop1 = c->pop(1);
     D.d4 = c->d4();
+    D.d4b = c->d4other();
     D.phi = c->phi();
     D.counter = c->counter();
     D.rho0 = (R)p->rho0;
@@ -358,10 +373,19 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
   return LBM_OK;
 }
 
-void set_parity(lbm_ctx *c, int cur) {
+// descriptor state for a launch that starts from population buffer `cur` and field buffer
+// `d4cur` (the context's own, unless a graph capture is simulating later launches)
+void set_parity(lbm_ctx *c, int cur, int d4cur) {
   c->d64.base_parity = cur;
   c->d32.base_parity = cur;
+  void *fa = c->base + (d4cur ? c->lay.off_d4b : c->lay.off_d4);
+  void *fb = c->base + (d4cur ? c->lay.off_d4 : c->lay.off_d4b);
+  c->d64.d4 = fa;
+  c->d32.d4 = fa;
+  c->d64.d4b = fb;
+  c->d32.d4b = fb;
 }
+void set_parity(lbm_ctx *c, int cur) { set_parity(c, cur, c->d4cur); }
 
 bool arch_ok(int dev, std::string &name) {
   hipDeviceProp_t prop;
@@ -493,6 +517,7 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   if (st != LBM_OK) return st;
   drop_graph(c);
   c->cur = 0;
+  c->d4cur = 0;
   set_parity(c, 0);
   // stage the inputs (FP64) on the device
   const size_t plane_bytes = (size_t)c->lay.plane * real_size(c->prec);
@@ -545,25 +570,46 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   return LBM_OK;
 }
 
-static int ctx_policy(const lbm_ctx *c) {
-  return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny);
+// Time steps per launch: 2 (the LDS-staged two-step kernel) unless the cavity has walls
+// through the nodes, or set otherwise.
+static int ctx_spl(const lbm_ctx *c) {
+  if (node_walls(&c->p)) return 1;
+  return c->steps_per_launch > 0 ? c->steps_per_launch : default_spl(c->prec, (double)c->p.nx * c->p.ny);
 }
 
+static int ctx_policy(const lbm_ctx *c) {
+  return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny, ctx_spl(c));
+}
+
+// n steps with plain launches: pairs of steps in the two-step kernel, an odd step alone
 static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   const int cp = ctx_policy(c);
-  for (int64_t k = 0; k < n; ++k) {
+  const int spl = ctx_spl(c);
+  while (n > 0) {
     set_parity(c, c->cur);
-    int e = launch_step(c->prec, c->desc(), c->tile, cp, 0, c->stream);
-    if (e) return hip_fail(c, (hipError_t)e, "step kernel launch");
+    if (spl == 2 && n >= 2) {
+      int e = launch_step2(c->prec, c->desc(), cp, 0, c->stream);
+      if (e) return hip_fail(c, (hipError_t)e, "two-step kernel launch");
+      c->d4cur ^= 1;
+      n -= 2;
+    } else {
+      int e = launch_step(c->prec, c->desc(), c->tile, cp, 0, c->stream);
+      if (e) return hip_fail(c, (hipError_t)e, "step kernel launch");
+      n -= 1;
+    }
     c->cur ^= 1;
   }
   return LBM_OK;
 }
 
+// Graph of graph_chunk steps.  With two steps per launch it holds graph_chunk / 2 launches,
+// each flipping the population and the field buffer; graph_chunk / 2 is taken even (one-step
+// launches otherwise), so a replay ends on the buffers it started from.
 static lbm_status ensure_graph(lbm_ctx *c) {
   const int cp = ctx_policy(c);
+  const int spl = (ctx_spl(c) == 2 && c->graph_chunk % 4 == 0) ? 2 : 1;
   if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty &&
-      c->graph_cp == cp)
+      c->graph_cp == cp && c->graph_d4 == c->d4cur && c->graph_spl == spl)
     return LBM_OK;
   drop_graph(c);
   hipStream_t cs;
@@ -572,10 +618,15 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   const int start = c->cur;
   if (e == hipSuccess) {
-    int cur = start;
-    for (int k = 0; k < c->graph_chunk && e == hipSuccess; ++k) {
-      set_parity(c, cur);
-      e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, cp, 0, cs);
+    int cur = start, d4 = c->d4cur;
+    for (int k = 0; k < c->graph_chunk / spl && e == hipSuccess; ++k) {
+      set_parity(c, cur, d4);
+      if (spl == 2) {
+        e = (hipError_t)launch_step2(c->prec, c->desc(), cp, 0, cs);
+        d4 ^= 1;
+      } else {
+        e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, cp, 0, cs);
+      }
       cur ^= 1;
     }
     hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -592,6 +643,8 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   c->graph_cur = start;
   c->graph_tile = c->tile;
   c->graph_cp = cp;
+  c->graph_d4 = c->d4cur;
+  c->graph_spl = spl;
   return LBM_OK;
 }
 
@@ -735,6 +788,7 @@ LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   const char *src = (const char *)host + sizeof h;
   drop_graph(c);
   c->cur = 0;
+  c->d4cur = 0;
   set_parity(c, 0);
   HIP_CHECK(c, hipMemcpyAsync(c->pop(0), src, h.pop_bytes, hipMemcpyHostToDevice, c->stream), "state copy");
   HIP_CHECK(c, hipMemcpyAsync(c->counter(), &h.counter, sizeof(unsigned), hipMemcpyHostToDevice, c->stream),
@@ -788,6 +842,15 @@ LBM_API lbm_status lbm_set_cache_policy(lbm_ctx *c, int32_t policy) {
 
 LBM_API int32_t lbm_get_cache_policy(const lbm_ctx *c) { return c ? ctx_policy(c) : -1; }
 
+LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0 || n > 2) return fail(c, LBM_EINVAL, "steps per launch must be 0 (default), 1 or 2");
+  c->steps_per_launch = n;
+  return LBM_OK;
+}
+
+LBM_API int32_t lbm_get_steps_per_launch(const lbm_ctx *c) { return c ? ctx_spl(c) : 0; }
+
 LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int32_t *ty_out, double *ms_out) {
   if (!c || steps < 2) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_set_fields");
@@ -800,7 +863,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   const int cur0 = c->cur;
   const int64_t step0 = c->step;
   const Tile tile0 = c->tile;
-  const int cp0 = c->cache_policy;
+  const int cp0 = c->cache_policy, spl0 = c->steps_per_launch, d4cur0 = c->d4cur;
   hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -810,30 +873,41 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   if (e == hipSuccess) e = hipEventCreate(&t1);
   double best = 1e300;
   Tile best_tile = tile0;
-  int best_cp = ctx_policy(c);
+  int best_cp = ctx_policy(c), best_spl = ctx_spl(c);
   const int txs[] = {64, 128, 256};
   const int tys[] = {1, 2, 4, 8};
+  struct Cand {
+    int spl, cp, tx, ty;
+  };
+  std::vector<Cand> cands;
   for (int cp = 0; cp < CP_COUNT; ++cp)
     for (int tx : txs)
-      for (int ty : tys) {
-        if (e != hipSuccess) break;
-        c->tile = Tile{tx, ty};
-        c->cache_policy = cp;
-        if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
-        e = hipEventRecord(t0, c->stream);
-        if (e == hipSuccess && step_plain(c, steps) != LBM_OK) e = hipErrorUnknown;
-        if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e == hipSuccess && ms / steps < best) {
-          best = ms / steps;
-          best_tile = c->tile;
-          best_cp = cp;
-        }
-      }
+      for (int ty : tys) cands.push_back(Cand{1, cp, tx, ty});
+  if (!node_walls(&c->p))   // the two-step kernel has a fixed 32 x 16 tile
+    for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty});
+  const int nsteps = steps + (steps & 1);
+  for (const Cand &k : cands) {
+    if (e != hipSuccess) break;
+    c->tile = Tile{k.tx, k.ty};
+    c->cache_policy = k.cp;
+    c->steps_per_launch = k.spl;
+    if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
+    e = hipEventRecord(t0, c->stream);
+    if (e == hipSuccess && step_plain(c, nsteps) != LBM_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && ms / nsteps < best) {
+      best = ms / nsteps;
+      best_tile = c->tile;
+      best_cp = k.cp;
+      best_spl = k.spl;
+    }
+  }
   // restore
   c->cur = cur0;
+  c->d4cur = d4cur0;
   set_parity(c, cur0);
   if (e == hipSuccess) e = hipMemcpyAsync(c->pop(cur0), save, pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d4(), save + pop_bytes, d4_bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -847,10 +921,12 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   if (e != hipSuccess) {
     c->tile = tile0;
     c->cache_policy = cp0;
+    c->steps_per_launch = spl0;
     return hip_fail(c, e, "autotune");
   }
   c->tile = best_tile;
   c->cache_policy = best_cp;
+  c->steps_per_launch = best_spl;
   drop_graph(c);
   if (tx_out) *tx_out = best_tile.tx;
   if (ty_out) *ty_out = best_tile.ty;
@@ -927,7 +1003,7 @@ lbm_status batch_upload(lbm_batch *b) {
         for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * tw, ty * rows, tw});
       BatchGroup &g = b->groups.back();
       g.count = (int)items.size() - g.first;
-      g.cp = default_policy(prec, gnodes);
+      g.cp = default_policy(prec, gnodes, 1);
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {

@@ -35,7 +35,8 @@ struct Desc {
   int kind[4];
   int base_parity, pad_[3];
   void *pop0, *pop1;       // population buffers (storage type)
-  void *d4;                // previous-step fields (type R)
+  void *d4;                // fields T, C, ux, uy of the current level (type R)
+  void *d4b;               // the other field buffer (written by the two-step kernel)
   void *phi;               // porosity plane (type R), when phi_field
   unsigned *counter;       // step counters [2]: counter[cur] is the step count of the state in
                            // buffer cur (drives the FP16 stochastic rounding)
@@ -74,6 +75,9 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
                 const double *uy, void *stream);
 // cp: cache policy CP_*
 int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream);
+// two time steps per launch (32 x 16 tiles staged in LDS); fields read from d4, written to d4b;
+// cavities without walls through the nodes only
+int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
 // range: device pointer to {first item, item count} of the group to step
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream);

@@ -626,13 +626,49 @@ __device__ __forceinline__ void finish_node(const Desc<typename St<S>::R> &d, co
 }
 
 // ---------------------------------------------------------------- one node of a step
-// INTERIOR: every upstream node of the tile lies inside the domain (no wall link, no wrap).
+// Wall rules of a node whose links leave the domain (ok* false for a link across that side):
+// f: half-way bounce-back with the moving-wall term 6 w_i rho0 e_i.u_w, the wall velocity
+// tangential (along x for the bottom/top sides, along y for left/right; the axis links carry
+// no tangential component); g, h: anti-bounce-back at a side held at fixed T/C, bounce-back
+// at a zero-flux side.  The bounced values have already been pulled from this node.
+template <typename R>
+__device__ __forceinline__ void wall_rules(const Desc<R> &d, bool okxm, bool okxp, bool okym, bool okyp, R *fd,
+                                           R *gd, R *hd) {
+  const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+  const R w5 = R(1.0 / 36.0);
+  const R uB = d.uw[BOTTOM], uT = d.uw[TOP], uL = d.uw[LEFT], uR = d.uw[RIGHT];
+  if (!ok5) fd[5] += w5 * (!okym ? uB : uL);
+  if (!ok6) fd[6] += w5 * (!okym ? -uB : uR);
+  if (!ok7) fd[7] += w5 * (!okyp ? -uT : -uR);
+  if (!ok8) fd[8] += w5 * (!okyp ? uT : -uL);
+  if (!okxm && d.kind[LEFT] != SIDE_ADIABATIC) {
+    gd[1] = d.wT[LEFT] - gd[1];
+    hd[1] = d.wC[LEFT] - hd[1];
+  }
+  if (!okym && d.kind[BOTTOM] != SIDE_ADIABATIC) {
+    gd[2] = d.wT[BOTTOM] - gd[2];
+    hd[2] = d.wC[BOTTOM] - hd[2];
+  }
+  if (!okxp && d.kind[RIGHT] != SIDE_ADIABATIC) {
+    gd[3] = d.wT[RIGHT] - gd[3];
+    hd[3] = d.wC[RIGHT] - hd[3];
+  }
+  if (!okyp && d.kind[TOP] != SIDE_ADIABATIC) {
+    gd[4] = d.wT[TOP] - gd[4];
+    hd[4] = d.wC[TOP] - hd[4];
+  }
+}
+
+// Pull streaming of node (x, y) from the post-collision populations of the previous level
+// in global memory (Eq. 11), with the wall rules.  INTERIOR: every upstream node lies inside
+// the domain (no wall link, no wrap).
 template <typename S, int CP, bool INTERIOR>
-__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
-                                          uint32_t step) {
+__device__ __forceinline__ void gather_global(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
+                                              typename St<S>::R *fd, typename St<S>::R *gd,
+                                              typename St<S>::R *hd) {
   using R = typename St<S>::R;
   using IO = PopIO<S, CP>;
-  constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
+  constexpr uint32_t ES = sizeof(S);
   const uint32_t PB = (uint32_t)d.plane * ES;        // plane stride in bytes (populations)
   const int pitch = d.pitch, nx = d.nx, ny = d.ny;
   const uint32_t c = (uint32_t)y * pitch + x;
@@ -661,14 +697,6 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   // for INTERIOR the plane is i itself
   auto plane = [&](int i, int o) -> uint32_t { return (uint32_t)(INTERIOR ? i : (i < o ? i : o)) * PB; };
   const R is = d.inv_scale;
-  R fd[9], gd[5], hd[5];
-  R phi = d.phi_u;
-  if (d.phi_field) phi = FieldIO<S, CP>::ld(rs.phi, c * RS, 0);
-  if (!INTERIOR && d.nee) {
-    // walls through the nodes: the perimeter work-groups update the boundary nodes
-    if ((!d.perx && (x == 0 || x == nx - 1)) || (!d.pery && (y == 0 || y == ny - 1))) return;
-  }
-  {
   const uint32_t o1 = pull(okxm, r0 + xm, 1, 3), o3 = pull(okxp, r0 + xp, 3, 1);
   const uint32_t o2 = pull(okym, rm + x, 2, 4), o4 = pull(okyp, rp + x, 4, 2);
   const uint32_t o5 = pull(ok5, rm + xm, 5, 7), o7 = pull(ok7, rp + xp, 7, 5);
@@ -693,35 +721,22 @@ __device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, cons
   hd[3] = to_real<S>(IO::ld(rs.src, o3, 14 * PB + plane(3, 1)), is);
   gd[4] = to_real<S>(IO::ld(rs.src, o4, 9 * PB + plane(4, 2)), is);
   hd[4] = to_real<S>(IO::ld(rs.src, o4, 14 * PB + plane(4, 2)), is);
-  if (!INTERIOR && !(okxm & okxp & okym & okyp)) {
-    // f: half-way bounce-back with the moving-wall term 6 w_i rho0 e_i.u_w; the wall
-    // velocity is tangential: along x for the bottom/top sides, along y for left/right.
-    // The axis links carry no tangential component.
-    const R w5 = R(1.0 / 36.0);
-    const R uB = d.uw[BOTTOM], uT = d.uw[TOP], uL = d.uw[LEFT], uR = d.uw[RIGHT];
-    if (!ok5) fd[5] += w5 * (!okym ? uB : uL);
-    if (!ok6) fd[6] += w5 * (!okym ? -uB : uR);
-    if (!ok7) fd[7] += w5 * (!okyp ? -uT : -uR);
-    if (!ok8) fd[8] += w5 * (!okyp ? uT : -uL);
-    // g, h: anti-bounce-back at a side held at fixed T/C, bounce-back at a zero-flux side
-    if (!okxm && d.kind[LEFT] != SIDE_ADIABATIC) {
-      gd[1] = d.wT[LEFT] - gd[1];
-      hd[1] = d.wC[LEFT] - hd[1];
-    }
-    if (!okym && d.kind[BOTTOM] != SIDE_ADIABATIC) {
-      gd[2] = d.wT[BOTTOM] - gd[2];
-      hd[2] = d.wC[BOTTOM] - hd[2];
-    }
-    if (!okxp && d.kind[RIGHT] != SIDE_ADIABATIC) {
-      gd[3] = d.wT[RIGHT] - gd[3];
-      hd[3] = d.wC[RIGHT] - hd[3];
-    }
-    if (!okyp && d.kind[TOP] != SIDE_ADIABATIC) {
-      gd[4] = d.wT[TOP] - gd[4];
-      hd[4] = d.wC[TOP] - hd[4];
-    }
+  if (!INTERIOR && !(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
+}
+
+template <typename S, int CP, bool INTERIOR>
+__device__ __forceinline__ void step_node(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y,
+                                          uint32_t step) {
+  using R = typename St<S>::R;
+  const uint32_t c = (uint32_t)y * d.pitch + x;
+  R fd[9], gd[5], hd[5];
+  R phi = d.phi_u;
+  if (d.phi_field) phi = FieldIO<S, CP>::ld(rs.phi, c * (uint32_t)sizeof(R), 0);
+  if (!INTERIOR && d.nee) {
+    // walls through the nodes: the perimeter work-groups update the boundary nodes
+    if ((!d.perx && (x == 0 || x == d.nx - 1)) || (!d.pery && (y == 0 || y == d.ny - 1))) return;
   }
-  }
+  gather_global<S, CP, INTERIOR>(d, rs, x, y, fd, gd, hd);
   finish_node<S, CP>(d, rs, c, step, phi, fd, gd, hd);
 }
 
@@ -802,6 +817,125 @@ __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, in
   const int b = (int)blockIdx.x - nperim, nb = (int)gridDim.x - nperim;
   const int t = Pol<S, CP>::xcd_bands ? xcd_remap(b, nb) : b;
   step_tile<S, CP>(d, rs, cur, (t % ntx) * blockDim.x, (t / ntx) * tile_y, tile_y);
+}
+
+// ---------------------------------------------------------------- two steps per launch
+// One work-group of TS_W x TS_H threads advances a TS_W x TS_H tile by two time steps.
+// Step one updates the tile and a one-node halo ((TS_W + 2) x (TS_H + 2) nodes, pulled from
+// global memory exactly as in step_node) into LDS; step two pulls from LDS, with the same
+// wall rules, and stores the tile.  Per node and two steps, global memory sees the loads of
+// one step (plus the halo share, (34 x 18)/(32 x 16) = 1.2) and the stores of one step.  The
+// fields of the two levels go to two buffers (d4 read, d4b written), since halo nodes are
+// read by more than one work-group.  The result is bitwise that of two step_kernel launches:
+// step one's values are rounded to the storage type in LDS (FP16: the same stochastic
+// rounding with the same random bits) as a store and a reload would round them.
+constexpr int TS_W = 32, TS_H = 16, TS_RW = TS_W + 2, TS_RH = TS_H + 2, TS_RN = TS_RW * TS_RH;
+constexpr int TS_THREADS = TS_W * TS_H;
+
+template <typename S>
+__device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R scale, Dither &dz) {
+  if constexpr (__is_same(S, _Float16)) {
+    return half_stochastic(v * scale, dz.next13());
+  } else {
+    (void)dz;
+    return from_real<S>(v, scale);
+  }
+}
+
+template <typename S, int CP>
+__global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
+  using R = typename St<S>::R;
+  using FIO = FieldIO<S, CP>;
+  __shared__ S lpop[NPOP][TS_RN];
+  __shared__ R lfld[ND4][TS_RN];
+  constexpr uint32_t RS = sizeof(R);
+  const uint32_t PR = (uint32_t)d.plane * RS;
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const int cur = (d.base_parity ^ parity) & 1;
+  const StepRes rs = step_resources<S>(d, cur);
+  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int x0 = (b % ntx) * TS_W, y0 = (b / ntx) * TS_H;
+  const uint32_t step = d.counter[cur];
+  if (b == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 2u;
+  const R is = d.inv_scale, sc = d.scale;
+  // the halo region and every node it pulls from lie inside the domain
+  const bool interior = x0 >= 2 && x0 + TS_W + 1 <= nx - 1 && y0 >= 2 && y0 + TS_H + 1 <= ny - 1;
+
+  // step one: the tile and its halo, into LDS
+  for (int r = threadIdx.x; r < TS_RN; r += TS_THREADS) {
+    int X = x0 - 1 + r % TS_RW, Y = y0 - 1 + r / TS_RW;
+    if (!interior) {
+      if (X < 0 || X >= nx) {
+        if (!d.perx) continue;             // outside a wall: never read in step two
+        X = X < 0 ? X + nx : X - nx;
+      }
+      if (Y < 0 || Y >= ny) {
+        if (!d.pery) continue;
+        Y = Y < 0 ? Y + ny : Y - ny;
+      }
+    }
+    const uint32_t c = (uint32_t)Y * pitch + X;
+    R fd[9], gd[5], hd[5], prev[4];
+    R phi = d.phi_u;
+    if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+    if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
+    else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(rs.d4, c * RS, (uint32_t)k * PR);
+    R a, bb;
+    porous_coeffs(d, phi, a, bb);
+    collide(d, phi, a, bb, fd, gd, hd, prev);
+    Dither dz(c, step);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lpop[i][r] = to_store<S>(fd[i], sc, dz);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lpop[9 + i][r] = to_store<S>(gd[i], sc, dz);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lpop[14 + i][r] = to_store<S>(hd[i], sc, dz);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lfld[k][r] = prev[k];
+  }
+  __syncthreads();
+
+  // step two: the tile, pulled from LDS
+  const int tx = (int)threadIdx.x % TS_W, ty = (int)threadIdx.x / TS_W;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= nx || y >= ny) return;
+  const int r = (ty + 1) * TS_RW + tx + 1;
+  const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
+  const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
+  const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+  // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
+  auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
+  R fd[9], gd[5], hd[5], prev[4];
+  fd[0] = L(0, 0);
+  fd[1] = okxm ? L(1, -1) : L(3, 0);
+  fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
+  fd[3] = okxp ? L(3, 1) : L(1, 0);
+  fd[4] = okyp ? L(4, TS_RW) : L(2, 0);
+  fd[5] = ok5 ? L(5, -TS_RW - 1) : L(7, 0);
+  fd[6] = ok6 ? L(6, -TS_RW + 1) : L(8, 0);
+  fd[7] = ok7 ? L(7, TS_RW + 1) : L(5, 0);
+  fd[8] = ok8 ? L(8, TS_RW - 1) : L(6, 0);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    R *e = q ? hd : gd;
+    const int p = q ? 14 : 9;
+    e[0] = L(p, 0);
+    e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
+    e[2] = okym ? L(p + 2, -TS_RW) : L(p + 4, 0);
+    e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
+    e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
+  }
+  if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) prev[k] = lfld[k][r];
+  const uint32_t c = (uint32_t)y * pitch + x;
+  R phi = d.phi_u;
+  if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+  StepRes rs2 = rs;
+  rs2.d4 = make_rsrc(d.d4b, ND4 * PR);
+  collide_store<S, CP>(d, rs2, c, step + 1u, phi, fd, gd, hd, prev);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1115,6 +1249,28 @@ int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void 
     case PREC_FP64: return step_t<double>(desc, tile, cp, parity, stream);
     case PREC_FP32: return step_t<float>(desc, tile, cp, parity, stream);
     default: return step_t<_Float16>(desc, tile, cp, parity, stream);
+  }
+}
+
+template <typename S>
+static int step2_t(const void *desc, int cp, int parity, void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  hipStream_t s = (hipStream_t)stream;
+  const int ntx = (d.nx + TS_W - 1) / TS_W, nty = (d.ny + TS_H - 1) / TS_H;
+  const dim3 grid(ntx * nty), block(TS_THREADS);
+  switch (cp) {
+    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_RESIDENT: hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT>), grid, block, 0, s, d, ntx, parity); break;
+    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED>), grid, block, 0, s, d, ntx, parity); break;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_step2(int prec, const void *desc, int cp, int parity, void *stream) {
+  switch (prec) {
+    case PREC_FP64: return step2_t<double>(desc, cp, parity, stream);
+    case PREC_FP32: return step2_t<float>(desc, cp, parity, stream);
+    default: return step2_t<_Float16>(desc, cp, parity, stream);
   }
 }
 

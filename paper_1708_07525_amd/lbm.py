@@ -25,7 +25,8 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
     "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-    "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_graph_chunk",
+    "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_steps_per_launch",
+    "lbm_get_steps_per_launch", "lbm_set_graph_chunk",
     "lbm_autotune", "lbm_last_error", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_size",
     "lbm_batch_destroy",
@@ -104,6 +105,10 @@ def lib():
         L.lbm_set_cache_policy.restype = ctypes.c_int
         L.lbm_get_cache_policy.argtypes = [_VP]
         L.lbm_get_cache_policy.restype = ctypes.c_int32
+        L.lbm_set_steps_per_launch.argtypes = [_VP, ctypes.c_int32]
+        L.lbm_set_steps_per_launch.restype = ctypes.c_int
+        L.lbm_get_steps_per_launch.argtypes = [_VP]
+        L.lbm_get_steps_per_launch.restype = ctypes.c_int32
         L.lbm_set_tile.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
         L.lbm_set_graph_chunk.argtypes = [_VP, ctypes.c_int32]
         L.lbm_get_tile.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -256,6 +261,13 @@ class Solver:
 
     def get_cache_policy(self) -> int:
         return int(lib().lbm_get_cache_policy(self._h))
+
+    def set_steps_per_launch(self, n: int):
+        """1, 2 (two-step LDS kernel) or 0 for the default (see include/lbm.h)."""
+        _check(lib().lbm_set_steps_per_launch(self._h, int(n)), self._h, "lbm_set_steps_per_launch")
+
+    def get_steps_per_launch(self) -> int:
+        return int(lib().lbm_get_steps_per_launch(self._h))
 
     def get_tile(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -24,6 +24,12 @@ class FakeSolver:
     def get_cache_policy(self):
         return self.policy
 
+    def set_steps_per_launch(self, n):
+        self.spl = n
+
+    def get_steps_per_launch(self):
+        return getattr(self, "spl", 2)
+
 
 def test_size_class_and_key():
     assert [autotune.size_class(n) for n in (1, 3, 64, 65, 2048)] == [1, 4, 64, 128, 2048]

@@ -225,6 +225,37 @@ def test_results_do_not_depend_on_cache_policy(prec):
     assert all(st == states[0] for st in states[1:])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "fp64"])
+@pytest.mark.parametrize("case", ["grf_ragged", "lid_periodic"])
+def test_two_step_kernel_matches_one_step(prec, case):
+    """The LDS-staged two-step kernel against two launches of the one-step kernel, bitwise,
+    on a ragged porosity-field cavity (tiles cut by every side) and on a channel periodic in
+    x with a moving lid; odd step counts leave one single step; with and without graphs."""
+    Solver = _solver()
+    if case == "grf_ragged":
+        c = workloads.grf_cavity(seed=5, n=100)
+        p, kw = dict(c["params"], ny=70), dict(phi=c["phi"][:70], T=c["T"][:70], C=c["C"][:70])
+    else:
+        p = workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "cold", "hot"),
+                                    wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4)
+        T, C = workloads.noise_fields(70, 37, 8)
+        kw = dict(T=T, C=C)
+    states = {}
+    for spl in (1, 2):
+        for chunk in (0, 64):
+            s = Solver(p, precision=prec, **kw)
+            s.set_steps_per_launch(spl)
+            s.set_graph_chunk(chunk)
+            assert s.get_steps_per_launch() == spl
+            s.step(131)
+            s.step(70)
+            states[(spl, chunk)] = s.get_state()
+            s.close()
+    ref = states[(1, 0)]
+    for k, st in states.items():
+        assert st == ref, k
+
+
 def test_graph_replays_match_plain_launches():
     """lbm_step uses a captured graph for chunks of 64 steps; replays interleaved with other
     work must give the same state as one launch per step."""
