@@ -195,8 +195,9 @@ lbm_status lbm_set_graph_chunk(struct lbm_ctx *c, int32_t chunk);
 lbm_status lbm_set_cache_policy(struct lbm_ctx *c, int32_t policy);
 int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 
-/* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 32 x 16 tiles and a
- * one-node halo staged in LDS, so the global loads of the second step are saved), or 0 for
+/* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 64 x 8 tiles, 32 x 8
+ * for FP64, and a one-node halo staged in LDS, so the global loads of the second step are
+ * saved), or 0 for
  * the default (2 unless the cavity has walls through the nodes, which always take 1).  An odd
  * remaining step runs alone.  Results do not depend on it.  lbm_get_steps_per_launch returns
  * the count in effect (0 for a NULL context). */

@@ -75,7 +75,8 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
                 const double *uy, void *stream);
 // cp: cache policy CP_*
 int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream);
-// two time steps per launch (32 x 16 tiles staged in LDS); fields read from d4, written to d4b;
+// two time steps per launch (tiles with a one-node halo staged in LDS); fields read from d4,
+// written to d4b;
 // cavities without walls through the nodes only
 int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
 // range: device pointer to {first item, item count} of the group to step

@@ -820,17 +820,32 @@ __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, in
 }
 
 // ---------------------------------------------------------------- two steps per launch
-// One work-group of TS_W x TS_H threads advances a TS_W x TS_H tile by two time steps.
-// Step one updates the tile and a one-node halo ((TS_W + 2) x (TS_H + 2) nodes, pulled from
+// One work-group of W x H threads advances a W x H tile by two time steps.
+// Step one updates the tile and a one-node halo ((W + 2) x (H + 2) nodes, pulled from
 // global memory exactly as in step_node) into LDS; step two pulls from LDS, with the same
 // wall rules, and stores the tile.  Per node and two steps, global memory sees the loads of
-// one step (plus the halo share, (34 x 18)/(32 x 16) = 1.2) and the stores of one step.  The
+// one step (plus the halo share, (66 x 10)/(64 x 8) = 1.29) and the stores of one step.  The
 // fields of the two levels go to two buffers (d4 read, d4b written), since halo nodes are
-// read by more than one work-group.  The result is bitwise that of two step_kernel launches:
-// step one's values are rounded to the storage type in LDS (FP16: the same stochastic
-// rounding with the same random bits) as a store and a reload would round them.
-constexpr int TS_W = 32, TS_H = 16, TS_RW = TS_W + 2, TS_RH = TS_H + 2, TS_RN = TS_RW * TS_RH;
-constexpr int TS_THREADS = TS_W * TS_H;
+// read by more than one work-group.  Each thread updates its own tile node in step one (one
+// aligned row segment per wave, its fields kept in registers for step two) and then at most
+// one node of the halo ring, so LDS holds populations only (50 KB in FP32: 3 work-groups
+// per CU).  The result is bitwise that of two step_kernel launches: step one's values are
+// rounded to the storage type in LDS (FP16: the same stochastic rounding with the same
+// random bits) as a store and a reload would round them.
+// Tile of the two-step kernel per storage type (measured, banded 2048^2 and 4096^2 cavities:
+// FP32 64 x 8 51.3 GLUPS against 46.9 for 32 x 16 and 43.7 for 32 x 8; FP16 64 x 8 60.5
+// against 52.2; FP64 32 x 8 24.9 against 21.8 for 32 x 16 and 22.9 for 64 x 8, its LDS being
+// twice as large)
+template <typename S>
+struct TwoStep {
+  static constexpr int W = 64, H = 8;
+  static constexpr int RW = W + 2, RH = H + 2, RN = RW * RH, THREADS = W * H;
+};
+template <>
+struct TwoStep<double> {
+  static constexpr int W = 32, H = 8;
+  static constexpr int RW = W + 2, RH = H + 2, RN = RW * RH, THREADS = W * H;
+};
 
 template <typename S>
 __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R scale, Dither &dz) {
@@ -843,11 +858,12 @@ __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R sca
 }
 
 template <typename S, int CP>
-__global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
+__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
   using R = typename St<S>::R;
   using FIO = FieldIO<S, CP>;
+  constexpr int TS_W = TwoStep<S>::W, TS_H = TwoStep<S>::H, TS_RW = TwoStep<S>::RW, TS_RH = TwoStep<S>::RH;
+  constexpr int TS_RN = TwoStep<S>::RN, TS_THREADS = TwoStep<S>::THREADS;
   __shared__ S lpop[NPOP][TS_RN];
-  __shared__ R lfld[ND4][TS_RN];
   constexpr uint32_t RS = sizeof(R);
   const uint32_t PR = (uint32_t)d.plane * RS;
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -861,21 +877,23 @@ __global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::
   // the halo region and every node it pulls from lie inside the domain
   const bool interior = x0 >= 2 && x0 + TS_W + 1 <= nx - 1 && y0 >= 2 && y0 + TS_H + 1 <= ny - 1;
 
-  // step one: the tile and its halo, into LDS
-  for (int r = threadIdx.x; r < TS_RN; r += TS_THREADS) {
-    int X = x0 - 1 + r % TS_RW, Y = y0 - 1 + r / TS_RW;
+  // step one at region node (lx, ly) (global x0 - 1 + lx, y0 - 1 + ly): populations into
+  // LDS, the fields into `prev`
+  auto step_one = [&](int lx, int ly, R *prev) {
+    int X = x0 - 1 + lx, Y = y0 - 1 + ly;
     if (!interior) {
       if (X < 0 || X >= nx) {
-        if (!d.perx) continue;             // outside a wall: never read in step two
+        if (!d.perx) return;               // outside a wall: never read in step two
         X = X < 0 ? X + nx : X - nx;
       }
       if (Y < 0 || Y >= ny) {
-        if (!d.pery) continue;
+        if (!d.pery) return;
         Y = Y < 0 ? Y + ny : Y - ny;
       }
     }
     const uint32_t c = (uint32_t)Y * pitch + X;
-    R fd[9], gd[5], hd[5], prev[4];
+    const int r = ly * TS_RW + lx;
+    R fd[9], gd[5], hd[5];
     R phi = d.phi_u;
     if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
     if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
@@ -892,13 +910,32 @@ __global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::
     for (int i = 0; i < 5; ++i) lpop[9 + i][r] = to_store<S>(gd[i], sc, dz);
 #pragma unroll
     for (int i = 0; i < 5; ++i) lpop[14 + i][r] = to_store<S>(hd[i], sc, dz);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lfld[k][r] = prev[k];
+  };
+  // each thread: its own node of the tile (fields kept in registers for step two), then at
+  // most one node of the halo ring: rows ly = 0 and TS_RH - 1, then columns lx = 0 and
+  // TS_RW - 1 without the corners
+  const int tx = (int)threadIdx.x % TS_W, ty = (int)threadIdx.x / TS_W;
+  R prev[4];
+  step_one(tx + 1, ty + 1, prev);
+  constexpr int NHALO = 2 * TS_RW + 2 * TS_H;
+  static_assert(NHALO <= TS_THREADS, "one halo node per thread at most");
+  if ((int)threadIdx.x < NHALO) {
+    const int h = threadIdx.x;
+    int hx, hy;
+    if (h < 2 * TS_RW) {
+      hx = h % TS_RW;
+      hy = h < TS_RW ? 0 : TS_RH - 1;
+    } else {
+      const int q = h - 2 * TS_RW;
+      hx = q < TS_H ? 0 : TS_RW - 1;
+      hy = 1 + q % TS_H;
+    }
+    R unused[4];
+    step_one(hx, hy, unused);
   }
   __syncthreads();
 
   // step two: the tile, pulled from LDS
-  const int tx = (int)threadIdx.x % TS_W, ty = (int)threadIdx.x / TS_W;
   const int x = x0 + tx, y = y0 + ty;
   if (x >= nx || y >= ny) return;
   const int r = (ty + 1) * TS_RW + tx + 1;
@@ -907,7 +944,7 @@ __global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::
   const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
   // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
   auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
-  R fd[9], gd[5], hd[5], prev[4];
+  R fd[9], gd[5], hd[5];
   fd[0] = L(0, 0);
   fd[1] = okxm ? L(1, -1) : L(3, 0);
   fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
@@ -928,8 +965,6 @@ __global__ void __launch_bounds__(TS_THREADS) step2_kernel(Desc<typename St<S>::
     e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
   }
   if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) prev[k] = lfld[k][r];
   const uint32_t c = (uint32_t)y * pitch + x;
   R phi = d.phi_u;
   if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
@@ -1256,8 +1291,9 @@ template <typename S>
 static int step2_t(const void *desc, int cp, int parity, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   hipStream_t s = (hipStream_t)stream;
-  const int ntx = (d.nx + TS_W - 1) / TS_W, nty = (d.ny + TS_H - 1) / TS_H;
-  const dim3 grid(ntx * nty), block(TS_THREADS);
+  constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
+  const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
+  const dim3 grid(ntx * nty), block(TwoStep<S>::THREADS);
   switch (cp) {
     case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM>), grid, block, 0, s, d, ntx, parity); break;
     case CP_RESIDENT: hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT>), grid, block, 0, s, d, ntx, parity); break;
