@@ -207,9 +207,10 @@ def cpu_baseline(case, target_s):
 
 def sweep(a):
     """Independent cavities of uneven size and parameters (sides 64..512, aspect 1 or 2,
-    Ra, Da, porosity, Le, N drawn per cavity), FP32: aggregate MLUPS of one batched launch
-    per step replayed from a HIP graph, against the same cavities stepped one by one, with
-    one plain launch per step and with the per-cavity graph replay."""
+    Ra, Da, porosity, Le, N drawn per cavity), FP32: aggregate MLUPS of the batch (cache-sized
+    groups, two steps per batched launch, replayed from a HIP graph), against the same
+    cavities stepped one by one with one plain launch per step (the one-step kernel, no
+    graph), and one by one with the library defaults (two steps per launch, graph replay)."""
     import torch
     import workloads
     from paper_1708_07525_amd import Batch, Solver
@@ -227,9 +228,10 @@ def sweep(a):
     out = {"metric": "aggregate MLUPS, batched sweep vs one-by-one", "unit": "MLUPS", "cavities": len(solvers),
            "nodes": nodes, "steps": steps, "data": "synthetic"}
     # one by one, plain launches
-    for mode, chunk in (("one_by_one_plain", 0), ("one_by_one_graph", 64)):
+    for mode, chunk, spl in (("one_by_one_plain", 0, 1), ("one_by_one_graph", 64, 0)):
         for s in solvers:
             s.set_graph_chunk(chunk)
+            s.set_steps_per_launch(spl)
             s.step(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -307,7 +309,7 @@ def precision_report(a):
 def sweep_until_converged(a, cav):
     """Every cavity of the sweep to steady state (K-step velocity residual below 1e-8, checked
     every 1000 steps) or the step cap: all together through the continuous-batching loop, then
-    the same solves one by one with one plain launch per step."""
+    the same solves one by one with one plain launch per step (one-step kernel, no graph)."""
     import torch
     import workloads
     from paper_1708_07525_amd import Solver
@@ -332,6 +334,7 @@ def sweep_until_converged(a, cav):
     for r in reqs:
         s = Solver(r.params, T=r.T, C=r.C, precision="fp32")
         s.set_graph_chunk(0)
+        s.set_steps_per_launch(1)
         n = 0
         while True:
             s.step(1000)
@@ -462,8 +465,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": profiled_traffic(a.precision, a.n, tile_used), "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes,
-                     "bytes_per_lu": BYTES_PER_LU[a.precision], "kernel": "step_kernel"},
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes * tile_used[3],
+                     "bytes_per_lu": BYTES_PER_LU[a.precision], "steps_per_launch": tile_used[3],
+                     "kernel": "step2_kernel" if tile_used[3] == 2 else "step_kernel"},
         "wall_s": round(wall, 3),
         "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0],
     }

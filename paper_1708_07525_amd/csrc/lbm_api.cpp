@@ -939,7 +939,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
 // that they stay in the Infinity Cache while the group advances a chunk of steps; items
 // [first, first + count) of the precision's item table.
 struct BatchGroup {
-  int prec, cp, first, count;
+  int prec, cp, first, count, first2, count2;   // one-step items, two-step items
 };
 
 struct lbm_batch {
@@ -947,14 +947,18 @@ struct lbm_batch {
   int chunk = 2;
   hipStream_t stream = nullptr;
   std::vector<lbm_ctx *> ctx;
-  // per precision: descriptor table and item table (device)
+  // per precision: descriptor table and item tables (device): one-step tiles and two-step
+  // tiles
   void *descs[3] = {nullptr, nullptr, nullptr};
   Item *items[3] = {nullptr, nullptr, nullptr};
+  Item *items2[3] = {nullptr, nullptr, nullptr};
   int item_cap[3] = {0, 0, 0};
+  int item2_cap[3] = {0, 0, 0};
   std::vector<BatchGroup> groups;
-  int *ranges = nullptr;     // device: {first, count} per group
+  int *ranges = nullptr;     // device: {first, count, first2, count2} per group
   int range_cap = 0;
-  int grid = 2048;
+  int grid = 2048;           // work-groups of the one-step batched launch
+  int grid2 = 1024;          // work-groups of the two-step batched launch
   hipGraphExec_t graph = nullptr;
   std::vector<int> graph_key;   // (precision, cache policy) of each group when the graph was captured
   bool dirty = true;
@@ -973,7 +977,9 @@ void drop_batch_graph(lbm_batch *b) {
 lbm_status batch_upload(lbm_batch *b) {
   b->groups.clear();
   for (int prec = 0; prec < 3; ++prec) {
-    std::vector<Item> items;
+    std::vector<Item> items, items2;
+    int w2 = 0, h2 = 0;
+    two_step_tile_shape(prec, &w2, &h2);
     std::vector<Desc<double>> d64;
     std::vector<Desc<float>> d32;
     double gnodes = 0;
@@ -988,7 +994,7 @@ lbm_status batch_upload(lbm_batch *b) {
       const double nodes = (double)c->p.nx * c->p.ny;
       if (b->groups.empty() || b->groups.back().prec != prec ||
           (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
-        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0});
+        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0, (int)items2.size(), 0});
         gnodes = 0;
       }
       gnodes += nodes;
@@ -1001,8 +1007,12 @@ lbm_status batch_upload(lbm_batch *b) {
       const int ntx = (c->p.nx + tw - 1) / tw, nty = (c->p.ny + rows - 1) / rows;
       for (int ty = 0; ty < nty; ++ty)
         for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * tw, ty * rows, tw});
+      const int ntx2 = (c->p.nx + w2 - 1) / w2, nty2 = (c->p.ny + h2 - 1) / h2;
+      for (int ty = 0; ty < nty2; ++ty)
+        for (int tx = 0; tx < ntx2; ++tx) items2.push_back(Item{idx, tx * w2, ty * h2, w2});
       BatchGroup &g = b->groups.back();
       g.count = (int)items.size() - g.first;
+      g.count2 = (int)items2.size() - g.first2;
       g.cp = default_policy(prec, gnodes, 1);
     }
     const int n = (int)items.size();
@@ -1014,6 +1024,17 @@ lbm_status batch_upload(lbm_batch *b) {
       if (hipMalloc((void **)&b->items[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
       b->item_cap[prec] = cap;
     }
+    const int n2 = (int)items2.size();
+    if (n2 > b->item2_cap[prec]) {
+      drop_batch_graph(b);
+      if (b->items2[prec]) (void)hipFree(b->items2[prec]);
+      int cap = std::max(n2, 2 * b->item2_cap[prec]);
+      if (hipMalloc((void **)&b->items2[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
+      b->item2_cap[prec] = cap;
+    }
+    if (n2 && hipMemcpyAsync(b->items2[prec], items2.data(), n2 * sizeof(Item), hipMemcpyHostToDevice, b->stream) !=
+                  hipSuccess)
+      return LBM_EDEVICE;
     if (n) {
       if (hipMemcpyAsync(b->items[prec], items.data(), n * sizeof(Item), hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_EDEVICE;
@@ -1031,13 +1052,15 @@ lbm_status batch_upload(lbm_batch *b) {
     if (b->ranges) (void)hipFree(b->ranges);
     b->ranges = nullptr;
     const int cap = std::max(ng, 2 * b->range_cap);
-    if (hipMalloc((void **)&b->ranges, (size_t)cap * 2 * sizeof(int)) != hipSuccess) return LBM_ENOMEM;
+    if (hipMalloc((void **)&b->ranges, (size_t)cap * 4 * sizeof(int)) != hipSuccess) return LBM_ENOMEM;
     b->range_cap = cap;
   }
   std::vector<int> r;
   for (const BatchGroup &g : b->groups) {
     r.push_back(g.first);
     r.push_back(g.count);
+    r.push_back(g.first2);
+    r.push_back(g.count2);
   }
   if (ng && hipMemcpyAsync(b->ranges, r.data(), r.size() * sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess)
     return LBM_EDEVICE;
@@ -1056,14 +1079,32 @@ std::vector<int> batch_key(const lbm_batch *b) {
   return k;
 }
 
+// Steps per batched launch: 2 when a replay chunk is a multiple of 4 steps (so a replay
+// flips the population and field buffers an even number of times), else 1.
+int batch_spl(const lbm_batch *b) { return b->chunk % 4 == 0 ? 2 : 1; }
+
 // n steps of every group, group after group (a group's cavities stay cache resident while
-// it advances; groups are independent, so the order changes no result)
+// it advances; groups are independent, so the order changes no result): pairs of steps in
+// the two-step kernel, an odd step in the one-step kernel (with the field buffer the pairs
+// left current: parity bit 1)
 hipError_t batch_launch_steps(lbm_batch *b, int64_t n, hipStream_t s) {
+  const int spl = batch_spl(b);
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     const BatchGroup &g = b->groups[gi];
-    for (int64_t k = 0; k < n; ++k) {
-      int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], b->ranges + 2 * gi, b->grid,
-                                (int)(k & 1), s);
+    const int *rg = b->ranges + 4 * gi;
+    int64_t k = 0;
+    if (spl == 2)
+      for (; k + 2 <= n; k += 2) {
+        const int q = (int)((k / 2) & 1);
+        int e = launch_step2_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2, b->grid2, q, s);
+        if (e) return (hipError_t)e;
+      }
+    for (; k < n; ++k) {
+      // launches so far: k / 2 two-step ones, then single steps
+      const int launches = (int)(spl == 2 ? k / 2 + (k - 2 * (k / 2)) : k);
+      const int pairs = (int)(spl == 2 ? (k / 2) & 1 : 0);
+      const int parity = (launches & 1) | (pairs << 1);
+      int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], rg, b->grid, parity, s);
       if (e) return (hipError_t)e;
     }
   }
@@ -1086,7 +1127,10 @@ LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *s
     return LBM_EDEVICE;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b->grid = prop.multiProcessorCount * 8;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    b->grid = prop.multiProcessorCount * 8;
+    b->grid2 = prop.multiProcessorCount * 4;
+  }
   bool ok = true;
   for (int prec = 0; prec < 3 && ok; ++prec) {
     const size_t dsz = prec == PREC_FP64 ? sizeof(Desc<double>) : sizeof(Desc<float>);
@@ -1110,6 +1154,7 @@ LBM_API void lbm_batch_destroy(lbm_batch *b) {
   for (int prec = 0; prec < 3; ++prec) {
     if (b->descs[prec]) (void)hipFree(b->descs[prec]);
     if (b->items[prec]) (void)hipFree(b->items[prec]);
+    if (b->items2[prec]) (void)hipFree(b->items2[prec]);
   }
   if (b->ranges) (void)hipFree(b->ranges);
   delete b;
@@ -1179,10 +1224,15 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     }
   }
   if (left > 0 && batch_launch_steps(b, left, b->stream) != hipSuccess) return LBM_EDEVICE;
+  // buffers flipped by the remainder: one per launch (populations), one per pair (fields)
+  const int spl = batch_spl(b);
+  const int64_t launches = spl == 2 ? left / 2 + (left & 1) : left;
+  const int64_t pairs = spl == 2 ? left / 2 : 0;
   for (lbm_ctx *c : b->ctx) {
     c->step += nsteps;
-    if (left & 1) c->cur ^= 1;
+    if (launches & 1) c->cur ^= 1;
+    if (pairs & 1) c->d4cur ^= 1;
   }
-  if (left & 1) b->dirty = true;   // base parities in the table changed
+  if ((launches & 1) || (pairs & 1)) b->dirty = true;   // parities and field buffers in the table changed
   return LBM_OK;
 }

@@ -79,9 +79,16 @@ int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void 
 // written to d4b;
 // cavities without walls through the nodes only
 int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
-// range: device pointer to {first item, item count} of the group to step
+// range: device pointer to {first item, item count} of the group to step; parity bit 0
+// selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream);
+// two steps per launch over items of two-step tiles (item.tw = tile width); parity as above
+// for both the population and the field buffers
+int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                       int parity, void *stream);
+// tile of the two-step kernels for a storage precision
+void two_step_tile_shape(int prec, int *w, int *h);
 // observables: partial sums per block, then a final fixed-order reduction.
 // out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)
 int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials,

@@ -857,22 +857,25 @@ __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R sca
   }
 }
 
+// Two steps of the tile at (x0, y0).  parity selects the population buffers as in step_kernel
+// and the field buffers: read d4, write d4b when even; the other way round when odd.
+// Every thread of the work-group calls this (it synchronises); none returns early.
 template <typename S, int CP>
-__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
+__device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
+                                              S (*lpop)[TwoStep<S>::RN]) {
   using R = typename St<S>::R;
   using FIO = FieldIO<S, CP>;
   constexpr int TS_W = TwoStep<S>::W, TS_H = TwoStep<S>::H, TS_RW = TwoStep<S>::RW, TS_RH = TwoStep<S>::RH;
-  constexpr int TS_RN = TwoStep<S>::RN, TS_THREADS = TwoStep<S>::THREADS;
-  __shared__ S lpop[NPOP][TS_RN];
+  constexpr int TS_THREADS = TwoStep<S>::THREADS;
   constexpr uint32_t RS = sizeof(R);
   const uint32_t PR = (uint32_t)d.plane * RS;
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
   const int cur = (d.base_parity ^ parity) & 1;
-  const StepRes rs = step_resources<S>(d, cur);
-  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int x0 = (b % ntx) * TS_W, y0 = (b / ntx) * TS_H;
+  StepRes rs = step_resources<S>(d, cur);
+  const rsrc_t fread = make_rsrc((parity & 1) ? d.d4b : d.d4, ND4 * PR);
+  const rsrc_t fwrite = make_rsrc((parity & 1) ? d.d4 : d.d4b, ND4 * PR);
   const uint32_t step = d.counter[cur];
-  if (b == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 2u;
+  if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 2u;
   const R is = d.inv_scale, sc = d.scale;
   // the halo region and every node it pulls from lie inside the domain
   const bool interior = x0 >= 2 && x0 + TS_W + 1 <= nx - 1 && y0 >= 2 && y0 + TS_H + 1 <= ny - 1;
@@ -899,7 +902,7 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typenam
     if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
     else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(rs.d4, c * RS, (uint32_t)k * PR);
+    for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
     R a, bb;
     porous_coeffs(d, phi, a, bb);
     collide(d, phi, a, bb, fd, gd, hd, prev);
@@ -937,40 +940,65 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typenam
 
   // step two: the tile, pulled from LDS
   const int x = x0 + tx, y = y0 + ty;
-  if (x >= nx || y >= ny) return;
-  const int r = (ty + 1) * TS_RW + tx + 1;
-  const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
-  const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
-  const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
-  // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
-  auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
-  R fd[9], gd[5], hd[5];
-  fd[0] = L(0, 0);
-  fd[1] = okxm ? L(1, -1) : L(3, 0);
-  fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
-  fd[3] = okxp ? L(3, 1) : L(1, 0);
-  fd[4] = okyp ? L(4, TS_RW) : L(2, 0);
-  fd[5] = ok5 ? L(5, -TS_RW - 1) : L(7, 0);
-  fd[6] = ok6 ? L(6, -TS_RW + 1) : L(8, 0);
-  fd[7] = ok7 ? L(7, TS_RW + 1) : L(5, 0);
-  fd[8] = ok8 ? L(8, TS_RW - 1) : L(6, 0);
+  if (x < nx && y < ny) {
+    const int r = (ty + 1) * TS_RW + tx + 1;
+    const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
+    const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
+    const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+    // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
+    auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
+    R fd[9], gd[5], hd[5];
+    fd[0] = L(0, 0);
+    fd[1] = okxm ? L(1, -1) : L(3, 0);
+    fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
+    fd[3] = okxp ? L(3, 1) : L(1, 0);
+    fd[4] = okyp ? L(4, TS_RW) : L(2, 0);
+    fd[5] = ok5 ? L(5, -TS_RW - 1) : L(7, 0);
+    fd[6] = ok6 ? L(6, -TS_RW + 1) : L(8, 0);
+    fd[7] = ok7 ? L(7, TS_RW + 1) : L(5, 0);
+    fd[8] = ok8 ? L(8, TS_RW - 1) : L(6, 0);
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    R *e = q ? hd : gd;
-    const int p = q ? 14 : 9;
-    e[0] = L(p, 0);
-    e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
-    e[2] = okym ? L(p + 2, -TS_RW) : L(p + 4, 0);
-    e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
-    e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
+    for (int q = 0; q < 2; ++q) {
+      R *e = q ? hd : gd;
+      const int p = q ? 14 : 9;
+      e[0] = L(p, 0);
+      e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
+      e[2] = okym ? L(p + 2, -TS_RW) : L(p + 4, 0);
+      e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
+      e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
+    }
+    if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
+    const uint32_t c = (uint32_t)y * pitch + x;
+    R phi = d.phi_u;
+    if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+    rs.d4 = fwrite;
+    collide_store<S, CP>(d, rs, c, step + 1u, phi, fd, gd, hd, prev);
   }
-  if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
-  const uint32_t c = (uint32_t)y * pitch + x;
-  R phi = d.phi_u;
-  if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
-  StepRes rs2 = rs;
-  rs2.d4 = make_rsrc(d.d4b, ND4 * PR);
-  collide_store<S, CP>(d, rs2, c, step + 1u, phi, fd, gd, hd, prev);
+}
+
+template <typename S, int CP>
+__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
+  __shared__ S lpop[NPOP][TwoStep<S>::RN];
+  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  two_step_tile<S, CP>(d, (b % ntx) * TwoStep<S>::W, (b / ntx) * TwoStep<S>::H, parity, lpop);
+}
+
+// Batched two steps: as step_batch_kernel, over items of W x H tiles (item.tw = W)
+template <typename S, int CP>
+__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_batch_kernel(
+    const Desc<typename St<S>::R> *__restrict__ descs, const Item *__restrict__ items,
+    const int *__restrict__ range, int parity) {
+  __shared__ S lpop[NPOP][TwoStep<S>::RN];
+  const int first = range[0], n = range[1];
+  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int end = min(n, (b + 1) * per);
+  for (int it = b * per; it < end; ++it) {
+    const Item item = items[first + it];
+    const Desc<typename St<S>::R> d = descs[item.cavity];
+    two_step_tile<S, CP>(d, item.x0, item.y0, parity, lpop);
+    __syncthreads();                       // LDS is reused by the next item
+  }
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1010,7 +1038,10 @@ __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<
     const Item item = items[first + it];
     const Desc<typename St<S>::R> d = descs[item.cavity];
     const int cur = (d.base_parity ^ parity) & 1;
-    const StepRes rs = step_resources<S>(d, cur);
+    StepRes rs = step_resources<S>(d, cur);
+    // bit 1 of parity: the fields are in the second buffer (after an odd number of two-step
+    // launches of the same replay)
+    if (parity & 2) rs.d4 = make_rsrc(d.d4b, ND4 * (uint32_t)d.plane * (uint32_t)sizeof(typename St<S>::R));
     step_tile2d<S, CP>(d, rs, cur, item.x0, item.y0, item.tw);
   }
 }
@@ -1308,6 +1339,41 @@ int launch_step2(int prec, const void *desc, int cp, int parity, void *stream) {
     case PREC_FP32: return step2_t<float>(desc, cp, parity, stream);
     default: return step2_t<_Float16>(desc, cp, parity, stream);
   }
+}
+
+template <typename S>
+static void batch2_t(int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
+                     hipStream_t s) {
+  using D = Desc<typename St<S>::R>;
+  const D *dd = (const D *)descs;
+  const dim3 block(TwoStep<S>::THREADS);
+  switch (cp) {
+    case CP_STREAM:
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_STREAM>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_RESIDENT>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    default:
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_TUNED>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+  }
+}
+
+int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                       int parity, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (prec) {
+    case PREC_FP64: batch2_t<double>(cp, descs, items, range, grid, parity, s); break;
+    case PREC_FP32: batch2_t<float>(cp, descs, items, range, grid, parity, s); break;
+    default: batch2_t<_Float16>(cp, descs, items, range, grid, parity, s); break;
+  }
+  return (int)hipGetLastError();
+}
+
+void two_step_tile_shape(int prec, int *w, int *h) {
+  *w = prec == PREC_FP64 ? TwoStep<double>::W : TwoStep<float>::W;
+  *h = prec == PREC_FP64 ? TwoStep<double>::H : TwoStep<float>::H;
 }
 
 template <typename S>
