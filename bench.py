@@ -87,7 +87,8 @@ def profiled_traffic(prec, n, launch):
     summary for this workload, the kernel code has changed since the counters were taken, or
     the launch shape and cache policy [tile_x, tile_y, policy] differ from the profiled ones."""
     import re
-    path = os.path.join(ROOT, "profiles", f"step_kernel_{prec}_cavity{n}.md")
+    kernel = "step2_kernel" if launch[3] == 2 else "step_kernel"
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_cavity{n}.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
