@@ -940,6 +940,8 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
 // [first, first + count) of the precision's item table.
 struct BatchGroup {
   int prec, cp, first, count, first2, count2;   // one-step items, two-step items
+  int grid2;   // work-groups of the two-step launch (one per item; count2 rounded up to a
+               // power of two, so that a graph survives small changes of the group)
 };
 
 struct lbm_batch {
@@ -958,7 +960,6 @@ struct lbm_batch {
   int *ranges = nullptr;     // device: {first, count, first2, count2} per group
   int range_cap = 0;
   int grid = 2048;           // work-groups of the one-step batched launch
-  int grid2 = 1024;          // work-groups of the two-step batched launch
   hipGraphExec_t graph = nullptr;
   std::vector<int> graph_key;   // (precision, cache policy) of each group when the graph was captured
   bool dirty = true;
@@ -994,7 +995,7 @@ lbm_status batch_upload(lbm_batch *b) {
       const double nodes = (double)c->p.nx * c->p.ny;
       if (b->groups.empty() || b->groups.back().prec != prec ||
           (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
-        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0, (int)items2.size(), 0});
+        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0, (int)items2.size(), 0, 1});
         gnodes = 0;
       }
       gnodes += nodes;
@@ -1013,6 +1014,8 @@ lbm_status batch_upload(lbm_batch *b) {
       BatchGroup &g = b->groups.back();
       g.count = (int)items.size() - g.first;
       g.count2 = (int)items2.size() - g.first2;
+      g.grid2 = 1;
+      while (g.grid2 < g.count2) g.grid2 *= 2;
       g.cp = default_policy(prec, gnodes, 1);
     }
     const int n = (int)items.size();
@@ -1069,12 +1072,14 @@ lbm_status batch_upload(lbm_batch *b) {
   return LBM_OK;
 }
 
-// (precision, cache policy) of each group: a captured graph stays valid while this is unchanged
+// (precision, cache policy, two-step grid) of each group: a captured graph stays valid while
+// this is unchanged
 std::vector<int> batch_key(const lbm_batch *b) {
   std::vector<int> k;
   for (const BatchGroup &g : b->groups) {
     k.push_back(g.prec);
     k.push_back(g.cp);
+    k.push_back(g.grid2);
   }
   return k;
 }
@@ -1096,7 +1101,7 @@ hipError_t batch_launch_steps(lbm_batch *b, int64_t n, hipStream_t s) {
     if (spl == 2)
       for (; k + 2 <= n; k += 2) {
         const int q = (int)((k / 2) & 1);
-        int e = launch_step2_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2, b->grid2, q, s);
+        int e = launch_step2_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2, g.grid2, q, s);
         if (e) return (hipError_t)e;
       }
     for (; k < n; ++k) {
@@ -1129,7 +1134,6 @@ LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *s
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
     b->grid = prop.multiProcessorCount * 8;
-    b->grid2 = prop.multiProcessorCount * 4;
   }
   bool ok = true;
   for (int prec = 0; prec < 3 && ok; ++prec) {

@@ -83,8 +83,9 @@ int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
 // selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream);
-// two steps per launch over items of two-step tiles (item.tw = tile width); parity as above
-// for both the population and the field buffers
+// two steps per launch over items of two-step tiles (item.tw = tile width), one item per
+// work-group: grid >= the group's item count; parity as above for both the population and
+// the field buffers
 int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
                        int parity, void *stream);
 // tile of the two-step kernels for a storage precision

@@ -983,22 +983,19 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typenam
   two_step_tile<S, CP>(d, (b % ntx) * TwoStep<S>::W, (b / ntx) * TwoStep<S>::H, parity, lpop);
 }
 
-// Batched two steps: as step_batch_kernel, over items of W x H tiles (item.tw = W)
+// Batched two steps over items of W x H tiles (item.tw = W): one item per work-group (a
+// loop over items keeps values live across iterations and costs a third of the occupancy);
+// the grid may exceed the item count, the extra work-groups exit at once.
 template <typename S, int CP>
 __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_batch_kernel(
     const Desc<typename St<S>::R> *__restrict__ descs, const Item *__restrict__ items,
     const int *__restrict__ range, int parity) {
   __shared__ S lpop[NPOP][TwoStep<S>::RN];
   const int first = range[0], n = range[1];
-  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int end = min(n, (b + 1) * per);
-  for (int it = b * per; it < end; ++it) {
-    const Item item = items[first + it];
-    const Desc<typename St<S>::R> d = descs[item.cavity];
-    two_step_tile<S, CP>(d, item.x0, item.y0, parity, lpop);
-    __syncthreads();                       // LDS is reused by the next item
-  }
+  if ((int)blockIdx.x >= n) return;
+  const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
+  const Item item = items[first + it];
+  two_step_tile<S, CP>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1036,7 +1033,7 @@ __global__ void __launch_bounds__(256) step_batch_kernel(const Desc<typename St<
   const int end = min(n, (b + 1) * per);
   for (int it = b * per; it < end; ++it) {
     const Item item = items[first + it];
-    const Desc<typename St<S>::R> d = descs[item.cavity];
+    const Desc<typename St<S>::R> &d = descs[item.cavity];
     const int cur = (d.base_parity ^ parity) & 1;
     StepRes rs = step_resources<S>(d, cur);
     // bit 1 of parity: the fields are in the second buffer (after an odd number of two-step
