@@ -123,7 +123,9 @@ uint64_t lbm_footprint_bytes(const lbm_params *p);
 /* Validates p, maps it to lattice units (section 4.1, Eq. 29) and allocates the device
  * buffers.  LBM_EINVAL: nx or ny < 3, a non-positive group, phi outside (0, 1], a free rate
  * outside (0, 2), a derived s_v, zeta_alpha or eta_D outside (0, 2), inconsistent periodic
- * sides.  *out is set only on LBM_OK. */
+ * sides, or a lattice whose 19 population planes (rows padded to 64 nodes) exceed 4 GiB in the
+ * storage type (about 28M nodes in FP64, 56M in FP32, 113M in FP16: the kernels use 32-bit
+ * buffer offsets).  *out is set only on LBM_OK. */
 lbm_status lbm_create(const lbm_params *p, struct lbm_ctx **out);
 
 /* Initial state from host fields (each nx*ny doubles): porosity (NULL: uniform p.phi; a

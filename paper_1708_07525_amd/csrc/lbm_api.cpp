@@ -46,6 +46,8 @@ struct Layout {
 // Planes of ny rows of `pitch` elements; the plane stride is padded by 256 elements past a
 // 1024-element boundary so that the 19 + 4 concurrent streams do not start on the same
 // HBM channel.
+constexpr double kMaxResourceBytes = 4294967295.0;   // largest range of one buffer resource
+
 Layout plan_layout(int nx, int ny, int prec) {
   Layout L{};
   const size_t es = store_size(prec), rs = real_size(prec);
@@ -151,6 +153,12 @@ lbm_status validate(const lbm_params *p, std::string &msg) {
   if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return bad("lattice too large");
   if (p->precision < 0 || p->precision > 2) return bad("unknown precision");
+  // the kernels address the 19 population planes of a buffer through one buffer resource with
+  // 32-bit byte offsets
+  if ((double)NPOP * (double)plan_layout(p->nx, p->ny, p->precision).plane * (double)store_size(p->precision) >
+      kMaxResourceBytes)
+    return bad("lattice too large for this storage type: the 19 population planes of a buffer must fit "
+               "in 4 GiB (about 28M nodes in FP64, 56M in FP32, 113M in FP16)");
   if (p->model != 0 && p->model != 1) return bad("model must be 0 (present) or 1 (Model-A)");
   int n_half = 0, n_node = 0;
   for (int s = 0; s < 4; ++s) {

@@ -64,9 +64,13 @@ def test_footprint_scales_with_precision():
     {"sides": ("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), "Bi_C": -0.5},
     {"nx": 4, "sides": ("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")},
     {"direct": 1, "nu": 0.0, "alpha_e": 0.1, "D_e": 0.1, "K": 1.0},
+    # population planes beyond the 4 GiB range of one buffer resource
+    {"nx": 8192, "ny": 8192, "precision": "fp32"}, {"nx": 6144, "ny": 6144, "precision": "fp64"},
+    {"nx": 11264, "ny": 11264, "precision": "fp16s"},
 ])
 def test_create_rejects_invalid_parameters(bad):
-    p = lbm.make_params(bad)
+    bad = dict(bad)
+    p = lbm.make_params(bad, bad.pop("precision", "fp32"))
     h = ctypes.c_void_p()
     rc = lbm.lib().lbm_create(ctypes.byref(p), ctypes.byref(h))
     assert rc == lbm.EINVAL
