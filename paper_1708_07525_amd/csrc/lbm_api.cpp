@@ -213,8 +213,8 @@ Tile default_tile(const lbm_params *p) {
 // accesses, 1 porosity load)
 double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC_FP32 ? 188.0 : 112.0); }
 
-// Steps per launch when none is set (cavities without walls through the nodes): the
-// two-step kernel at every measured size and storage type.
+// Steps per launch when none is set: the two-step kernel at every measured size and storage
+// type (where it applies, see two_step_ok).
 int default_spl(int prec, double nodes) {
   (void)prec;
   (void)nodes;
@@ -580,8 +580,23 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
 
 // Time steps per launch: 2 (the LDS-staged two-step kernel) unless the cavity has walls
 // through the nodes, or set otherwise.
+// With walls through the nodes the two-step kernel places its last tiles against the far
+// walls, so the lattice must hold one tile.  FP16 storage with walls through the nodes always
+// takes one step per launch: the two-step kernel is slower there (2048^2: 41 against 50
+// GLUPS), and its FP16 results would not match the one-step kernel's bit for bit (the
+// compiler fuses multiply-adds of the boundary rule differently in the two kernels, and
+// stochastic rounding turns a last-bit FP32 difference into a different FP16 value now and
+// then).
+static bool two_step_ok(const lbm_ctx *c) {
+  if (!node_walls(&c->p)) return true;
+  if (c->prec == PREC_FP16S) return false;
+  int w = 0, h = 0;
+  two_step_tile_shape(c->prec, &w, &h);
+  return c->p.nx >= w && c->p.ny >= h;
+}
+
 static int ctx_spl(const lbm_ctx *c) {
-  if (node_walls(&c->p)) return 1;
+  if (!two_step_ok(c)) return 1;
   return c->steps_per_launch > 0 ? c->steps_per_launch : default_spl(c->prec, (double)c->p.nx * c->p.ny);
 }
 
@@ -891,7 +906,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   for (int cp = 0; cp < CP_COUNT; ++cp)
     for (int tx : txs)
       for (int ty : tys) cands.push_back(Cand{1, cp, tx, ty});
-  if (!node_walls(&c->p))   // the two-step kernel has a fixed 32 x 16 tile
+  if (two_step_ok(c))   // the two-step kernel has a fixed tile (64 x 8, FP64 32 x 8)
     for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty});
   const int nsteps = steps + (steps & 1);
   for (const Cand &k : cands) {

@@ -500,10 +500,14 @@ __device__ __forceinline__ R boundary_scalar(int kind, R fixed, R beta, R amb, R
 // The boundary update of node (x, y): bx / by mark a wall through the node in x / y.  Every
 // load it needs (the pulls of f and ff, the porosities, the previous-step fields of the
 // node) is issued before any arithmetic, so a boundary thread waits for memory once.
-template <typename S, int CP>
+// pull(X, Y, f, g, h) gives the pre-collision populations of node (X, Y) of this step (from
+// global memory, or from the first step's results in LDS); LOAD_PREV: read the node's
+// previous-step fields into prev (else the caller has them).
+template <typename S, int CP, bool LOAD_PREV, typename Pull>
 __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, const StepRes &rs, int x, int y, bool bx,
                                           bool by, typename St<S>::R *fd, typename St<S>::R *gd,
-                                          typename St<S>::R *hd, typename St<S>::R *prev, typename St<S>::R &phib) {
+                                          typename St<S>::R *hd, typename St<S>::R *prev, typename St<S>::R &phib,
+                                          Pull pull) {
   using R = typename St<S>::R;
   const int dx = bx ? (x == 0 ? 1 : -1) : 0, dy = by ? (y == 0 ? 1 : -1) : 0;
   const int sx = x == 0 ? LEFT : RIGHT, sy = y == 0 ? BOTTOM : TOP;
@@ -533,8 +537,8 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   const uint32_t RS = sizeof(R), PR = (uint32_t)d.plane * RS;
   const uint32_t cb = ((uint32_t)y * d.pitch + x) * RS;
   R ff[9], gf[5], hf[5], f2[9], g2[5], h2[5];
-  pull_inner<S, CP>(d, rs, xf, yf, ff, gf, hf);
-  pull_inner<S, CP>(d, rs, xff, yff, f2, g2, h2);
+  pull(xf, yf, ff, gf, hf);
+  pull(xff, yff, f2, g2, h2);
   R phif = d.phi_u, phiff = d.phi_u;
   phib = d.phi_u;
   if (d.phi_field) {
@@ -542,8 +546,10 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
     phif = FieldIO<S, CP>::ld(rs.phi, ((uint32_t)yf * d.pitch + xf) * RS, 0);
     phiff = FieldIO<S, CP>::ld(rs.phi, ((uint32_t)yff * d.pitch + xff) * RS, 0);
   }
+  if (LOAD_PREV) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) prev[k] = FieldIO<S, CP>::ld(rs.d4, cb, (uint32_t)k * PR);
+    for (int k = 0; k < 4; ++k) prev[k] = FieldIO<S, CP>::ld(rs.d4, cb, (uint32_t)k * PR);
+  }
   R af, bf;
   porous_coeffs(d, phif, af, bf);
   R drho, uxf, uyf, dTf, dCf;
@@ -791,8 +797,8 @@ __device__ __forceinline__ void nee_node(const Desc<typename St<S>::R> &d, const
   }
   const uint32_t step = d.counter[cur];
   R fd[9], gd[5], hd[5], prev[4], phi;
-  nee_boundary<S, CP>(d, rs, x, y, wx && (x == 0 || x == nx - 1), wy && (y == 0 || y == ny - 1), fd, gd, hd, prev,
-                      phi);
+  nee_boundary<S, CP, true>(d, rs, x, y, wx && (x == 0 || x == nx - 1), wy && (y == 0 || y == ny - 1), fd, gd, hd,
+                            prev, phi, [&](int X, int Y, R *f, R *g, R *h) { pull_inner<S, CP>(d, rs, X, Y, f, g, h); });
   collide_store<S, CP>(d, rs, (uint32_t)y * d.pitch + x, step, phi, fd, gd, hd, prev);
 }
 
@@ -860,7 +866,12 @@ __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R sca
 // Two steps of the tile at (x0, y0).  parity selects the population buffers as in step_kernel
 // and the field buffers: read d4, write d4b when even; the other way round when odd.
 // Every thread of the work-group calls this (it synchronises); none returns early.
-template <typename S, int CP>
+// NEE: walls through the boundary nodes.  A boundary node takes the rule of nee_node in both
+// steps, in step one from global memory, in step two from the first step's results in LDS:
+// its f and ff and their upstream nodes (up to three nodes inward and one along the wall)
+// lie in the tile's region, which the caller guarantees by placing the last tile of a row or
+// column against the far wall (tiles then overlap and write equal values twice).
+template <typename S, int CP, bool NEE>
 __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
                                               S (*lpop)[TwoStep<S>::RN]) {
   using R = typename St<S>::R;
@@ -874,6 +885,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
   StepRes rs = step_resources<S>(d, cur);
   const rsrc_t fread = make_rsrc((parity & 1) ? d.d4b : d.d4, ND4 * PR);
   const rsrc_t fwrite = make_rsrc((parity & 1) ? d.d4 : d.d4b, ND4 * PR);
+  rs.d4 = fread;                           // the fields of step one's previous level
   const uint32_t step = d.counter[cur];
   if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 2u;
   const R is = d.inv_scale, sc = d.scale;
@@ -898,11 +910,18 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
     const int r = ly * TS_RW + lx;
     R fd[9], gd[5], hd[5];
     R phi = d.phi_u;
-    if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
-    if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
-    else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
+    const bool bx = NEE && !interior && !d.perx && (X == 0 || X == nx - 1);
+    const bool by = NEE && !interior && !d.pery && (Y == 0 || Y == ny - 1);
+    if (NEE && (bx || by)) {
+      nee_boundary<S, CP, true>(d, rs, X, Y, bx, by, fd, gd, hd, prev, phi,
+                                [&](int PX, int PY, R *f, R *g, R *h) { pull_inner<S, CP>(d, rs, PX, PY, f, g, h); });
+    } else {
+      if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+      if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
+      else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
+      for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
+    }
     R a, bb;
     porous_coeffs(d, phi, a, bb);
     collide(d, phi, a, bb, fd, gd, hd, prev);
@@ -942,12 +961,33 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
   const int x = x0 + tx, y = y0 + ty;
   if (x < nx && y < ny) {
     const int r = (ty + 1) * TS_RW + tx + 1;
+    const uint32_t c = (uint32_t)y * pitch + x;
+    R fd[9], gd[5], hd[5];
+    R phi = d.phi_u;
+    const bool bx = NEE && !interior && !d.perx && (x == 0 || x == nx - 1);
+    const bool by = NEE && !interior && !d.pery && (y == 0 || y == ny - 1);
+    if (NEE && (bx || by)) {
+      // the pulls of f and ff from LDS (region node of (PX, PY): PX - x0 + 1, PY - y0 + 1)
+      auto lds_pull = [&](int PX, int PY, R *f, R *g, R *h) {
+        const int q = (PY - y0 + 1) * TS_RW + (PX - x0 + 1);
+        const int up[9] = {q, q - 1, q - TS_RW, q + 1, q + TS_RW, q - TS_RW - 1, q - TS_RW + 1, q + TS_RW + 1,
+                           q + TS_RW - 1};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = to_real<S>(lpop[i][up[i]], is);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          g[i] = to_real<S>(lpop[9 + i][up[i]], is);
+          h[i] = to_real<S>(lpop[14 + i][up[i]], is);
+        }
+      };
+      R unused[4];
+      nee_boundary<S, CP, false>(d, rs, x, y, bx, by, fd, gd, hd, unused, phi, lds_pull);
+    } else {
     const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
     const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
     const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
     // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
     auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
-    R fd[9], gd[5], hd[5];
     fd[0] = L(0, 0);
     fd[1] = okxm ? L(1, -1) : L(3, 0);
     fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
@@ -968,19 +1008,25 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
     }
     if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
-    const uint32_t c = (uint32_t)y * pitch + x;
-    R phi = d.phi_u;
     if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+    }
     rs.d4 = fwrite;
     collide_store<S, CP>(d, rs, c, step + 1u, phi, fd, gd, hd, prev);
   }
 }
 
-template <typename S, int CP>
+// NEE: the last tile of each row and column is placed against the far side (nx >= W and
+// ny >= H, checked by the launcher)
+template <typename S, int CP, bool NEE>
 __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
   __shared__ S lpop[NPOP][TwoStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  two_step_tile<S, CP>(d, (b % ntx) * TwoStep<S>::W, (b / ntx) * TwoStep<S>::H, parity, lpop);
+  int x0 = (b % ntx) * TwoStep<S>::W, y0 = (b / ntx) * TwoStep<S>::H;
+  if (NEE) {
+    x0 = min(x0, d.nx - TwoStep<S>::W);
+    y0 = min(y0, d.ny - TwoStep<S>::H);
+  }
+  two_step_tile<S, CP, NEE>(d, x0, y0, parity, lpop);
 }
 
 // Batched two steps over items of W x H tiles (item.tw = W): one item per work-group (a
@@ -995,7 +1041,7 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_batch_kernel(
   if ((int)blockIdx.x >= n) return;
   const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
   const Item item = items[first + it];
-  two_step_tile<S, CP>(descs[item.cavity], item.x0, item.y0, parity, lpop);
+  two_step_tile<S, CP, false>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1322,10 +1368,31 @@ static int step2_t(const void *desc, int cp, int parity, void *stream) {
   constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
   const dim3 grid(ntx * nty), block(TwoStep<S>::THREADS);
+  if (d.nee) {
+    // FP16 storage with walls through the nodes runs one step per launch; the tiles placed
+    // against the far sides must fit in the lattice
+    if constexpr (__is_same(S, _Float16)) {
+      return (int)hipErrorInvalidValue;
+    } else {
+      if (d.nx < W || d.ny < H) return (int)hipErrorInvalidValue;
+      switch (cp) {
+        case CP_STREAM:
+          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, d, ntx, parity);
+          break;
+        case CP_RESIDENT:
+          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, d, ntx, parity);
+          break;
+        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, d, ntx, parity); break;
+      }
+      return (int)hipGetLastError();
+    }
+  }
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM>), grid, block, 0, s, d, ntx, parity); break;
-    case CP_RESIDENT: hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT>), grid, block, 0, s, d, ntx, parity); break;
-    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, d, ntx, parity);
+      break;
+    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, d, ntx, parity); break;
   }
   return (int)hipGetLastError();
 }
