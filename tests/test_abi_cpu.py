@@ -98,3 +98,27 @@ def test_solver_refuses_to_run_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         lbm.Solver({"nx": 16, "ny": 16})
+
+
+# the largest lattices whose 19 population planes (rows padded to 64 nodes, planes to 1024
+# elements plus 256) fit in 4 GiB, and the next row up
+LARGEST = [("fp32", 7500, 7482), ("fp64", 5300, 5319), ("fp16s", 10600, 10638)]
+
+
+@pytest.mark.parametrize("prec,nx,ny", LARGEST)
+def test_largest_lattice_is_accepted_and_the_next_row_refused(prec, nx, ny):
+    es = {"fp32": 4, "fp64": 8, "fp16s": 2}[prec]
+    pitch = -(-nx // 64) * 64
+
+    def planes_bytes(rows):
+        return 19 * (-(-pitch * rows // 1024) * 1024 + 256) * es
+
+    assert planes_bytes(ny) < 2 ** 32 <= planes_bytes(ny + 1)
+    for rows, ok in ((ny, True), (ny + 1, False)):
+        p = lbm.make_params({"nx": nx, "ny": rows}, prec)
+        h = ctypes.c_void_p()
+        rc = lbm.lib().lbm_create(ctypes.byref(p), ctypes.byref(h))
+        # without a GPU an accepted lattice fails later, at the device (never LBM_EINVAL)
+        assert (rc != lbm.EINVAL) if ok else (rc == lbm.EINVAL)
+        if h.value:
+            lbm.lib().lbm_destroy(h)

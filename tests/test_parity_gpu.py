@@ -99,6 +99,44 @@ def test_full_size_band_cavity(prec):
     assert max(e.values()) <= TOL[prec], e
 
 
+@pytest.mark.parametrize("prec,nx,ny", [("fp32", 7500, 7482), ("fp64", 5300, 5319), ("fp16s", 10600, 10638)])
+def test_largest_lattice(prec, nx, ny):
+    """The largest lattice each storage type accepts: its 19 population planes just under the
+    4 GiB range of one buffer resource, so the largest plane and lane offsets of the kernels
+    are used.  Ragged tiles, a banded porosity field, 3 steps (a two-step launch, then a
+    one-step launch), every node against the oracle.  FP16 storage: T, C and rho against the
+    oracle within 1e-3 (a few stochastic roundings of deviations; the velocity after 3 steps
+    from rest is too small for a relative bound), and bit for bit against one step per
+    launch.  FP64: the largest speed after 3 steps is 3.3e-7, so the velocity is held to an absolute
+    1e-13 (the oracle sums O(1) populations, 9 per component, each rounded to 1.1e-16, over
+    3 steps: a few 1e-15; measured 2e-16) instead of 1e-10 of the largest speed."""
+    phi = np.repeat(0.35 + 0.07 * (np.arange(ny) * 8 // ny), nx).reshape(ny, nx)
+    T, C = workloads.noise_fields(nx, ny, 21)
+    p = workloads.cavity_params(nx=nx, ny=ny, Ra=1e6, Da=1e-3)
+    gpu, ref, e = run_pair(p, 3, prec, phi=phi, T=T, C=C)
+    if prec == "fp64":
+        F, R = gpu.fields(), ref.fields()
+        e["ux_abs"] = float(np.abs(F["ux"] - R["ux"]).max())
+        e["uy_abs"] = float(np.abs(F["uy"] - R["uy"]).max())
+        e["speed"] = float(np.hypot(R["ux"], R["uy"]).max())
+        del F, R
+    ref.close()
+    print(prec, nx, ny, e, flush=True)
+    if prec == "fp64":
+        assert max(e["T"], e["C"], e["rho"]) <= TOL[prec] and max(e["ux_abs"], e["uy_abs"]) <= 1e-13, e
+    elif prec == "fp16s":
+        assert e["T"] < 1e-3 and e["C"] < 1e-3 and e["rho"] < 1e-3, e
+        one = _solver()(p, phi=phi, T=T, C=C, precision=prec)
+        one.set_steps_per_launch(1)
+        one.step(3)
+        d = _state_diff(one.get_state(), gpu.get_state())
+        assert d is None, d
+        one.close()
+    else:
+        assert max(e.values()) <= TOL[prec], e
+    gpu.close()
+
+
 def test_observables_parity():
     case = workloads.small_cavity(seed=0)
     p = case["params"]
