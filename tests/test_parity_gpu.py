@@ -107,9 +107,10 @@ def test_largest_lattice(prec, nx, ny):
     one-step launch), every node against the oracle.  FP16 storage: T, C and rho against the
     oracle within 1e-3 (a few stochastic roundings of deviations; the velocity after 3 steps
     from rest is too small for a relative bound), and bit for bit against one step per
-    launch.  FP64: the largest speed after 3 steps is 3.3e-7, so the velocity is held to an absolute
-    1e-13 (the oracle sums O(1) populations, 9 per component, each rounded to 1.1e-16, over
-    3 steps: a few 1e-15; measured 2e-16) instead of 1e-10 of the largest speed."""
+    launch.  FP64: the largest speed after 3 steps is 3.3e-7, so the velocity is held to an
+    absolute 1e-13 (the oracle sums O(1) populations, 9 per component, each rounded to
+    1.1e-16, over 3 steps: a few 1e-15; measured 2e-16) instead of 1e-10 of the largest
+    speed."""
     phi = np.repeat(0.35 + 0.07 * (np.arange(ny) * 8 // ny), nx).reshape(ny, nx)
     T, C = workloads.noise_fields(nx, ny, 21)
     p = workloads.cavity_params(nx=nx, ny=ny, Ra=1e6, Da=1e-3)
