@@ -584,18 +584,18 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
 }
 
 // Second half of a node update: collision (moment space) with the previous-step fields
-// `prev`, then the stores.
+// `prev` and the porous coefficients a, b (Darcy and Forchheimer terms of Eq. 5), then the
+// stores.
 template <typename S, int CP>
-__device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
-                                              uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
-                                              typename St<S>::R *gd, typename St<S>::R *hd, typename St<S>::R *prev) {
+__device__ __forceinline__ void collide_store_ab(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
+                                                 uint32_t step, typename St<S>::R phi, typename St<S>::R a,
+                                                 typename St<S>::R b, typename St<S>::R *fd, typename St<S>::R *gd,
+                                                 typename St<S>::R *hd, typename St<S>::R *prev) {
   using R = typename St<S>::R;
   constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
   const uint32_t PB = (uint32_t)d.plane * ES;
   const uint32_t PR = (uint32_t)d.plane * RS;
   const uint32_t cr = c * RS;
-  R a, b;
-  porous_coeffs(d, phi, a, b);
   collide(d, phi, a, b, fd, gd, hd, prev);
   const R sc = d.scale;
   const uint32_t co = c * ES;
@@ -611,6 +611,16 @@ __device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, 
   FIO::st(prev[1], rs.d4, cr, PR);
   FIO::st(prev[2], rs.d4, cr, 2 * PR);
   FIO::st(prev[3], rs.d4, cr, 3 * PR);
+}
+
+// as collide_store_ab, with the porous coefficients of Eq. (7) computed from phi
+template <typename S, int CP>
+__device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
+                                              uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
+                                              typename St<S>::R *gd, typename St<S>::R *hd, typename St<S>::R *prev) {
+  typename St<S>::R a, b;
+  porous_coeffs(d, phi, a, b);
+  collide_store_ab<S, CP>(d, rs, c, step, phi, a, b, fd, gd, hd, prev);
 }
 
 // Second half of an interior or half-way-wall node update: previous-step fields, then
@@ -893,8 +903,8 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
   const bool interior = x0 >= 2 && x0 + TS_W + 1 <= nx - 1 && y0 >= 2 && y0 + TS_H + 1 <= ny - 1;
 
   // step one at region node (lx, ly) (global x0 - 1 + lx, y0 - 1 + ly): populations into
-  // LDS, the fields into `prev`
-  auto step_one = [&](int lx, int ly, R *prev) {
+  // LDS, the fields into `prev`, the porosity and porous coefficients into `pab`
+  auto step_one = [&](int lx, int ly, R *prev, R *pab) {
     int X = x0 - 1 + lx, Y = y0 - 1 + ly;
     if (!interior) {
       if (X < 0 || X >= nx) {
@@ -924,6 +934,9 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
     }
     R a, bb;
     porous_coeffs(d, phi, a, bb);
+    pab[0] = phi;
+    pab[1] = a;
+    pab[2] = bb;
     collide(d, phi, a, bb, fd, gd, hd, prev);
     Dither dz(c, step);
 #pragma unroll
@@ -937,8 +950,8 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
   // most one node of the halo ring: rows ly = 0 and TS_RH - 1, then columns lx = 0 and
   // TS_RW - 1 without the corners
   const int tx = (int)threadIdx.x % TS_W, ty = (int)threadIdx.x / TS_W;
-  R prev[4];
-  step_one(tx + 1, ty + 1, prev);
+  R prev[4], pab[3];
+  step_one(tx + 1, ty + 1, prev, pab);
   constexpr int NHALO = 2 * TS_RW + 2 * TS_H;
   static_assert(NHALO <= TS_THREADS, "one halo node per thread at most");
   if ((int)threadIdx.x < NHALO) {
@@ -952,8 +965,8 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       hx = q < TS_H ? 0 : TS_RW - 1;
       hy = 1 + q % TS_H;
     }
-    R unused[4];
-    step_one(hx, hy, unused);
+    R unused[4], unused_pab[3];
+    step_one(hx, hy, unused, unused_pab);
   }
   __syncthreads();
 
@@ -963,7 +976,6 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
     const int r = (ty + 1) * TS_RW + tx + 1;
     const uint32_t c = (uint32_t)y * pitch + x;
     R fd[9], gd[5], hd[5];
-    R phi = d.phi_u;
     const bool bx = NEE && !interior && !d.perx && (x == 0 || x == nx - 1);
     const bool by = NEE && !interior && !d.pery && (y == 0 || y == ny - 1);
     if (NEE && (bx || by)) {
@@ -980,38 +992,55 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
           h[i] = to_real<S>(lpop[14 + i][up[i]], is);
         }
       };
-      R unused[4];
-      nee_boundary<S, CP, false>(d, rs, x, y, bx, by, fd, gd, hd, unused, phi, lds_pull);
-    } else {
-    const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
-    const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
-    const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+      R unused[4], phib;
+      nee_boundary<S, CP, false>(d, rs, x, y, bx, by, fd, gd, hd, unused, phib, lds_pull);
+      rs.d4 = fwrite;
+      collide_store<S, CP>(d, rs, c, step + 1u, phib, fd, gd, hd, prev);
+      return;
+    }
     // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
     auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
-    fd[0] = L(0, 0);
-    fd[1] = okxm ? L(1, -1) : L(3, 0);
-    fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
-    fd[3] = okxp ? L(3, 1) : L(1, 0);
-    fd[4] = okyp ? L(4, TS_RW) : L(2, 0);
-    fd[5] = ok5 ? L(5, -TS_RW - 1) : L(7, 0);
-    fd[6] = ok6 ? L(6, -TS_RW + 1) : L(8, 0);
-    fd[7] = ok7 ? L(7, TS_RW + 1) : L(5, 0);
-    fd[8] = ok8 ? L(8, TS_RW - 1) : L(6, 0);
+    if (interior) {
+      // no wall link in the tile: plain pulls
+      const int off[5] = {0, -1, -TS_RW, 1, TS_RW};
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      R *e = q ? hd : gd;
-      const int p = q ? 14 : 9;
-      e[0] = L(p, 0);
-      e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
-      e[2] = okym ? L(p + 2, -TS_RW) : L(p + 4, 0);
-      e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
-      e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
+      for (int i = 0; i < 5; ++i) {
+        fd[i] = L(i, off[i]);
+        gd[i] = L(9 + i, off[i]);
+        hd[i] = L(14 + i, off[i]);
+      }
+      fd[5] = L(5, -TS_RW - 1);
+      fd[6] = L(6, -TS_RW + 1);
+      fd[7] = L(7, TS_RW + 1);
+      fd[8] = L(8, TS_RW - 1);
+    } else {
+      const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
+      const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
+      const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+      fd[0] = L(0, 0);
+      fd[1] = okxm ? L(1, -1) : L(3, 0);
+      fd[2] = okym ? L(2, -TS_RW) : L(4, 0);
+      fd[3] = okxp ? L(3, 1) : L(1, 0);
+      fd[4] = okyp ? L(4, TS_RW) : L(2, 0);
+      fd[5] = ok5 ? L(5, -TS_RW - 1) : L(7, 0);
+      fd[6] = ok6 ? L(6, -TS_RW + 1) : L(8, 0);
+      fd[7] = ok7 ? L(7, TS_RW + 1) : L(5, 0);
+      fd[8] = ok8 ? L(8, TS_RW - 1) : L(6, 0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        R *e = q ? hd : gd;
+        const int p = q ? 14 : 9;
+        e[0] = L(p, 0);
+        e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
+        e[2] = okym ? L(p + 2, -TS_RW) : L(p + 4, 0);
+        e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
+        e[4] = okyp ? L(p + 4, TS_RW) : L(p + 2, 0);
+      }
+      if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
     }
-    if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
-    if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
-    }
+    // the node's porosity and porous coefficients, as step one computed them
     rs.d4 = fwrite;
-    collide_store<S, CP>(d, rs, c, step + 1u, phi, fd, gd, hd, prev);
+    collide_store_ab<S, CP>(d, rs, c, step + 1u, pab[0], pab[1], pab[2], fd, gd, hd, prev);
   }
 }
 
