@@ -978,6 +978,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
     R fd[9], gd[5], hd[5];
     const bool bx = NEE && !interior && !d.perx && (x == 0 || x == nx - 1);
     const bool by = NEE && !interior && !d.pery && (y == 0 || y == ny - 1);
+    auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
     if (NEE && (bx || by)) {
       // the pulls of f and ff from LDS (region node of (PX, PY): PX - x0 + 1, PY - y0 + 1)
       auto lds_pull = [&](int PX, int PY, R *f, R *g, R *h) {
@@ -994,13 +995,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       };
       R unused[4], phib;
       nee_boundary<S, CP, false>(d, rs, x, y, bx, by, fd, gd, hd, unused, phib, lds_pull);
-      rs.d4 = fwrite;
-      collide_store<S, CP>(d, rs, c, step + 1u, phib, fd, gd, hd, prev);
-      return;
-    }
-    // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
-    auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
-    if (interior) {
+    } else if (interior) {
       // no wall link in the tile: plain pulls
       const int off[5] = {0, -1, -TS_RW, 1, TS_RW};
 #pragma unroll
@@ -1014,6 +1009,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       fd[7] = L(7, TS_RW + 1);
       fd[8] = L(8, TS_RW - 1);
     } else {
+      // f_i(x) = f_i*(x - e_i), or the opposite population of this node across a wall
       const bool okxm = (x > 0) | d.perx, okxp = (x < nx - 1) | d.perx;
       const bool okym = (y > 0) | d.pery, okyp = (y < ny - 1) | d.pery;
       const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
@@ -1038,7 +1034,8 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       }
       if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
     }
-    // the node's porosity and porous coefficients, as step one computed them
+    // the node's porosity and porous coefficients, as step one computed them (a boundary
+    // node's too: the rule reads the same porosity)
     rs.d4 = fwrite;
     collide_store_ab<S, CP>(d, rs, c, step + 1u, pab[0], pab[1], pab[2], fd, gd, hd, prev);
   }
