@@ -336,12 +336,15 @@ __device__ __forceinline__ _Float16 from_real(float v, float scale) { return (_F
 // ---------------------------------------------------------------- FP16 stochastic rounding
 // Round-to-nearest binary16 storage stagnates: a population that changes by less than half a
 // binary16 ulp per step never changes at all, which freezes slow diffusion.  The step kernel
-// therefore rounds stochastically: 13 random bits (the bits binary16 drops from a binary32
-// mantissa) are added to the scaled value's bit pattern before a round-toward-zero
-// conversion, so the stored value is unbiased.  The random bits are a function of (node,
-// step) only -- the hash of Jarzynski & Olano, "Hash functions for GPU rendering" (JCGT
-// 2020, PCG-based), seeding Marsaglia's xorshift32 -- so results are reproducible and do
-// not depend on the launch shape or on the other cavities of a batch.
+// therefore rounds stochastically, with the conversion gfx950 provides for it: 13 random
+// bits are added below the binary16 mantissa of the scaled binary32 value, which is then
+// truncated, so the stored value is unbiased (for a binary16 subnormal result the random
+// bits are aligned with the dropped bits; a value of magnitude 65504 or more goes to the
+// infinity the non-finite check looks for, stochastically below 65536).  The instruction
+// takes its 13 random bits from bits 19-31 of its operand.  The random bits are a function
+// of (node, step) only -- the hash of Jarzynski & Olano, "Hash functions for GPU
+// rendering" (JCGT 2020, PCG-based), seeding Marsaglia's xorshift32 -- so results are
+// reproducible and do not depend on the launch shape or on the other cavities of a batch.
 __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
   const uint32_t state = v * 747796405u + 2891336453u;
   const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
@@ -352,6 +355,8 @@ struct Dither {
   uint32_t s, pool;
   int left;
   __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step)) | 1u), pool(0), left(0) {}
+  // 13 fresh random bits in bits 19-31 (two values per xorshift32 draw: its bits 0-12,
+  // then 13-25)
   __device__ __forceinline__ uint32_t next13() {
     if (left == 0) {
       s ^= s << 13;
@@ -360,19 +365,17 @@ struct Dither {
       pool = s;
       left = 2;
     }
-    const uint32_t r = pool & 0x1FFFu;
+    const uint32_t r = pool << 19;
     pool >>= 13;
     --left;
     return r;
   }
 };
 
-__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r13) {
-  // beyond the binary16 range: round to nearest, which gives the infinity the
-  // non-finite check looks for
-  if (!(__builtin_fabsf(v) < 65504.0f)) return (_Float16)v;
-  const float d = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) + r13);
-  return __builtin_amdgcn_cvt_pkrtz(d, 0.0f)[0];
+__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r13_hi) {
+  typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+  half2_t z = {(_Float16)0, (_Float16)0};
+  return __builtin_amdgcn_cvt_sr_f16_f32(z, v, r13_hi, false)[0];
 }
 
 // resources of one cavity for one step
