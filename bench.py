@@ -38,7 +38,7 @@ def parse():
                     help="tile_x,tile_y, 'default' (library rule) or 'auto' (time every tile shape and cache "
                          "policy on the workload before the timed region; default)")
     ap.add_argument("--policy", type=int, default=-1, help="cache policy 0/1/2 with an explicit --tile (-1: rule)")
-    ap.add_argument("--spl", type=int, default=0, help="steps per launch 1/2 with an explicit --tile (0: rule)")
+    ap.add_argument("--spl", type=int, default=0, help="steps per launch 1/2/3 with an explicit --tile (0: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
@@ -87,7 +87,7 @@ def profiled_traffic(prec, n, launch):
     summary for this workload, the kernel code has changed since the counters were taken, or
     the launch shape and cache policy [tile_x, tile_y, policy] differ from the profiled ones."""
     import re
-    kernel = "step2_kernel" if launch[3] == 2 else "step_kernel"
+    kernel = {2: "step2_kernel", 3: "step3_kernel"}.get(launch[3], "step_kernel")
     path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_cavity{n}.md")
     if not os.path.exists(path):
         return None
@@ -468,7 +468,7 @@ def main():
                      "traffic": profiled_traffic(a.precision, a.n, tile_used), "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes * tile_used[3],
                      "bytes_per_lu": BYTES_PER_LU[a.precision], "steps_per_launch": tile_used[3],
-                     "kernel": "step2_kernel" if tile_used[3] == 2 else "step_kernel"},
+                     "kernel": {2: "step2_kernel", 3: "step3_kernel"}.get(tile_used[3], "step_kernel")},
         "wall_s": round(wall, 3),
         "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0],
     }

@@ -213,22 +213,23 @@ Tile default_tile(const lbm_params *p) {
 // accesses, 1 porosity load)
 double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC_FP32 ? 188.0 : 112.0); }
 
-// Steps per launch when none is set: the two-step kernel at every measured size and storage
-// type (where it applies, see two_step_ok).
+// Steps per launch when none is set: three for FP64 storage (2048^2: 25.9 against 23.8 GLUPS
+// with two), two otherwise (FP32: three steps per launch 46.5 against 48.5: the third step's
+// arithmetic, barriers and lower occupancy cost more than the saved traffic); where a count
+// does not apply the next lower one is taken (two_step_ok, three_step_ok).
 int default_spl(int prec, double nodes) {
-  (void)prec;
   (void)nodes;
-  return 2;
+  return prec == PREC_FP64 ? 3 : 2;
 }
 
 // Cache policy when none is set: a step that touches at most 400 MB keeps its data in the
 // 256 MB Infinity Cache between steps for the most part, so plain loads and stores win
-// (CP_RESIDENT); above that the two-step kernel streams with non-temporal stores
+// (CP_RESIDENT); above that the multi-step kernels stream with non-temporal stores
 // (CP_STREAM), and so does the one-step FP32 kernel, while the one-step FP16 and FP64
 // kernels keep their tuned policy (measured on 512^2 to 4096^2 lattices).
 int default_policy(int prec, double nodes, int spl) {
   if (nodes * bytes_per_lu(prec) <= 400e6) return CP_RESIDENT;
-  return (spl == 2 || prec == PREC_FP32) ? CP_STREAM : CP_TUNED;
+  return (spl >= 2 || prec == PREC_FP32) ? CP_STREAM : CP_TUNED;
 }
 
 void map_params(const lbm_params *p, lbm_derived &d) {
@@ -595,9 +596,13 @@ static bool two_step_ok(const lbm_ctx *c) {
   return c->p.nx >= w && c->p.ny >= h;
 }
 
+// The three-step kernel: FP32 and FP64 storage, walls half a spacing outside.
+static bool three_step_ok(const lbm_ctx *c) { return !node_walls(&c->p) && c->prec != PREC_FP16S; }
+
 static int ctx_spl(const lbm_ctx *c) {
   if (!two_step_ok(c)) return 1;
-  return c->steps_per_launch > 0 ? c->steps_per_launch : default_spl(c->prec, (double)c->p.nx * c->p.ny);
+  const int n = c->steps_per_launch > 0 ? c->steps_per_launch : default_spl(c->prec, (double)c->p.nx * c->p.ny);
+  return (n == 3 && !three_step_ok(c)) ? 2 : n;
 }
 
 static int ctx_policy(const lbm_ctx *c) {
@@ -610,7 +615,12 @@ static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   const int spl = ctx_spl(c);
   while (n > 0) {
     set_parity(c, c->cur);
-    if (spl == 2 && n >= 2) {
+    if (spl == 3 && n >= 3) {
+      int e = launch_step3(c->prec, c->desc(), cp, 0, c->stream);
+      if (e) return hip_fail(c, (hipError_t)e, "three-step kernel launch");
+      c->d4cur ^= 1;
+      n -= 3;
+    } else if (spl >= 2 && n >= 2) {
       int e = launch_step2(c->prec, c->desc(), cp, 0, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "two-step kernel launch");
       c->d4cur ^= 1;
@@ -625,12 +635,30 @@ static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   return LBM_OK;
 }
 
-// Graph of graph_chunk steps.  With two steps per launch it holds graph_chunk / 2 launches,
-// each flipping the population and the field buffer; graph_chunk / 2 is taken even (one-step
-// launches otherwise), so a replay ends on the buffers it started from.
+// Steps per launch and steps per replay of the step graph.  A multi-step launch flips the
+// population and the field buffer, a one-step launch the population buffer only; a replay
+// must flip each an even number of times, so that it ends on the buffers it started from:
+// three steps per launch replay the largest multiple of 6 steps in graph_chunk, two steps per
+// launch the whole chunk when it is a multiple of 4; otherwise one step per launch.
+static void graph_plan(const lbm_ctx *c, int *spl, int *steps) {
+  const int n = ctx_spl(c);
+  if (n == 3 && c->graph_chunk >= 6) {
+    *spl = 3;
+    *steps = c->graph_chunk / 6 * 6;
+  } else if (n >= 2 && c->graph_chunk % 4 == 0) {
+    *spl = 2;
+    *steps = c->graph_chunk;
+  } else {
+    *spl = 1;
+    *steps = c->graph_chunk;
+  }
+}
+
+// Graph of one replay (graph_plan): its launches in a fixed order.
 static lbm_status ensure_graph(lbm_ctx *c) {
   const int cp = ctx_policy(c);
-  const int spl = (ctx_spl(c) == 2 && c->graph_chunk % 4 == 0) ? 2 : 1;
+  int spl = 1, gsteps = 0;
+  graph_plan(c, &spl, &gsteps);
   if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty &&
       c->graph_cp == cp && c->graph_d4 == c->d4cur && c->graph_spl == spl)
     return LBM_OK;
@@ -642,9 +670,12 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   const int start = c->cur;
   if (e == hipSuccess) {
     int cur = start, d4 = c->d4cur;
-    for (int k = 0; k < c->graph_chunk / spl && e == hipSuccess; ++k) {
+    for (int k = 0; k < gsteps / spl && e == hipSuccess; ++k) {
       set_parity(c, cur, d4);
-      if (spl == 2) {
+      if (spl == 3) {
+        e = (hipError_t)launch_step3(c->prec, c->desc(), cp, 0, cs);
+        d4 ^= 1;
+      } else if (spl == 2) {
         e = (hipError_t)launch_step2(c->prec, c->desc(), cp, 0, cs);
         d4 ^= 1;
       } else {
@@ -676,12 +707,14 @@ LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   int64_t left = nsteps;
-  if (c->graph_chunk > 0 && left >= c->graph_chunk) {
+  int gspl = 1, gsteps = 0;
+  graph_plan(c, &gspl, &gsteps);
+  if (c->graph_chunk > 0 && left >= gsteps) {
     lbm_status s = ensure_graph(c);
     if (s != LBM_OK) return s;
-    while (left >= c->graph_chunk) {
+    while (left >= gsteps) {
       HIP_CHECK(c, hipGraphLaunch(c->graph, c->stream), "hipGraphLaunch");
-      left -= c->graph_chunk;   // the chunk is even: the current buffer is unchanged
+      left -= gsteps;   // a replay leaves the current buffers unchanged
     }
   }
   lbm_status s = step_plain(c, left);
@@ -867,7 +900,7 @@ LBM_API int32_t lbm_get_cache_policy(const lbm_ctx *c) { return c ? ctx_policy(c
 
 LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
   if (!c) return LBM_EINVAL;
-  if (n < 0 || n > 2) return fail(c, LBM_EINVAL, "steps per launch must be 0 (default), 1 or 2");
+  if (n < 0 || n > 3) return fail(c, LBM_EINVAL, "steps per launch must be 0 (default), 1, 2 or 3");
   c->steps_per_launch = n;
   return LBM_OK;
 }
@@ -906,15 +939,17 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   for (int cp = 0; cp < CP_COUNT; ++cp)
     for (int tx : txs)
       for (int ty : tys) cands.push_back(Cand{1, cp, tx, ty});
-  if (two_step_ok(c))   // the two-step kernel has a fixed tile (64 x 8, FP64 32 x 8)
+  if (two_step_ok(c))   // the multi-step kernels have a fixed tile (64 x 8, FP64 32 x 8)
     for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty});
-  const int nsteps = steps + (steps & 1);
+  if (three_step_ok(c))
+    for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{3, cp, tile0.tx, tile0.ty});
+  const int nsteps = (steps + 5) / 6 * 6;   // whole launches of two and of three steps
   for (const Cand &k : cands) {
     if (e != hipSuccess) break;
     c->tile = Tile{k.tx, k.ty};
     c->cache_policy = k.cp;
     c->steps_per_launch = k.spl;
-    if (step_plain(c, 2) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
+    if (step_plain(c, 6) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
     e = hipEventRecord(t0, c->stream);
     if (e == hipSuccess && step_plain(c, nsteps) != LBM_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = hipEventRecord(t1, c->stream);

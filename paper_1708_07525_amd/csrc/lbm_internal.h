@@ -79,6 +79,9 @@ int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void 
 // written to d4b;
 // cavities without walls through the nodes only
 int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
+// three time steps per launch (tiles with a two-node halo staged in LDS); FP32 and FP64
+// storage, walls half a spacing outside; fields read from d4, written to d4b
+int launch_step3(int prec, const void *desc, int cp, int parity, void *stream);
 // range: device pointer to {first item, item count} of the group to step; parity bit 0
 // selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,

@@ -1058,6 +1058,206 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typenam
   two_step_tile<S, CP, NEE>(d, x0, y0, parity, lpop);
 }
 
+// ---------------------------------------------------------------- three steps per launch
+// One work-group of W x H threads advances a W x H tile by three time steps (storage FP32 or
+// FP64, walls half a spacing outside).  Step one updates the tile and a two-node halo
+// ((W + 4) x (H + 4) nodes, pulled from global memory as in step_node) into LDS; step two
+// updates the tile and the inner halo ring ((W + 2) x (H + 2) nodes) from LDS, in place: every
+// thread first reads the pulls of its nodes, then, after a barrier, writes the results over
+// them; step three pulls the tile from LDS and stores it.  Per node and three steps, global
+// memory sees about one step's loads and one step's stores.  Each node of the region belongs
+// to one thread for all its steps, so its fields and porous coefficients stay in registers:
+// a thread owns its tile node, and at most one node of the inner ring (threads [0, N1)) or
+// of the outer ring (threads [N1, N1 + N2)).  The values kept in LDS are rounded to the
+// storage type as a store and a reload would round them, so the result is bitwise that of
+// three one-step launches.
+template <typename S>
+struct ThreeStep {
+  static constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
+  static constexpr int RW = W + 4, RH = H + 4, RN = RW * RH, THREADS = W * H;
+  static constexpr int N1 = 2 * (W + 2) + 2 * H;        // inner ring
+  static constexpr int N2 = 2 * RW + 2 * (H + 2);       // outer ring
+};
+
+template <typename S, int CP>
+__device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
+                                                S (*lpop)[ThreeStep<S>::RN]) {
+  using R = typename St<S>::R;
+  using FIO = FieldIO<S, CP>;
+  constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H, RW = ThreeStep<S>::RW, RH = ThreeStep<S>::RH;
+  constexpr int N1 = ThreeStep<S>::N1, N2 = ThreeStep<S>::N2;
+  static_assert(N1 + N2 <= ThreeStep<S>::THREADS, "one ring node per thread at most");
+  constexpr uint32_t RS = sizeof(R);
+  const uint32_t PR = (uint32_t)d.plane * RS;
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const int cur = (d.base_parity ^ parity) & 1;
+  StepRes rs = step_resources<S>(d, cur);
+  const rsrc_t fread = make_rsrc((parity & 1) ? d.d4b : d.d4, ND4 * PR);
+  const rsrc_t fwrite = make_rsrc((parity & 1) ? d.d4 : d.d4b, ND4 * PR);
+  rs.d4 = fread;
+  const uint32_t step = d.counter[cur];
+  if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 3u;
+  const R is = d.inv_scale, sc = d.scale;
+  // the region and every node it pulls from lie inside the domain
+  const bool interior = x0 >= 3 && x0 + W + 2 <= nx - 1 && y0 >= 3 && y0 + H + 2 <= ny - 1;
+
+  // domain node of region node (lx, ly), wrapped across periodic sides; false beyond a wall
+  auto locate = [&](int lx, int ly, int &X, int &Y) -> bool {
+    X = x0 - 2 + lx;
+    Y = y0 - 2 + ly;
+    if (interior) return true;
+    if (X < 0 || X >= nx) {
+      if (!d.perx) return false;
+      X = X < 0 ? X + nx : X - nx;
+    }
+    if (Y < 0 || Y >= ny) {
+      if (!d.pery) return false;
+      Y = Y < 0 ? Y + ny : Y - ny;
+    }
+    return true;
+  };
+  auto lds_store = [&](int r, uint32_t c, uint32_t stp, const R *fd, const R *gd, const R *hd) {
+    Dither dz(c, stp);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lpop[i][r] = to_store<S>(fd[i], sc, dz);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lpop[9 + i][r] = to_store<S>(gd[i], sc, dz);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lpop[14 + i][r] = to_store<S>(hd[i], sc, dz);
+  };
+  // step one at region node (lx, ly): populations into LDS, fields into prev, porosity and
+  // porous coefficients into pab
+  auto step_one = [&](int lx, int ly, R *prev, R *pab) {
+    int X, Y;
+    if (!locate(lx, ly, X, Y)) return;     // beyond a wall: never read
+    const uint32_t c = (uint32_t)Y * pitch + X;
+    R fd[9], gd[5], hd[5];
+    R phi = d.phi_u;
+    if (d.phi_field) phi = FIO::ld(rs.phi, c * RS, 0);
+    if (interior) gather_global<S, CP, true>(d, rs, X, Y, fd, gd, hd);
+    else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
+    R a, bb;
+    porous_coeffs(d, phi, a, bb);
+    pab[0] = phi;
+    pab[1] = a;
+    pab[2] = bb;
+    collide(d, phi, a, bb, fd, gd, hd, prev);
+    lds_store(ly * RW + lx, c, step, fd, gd, hd);
+  };
+  // pulls of region node (lx, ly) = domain node (X, Y) from LDS, with the wall rules
+  auto lds_pulls = [&](int lx, int ly, int X, int Y, R *fd, R *gd, R *hd) {
+    const int r = ly * RW + lx;
+    auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
+    if (interior) {
+      const int off[5] = {0, -1, -RW, 1, RW};
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        fd[i] = L(i, off[i]);
+        gd[i] = L(9 + i, off[i]);
+        hd[i] = L(14 + i, off[i]);
+      }
+      fd[5] = L(5, -RW - 1);
+      fd[6] = L(6, -RW + 1);
+      fd[7] = L(7, RW + 1);
+      fd[8] = L(8, RW - 1);
+      return;
+    }
+    const bool okxm = (X > 0) | d.perx, okxp = (X < nx - 1) | d.perx;
+    const bool okym = (Y > 0) | d.pery, okyp = (Y < ny - 1) | d.pery;
+    const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
+    fd[0] = L(0, 0);
+    fd[1] = okxm ? L(1, -1) : L(3, 0);
+    fd[2] = okym ? L(2, -RW) : L(4, 0);
+    fd[3] = okxp ? L(3, 1) : L(1, 0);
+    fd[4] = okyp ? L(4, RW) : L(2, 0);
+    fd[5] = ok5 ? L(5, -RW - 1) : L(7, 0);
+    fd[6] = ok6 ? L(6, -RW + 1) : L(8, 0);
+    fd[7] = ok7 ? L(7, RW + 1) : L(5, 0);
+    fd[8] = ok8 ? L(8, RW - 1) : L(6, 0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      R *e = q ? hd : gd;
+      const int p = q ? 14 : 9;
+      e[0] = L(p, 0);
+      e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
+      e[2] = okym ? L(p + 2, -RW) : L(p + 4, 0);
+      e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
+      e[4] = okyp ? L(p + 4, RW) : L(p + 2, 0);
+    }
+    if (!(okxm & okxp & okym & okyp)) wall_rules(d, okxm, okxp, okym, okyp, fd, gd, hd);
+  };
+
+  const int t = (int)threadIdx.x;
+  const int tx = t % W, ty = t / W;
+  // this thread's ring node: inner ring (rows 1 and RH - 2, then columns 1 and RW - 2), or
+  // outer ring (rows 0 and RH - 1, then columns 0 and RW - 1)
+  int rx = 0, ry = 0;
+  const bool ring1 = t < N1, ring2 = t >= N1 && t < N1 + N2;
+  if (ring1) {
+    if (t < 2 * (W + 2)) {
+      rx = 1 + t % (W + 2);
+      ry = t < W + 2 ? 1 : RH - 2;
+    } else {
+      const int q = t - 2 * (W + 2);
+      rx = q < H ? 1 : RW - 2;
+      ry = 2 + q % H;
+    }
+  } else if (ring2) {
+    const int k = t - N1;
+    if (k < 2 * RW) {
+      rx = k % RW;
+      ry = k < RW ? 0 : RH - 1;
+    } else {
+      const int q = k - 2 * RW;
+      rx = q < H + 2 ? 0 : RW - 1;
+      ry = 1 + q % (H + 2);
+    }
+  }
+
+  // step one: own node, then the ring node
+  R prev[4], pab[3], prev1[4], pab1[3];
+  step_one(tx + 2, ty + 2, prev, pab);
+  if (ring1 || ring2) step_one(rx, ry, prev1, pab1);
+  __syncthreads();
+
+  // step two, in place: read the pulls of the own node and of an inner-ring node, then write.
+  // Every region node step one computed is updated (across a periodic side a ragged tile's
+  // own positions past the edge hold wrapped nodes, which step three pulls from)
+  int X, Y, X1 = 0, Y1 = 0;
+  const bool own_in = locate(tx + 2, ty + 2, X, Y);
+  const bool r1_in = ring1 && locate(rx, ry, X1, Y1);
+  R fd[9], gd[5], hd[5], f1[9], g1[5], h1[5];
+  if (own_in) lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd);
+  if (r1_in) lds_pulls(rx, ry, X1, Y1, f1, g1, h1);
+  __syncthreads();
+  if (own_in) {
+    collide(d, pab[0], pab[1], pab[2], fd, gd, hd, prev);
+    lds_store((ty + 2) * RW + tx + 2, (uint32_t)Y * pitch + X, step + 1u, fd, gd, hd);
+  }
+  if (r1_in) {
+    collide(d, pab1[0], pab1[1], pab1[2], f1, g1, h1, prev1);
+    lds_store(ry * RW + rx, (uint32_t)Y1 * pitch + X1, step + 1u, f1, g1, h1);
+  }
+  __syncthreads();
+
+  // step three: the tile's nodes inside the domain, pulled from LDS, stored to global memory
+  if (x0 + tx < nx && y0 + ty < ny) {
+    lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd);
+    rs.d4 = fwrite;
+    collide_store_ab<S, CP>(d, rs, (uint32_t)Y * pitch + X, step + 2u, pab[0], pab[1], pab[2], fd, gd, hd, prev);
+  }
+}
+
+template <typename S, int CP>
+__global__ void __launch_bounds__(ThreeStep<S>::THREADS) step3_kernel(Desc<typename St<S>::R> d, int ntx,
+                                                                      int parity) {
+  __shared__ S lpop[NPOP][ThreeStep<S>::RN];
+  const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  three_step_tile<S, CP>(d, (b % ntx) * ThreeStep<S>::W, (b / ntx) * ThreeStep<S>::H, parity, lpop);
+}
+
 // Batched two steps over items of W x H tiles (item.tw = W): one item per work-group (a
 // loop over items keeps values live across iterations and costs a third of the occupancy);
 // the grid may exceed the item count, the extra work-groups exit at once.
@@ -1431,6 +1631,34 @@ int launch_step2(int prec, const void *desc, int cp, int parity, void *stream) {
     case PREC_FP64: return step2_t<double>(desc, cp, parity, stream);
     case PREC_FP32: return step2_t<float>(desc, cp, parity, stream);
     default: return step2_t<_Float16>(desc, cp, parity, stream);
+  }
+}
+
+template <typename S>
+static int step3_t(const void *desc, int cp, int parity, void *stream) {
+  const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  hipStream_t s = (hipStream_t)stream;
+  constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H;
+  const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
+  const dim3 grid(ntx * nty), block(ThreeStep<S>::THREADS);
+  switch (cp) {
+    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, d, ntx, parity); break;
+    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, d, ntx, parity); break;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_step3(int prec, const void *desc, int cp, int parity, void *stream) {
+  const auto nee = [&](auto *dp) { return dp->nee != 0; };
+  switch (prec) {
+    case PREC_FP64:
+      if (nee((const Desc<double> *)desc)) return (int)hipErrorInvalidValue;
+      return step3_t<double>(desc, cp, parity, stream);
+    case PREC_FP32:
+      if (nee((const Desc<float> *)desc)) return (int)hipErrorInvalidValue;
+      return step3_t<float>(desc, cp, parity, stream);
+    default: return (int)hipErrorInvalidValue;   // FP16 storage: one or two steps per launch
   }
 }
 

@@ -286,8 +286,10 @@ def test_two_step_kernel_matches_one_step(prec, case):
     on a ragged porosity-field cavity (tiles cut by every side) and on a channel periodic in
     x with a moving lid, each with half-way walls and with walls through the nodes (fixed,
     convective and zero-gradient sides; there the last tiles sit against the far walls and
-    overlap their neighbours); odd step counts leave one single step; with and without
-    graphs.  FP16 storage with walls through the nodes always takes one step per launch."""
+    overlap their neighbours); the three-step kernel (FP32, FP64, half-way walls) too; step
+    counts that are not multiples leave shorter launches; with and without graphs (a replay
+    of 60 steps for three per launch).  FP16 storage with walls through the nodes always
+    takes one step per launch."""
     Solver = _solver()
     if case.endswith("grf_ragged"):
         c = workloads.grf_cavity(seed=5, n=100)
@@ -301,12 +303,17 @@ def test_two_step_kernel_matches_one_step(prec, case):
         T, C = workloads.noise_fields(70, 37, 8)
         kw = dict(T=T, C=C)
     states = {}
-    for spl in (1, 2):
+    for spl in (1, 2, 3):
         for chunk in (0, 64):
             s = Solver(p, precision=prec, **kw)
             s.set_steps_per_launch(spl)
             s.set_graph_chunk(chunk)
-            assert s.get_steps_per_launch() == (1 if prec == "fp16s" and case.startswith("nee") else spl)
+            expect = spl
+            if spl == 3 and (prec == "fp16s" or case.startswith("nee")):
+                expect = 2          # three steps per launch: FP32/FP64, half-way walls
+            if prec == "fp16s" and case.startswith("nee"):
+                expect = 1
+            assert s.get_steps_per_launch() == expect
             s.step(131)
             s.step(70)
             states[(spl, chunk)] = s.get_state()
