@@ -9,18 +9,21 @@
 //   space (Eqs. 10, 13-15), collide g and h in moment space (Eqs. 21-25) with the source
 //   term of Eq. (27) (time derivative: one-step backward difference), and store.
 // Cavities whose walls pass through the boundary nodes (Eqs. 33-37, 39) have their
-// perimeter nodes rebuilt by non-equilibrium extrapolation in work-groups of their own at
-// the front of the same launch (nee_node); the tiles skip those nodes.
+// perimeter nodes rebuilt by non-equilibrium extrapolation: in a one-step launch by
+// work-groups of their own at its front (nee_node, the tiles skip those nodes), in the
+// two-step kernel by the tiles themselves.
 // The 9x9 and 5x5 transforms are written out as sums with the integer / rational
 // coefficients of M, N and their inverses (the inverse of an orthogonal-row matrix is its
 // transpose over the squared row norms 9, 36, 36, 6, 12, 6, 12, 4, 4 and 5, 2, 2, 20, 4).
 // Populations are deviations from the rest state (rho0, T0, C0); all three storage
 // types share this one node function, so results do not depend on the launch shape.
 //
-// The path is bound by HBM bandwidth (19 population loads + 19 stores + 4 + 4 previous-step
-// field accesses + 1 porosity load per node, against ~350 flops), so there is no MFMA and
-// no LDS staging: each population element is read exactly once, by the one node that pulls
-// it, and the +-1 shifted reads of neighbouring tiles hit in L2.
+// One step is bound by HBM bandwidth (19 population loads + 19 stores + 4 + 4 previous-step
+// field accesses + 1 porosity load per node, against ~350 flops), so there is no MFMA.  The
+// one-step kernel reads each population element once, by the one node that pulls it (the
+// +-1 shifted reads of neighbouring tiles hit in L2).  The two- and three-step kernels keep
+// the intermediate steps of a tile and its halo in LDS, so that global memory sees about
+// one step's loads and stores per launch.
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"

@@ -263,7 +263,8 @@ class Solver:
         return int(lib().lbm_get_cache_policy(self._h))
 
     def set_steps_per_launch(self, n: int):
-        """1, 2 (two-step LDS kernel) or 0 for the default (see include/lbm.h)."""
+        """1, 2 (two-step LDS kernel), 3 (three-step LDS kernel) or 0 for the default (see
+        include/lbm.h)."""
         _check(lib().lbm_set_steps_per_launch(self._h, int(n)), self._h, "lbm_set_steps_per_launch")
 
     def get_steps_per_launch(self) -> int:
