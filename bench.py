@@ -483,9 +483,9 @@ def main():
             var[prec] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
                          "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3]}
         out["precisions"] = var
-        # the same cavity with the walls through the boundary nodes (Eqs. 33-37): perimeter
-        # work-groups in the same launch; per-node bytes as above (the perimeter's second
-        # pull is 0.2% of the nodes)
+        # the same cavity with the walls through the boundary nodes (Eqs. 33-37): the boundary
+        # rule inside the tiles (two steps per launch) or perimeter work-groups (one step);
+        # per-node bytes as above (the rule's second pull is 0.2% of the nodes)
         nee = dict(case, params=dict(case["params"], sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
         vms, _, vob, vt = timed_run(nee, a.precision, a.variant_steps, a.warmup, tile)
         v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
@@ -493,6 +493,16 @@ def main():
         out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
                              "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "precision": a.precision,
                              "Nu_hot": vob["Nu"][0]}
+        # the 512^2 Gaussian-random-field cavity (FP32): its 53 MB stay in the 256 MB Infinity
+        # Cache, so its bytes per second are not HBM bandwidth; the HBM roofline is quoted at
+        # 2048^2 only
+        grf = workloads.grf_cavity(seed=1, n=512)
+        gn = 512 * 512
+        vms, _, vob, vt = timed_run(grf, "fp32", 4 * a.variant_steps, a.warmup, tile)
+        v = gn * 4 * a.variant_steps / (vms * 1e-3) / 1e6
+        out["grf512"] = {"MLUPS": round(v, 1), "precision": "fp32", "steps": 4 * a.variant_steps, "tile": vt[:2],
+                         "cache_policy": vt[2], "steps_per_launch": vt[3], "Nu_hot": vob["Nu"][0],
+                         "note": "cache-resident lattice (53 MB): rate is not HBM-bound"}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)
     print(json.dumps(out), flush=True)
