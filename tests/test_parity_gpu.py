@@ -195,6 +195,47 @@ def test_minimum_lattice():
     assert max(e.values()) <= 1e-10, e
 
 
+def test_degenerate_calls_and_smallest_lattices():
+    """Zero steps change nothing; a negative count is refused; an empty batch steps as a no-op;
+    the 3x3 lattice, with walls and periodic in one or both directions, gives the same state
+    bit for bit with one, two and three steps per launch (tiles far wider than the lattice,
+    halo nodes wrapped more than once across a periodic side)."""
+    from paper_1708_07525_amd import Batch
+    from paper_1708_07525_amd.lbm import LbmError
+    Solver = _solver()
+    p = workloads.cavity_params(nx=3, ny=3)
+    s = Solver(p, T=0.5, C=0.5, precision="fp32")
+    s.step(7)
+    before = s.get_state()
+    s.step(0)
+    d = _state_diff(s.get_state(), before)
+    assert d is None, d
+    with pytest.raises(LbmError):
+        s.step(-1)
+    s.close()
+    b = Batch(4, chunk=8)
+    b.step(0)
+    b.step(20)
+    assert len(b) == 0
+    b.close()
+    for sides, g_ext in ((("cold", "hot", "adiabatic", "adiabatic"), (0.0, 0.0)),
+                         (("periodic", "periodic", "cold", "hot"), (0.0, 0.0)),
+                         (("periodic", "periodic", "periodic", "periodic"), (1e-5, 0.0))):
+        for prec in ("fp32", "fp64"):
+            pp = workloads.cavity_params(nx=3, ny=3, sides=sides, g_ext=g_ext)
+            T, C = workloads.noise_fields(3, 3, 9)
+            states = []
+            for spl in (1, 2, 3):
+                sv = Solver(pp, T=T, C=C, precision=prec)
+                sv.set_steps_per_launch(spl)
+                sv.step(61)
+                states.append(sv.get_state())
+                sv.close()
+            for st in states[1:]:
+                d = _state_diff(st, states[0])
+                assert d is None, (sides, prec, d)
+
+
 # ------------------------------------------------------------ pins re-run on the GPU path
 
 def test_gpu_linear_conduction_exact():
