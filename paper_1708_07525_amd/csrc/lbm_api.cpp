@@ -1074,7 +1074,7 @@ lbm_status batch_upload(lbm_batch *b) {
       g.count2 = (int)items2.size() - g.first2;
       g.grid2 = 1;
       while (g.grid2 < g.count2) g.grid2 *= 2;
-      g.cp = default_policy(prec, gnodes, 1);
+      g.cp = default_policy(prec, gnodes, b->chunk % 4 == 0 ? 2 : 1);   // steps per launch as batch_spl
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {
