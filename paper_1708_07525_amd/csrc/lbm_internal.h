@@ -6,8 +6,10 @@
 //           (pitch >= nx, a multiple of 64), planes are `plane` elements apart
 //           (plane >= ny*pitch, padded so that planes do not alias on the same HBM
 //           channels).  Element (x, y) of plane i is at i*plane + y*pitch + x.
-//   d4      4 planes of the fields of the previous step: T, C, ux, uy (FP64 for FP64
-//           storage, FP32 otherwise).  Read and rewritten in place by the node itself.
+//   d4[2]   two buffers of 4 planes, the fields of the previous step: T, C, ux, uy (FP64 for
+//           FP64 storage, FP32 otherwise).  The one-step kernel reads and rewrites the current
+//           one in place (each node its own values); the multi-step kernels read one and write
+//           the other (their halo nodes are read by neighbouring work-groups).
 //   phi     1 plane of porosity (only when the porosity is a field).
 //   snap    4 planes: residual snapshot of T, C, ux, uy.
 //   counter 2 words: the step count, kept beside the state it belongs to (index = buffer).
