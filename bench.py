@@ -416,7 +416,8 @@ def serve(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is in DESIGN.md",
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}): the library has no sharded lattice; "
+              "independent cavities would be placed on GPUs by footprint, one process per GPU",
               file=sys.stderr)
         sys.exit(2)
     import torch
