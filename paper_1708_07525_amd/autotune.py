@@ -3,7 +3,7 @@
 ``lbm_autotune`` (C ABI) times every supported tile shape, cache policy and steps-per-launch
 count of the step kernels
 on a context, keeps the fastest and restores the state it started from.  This module keys the
-winner by GPU, storage precision, lattice size class and porosity kind, stores it in a JSON
+winner by GPU, storage precision, lattice size class, porosity kind and wall family, stores it in a JSON
 file, and applies the cached choice to later contexts of the same class without re-timing.
 Results never depend on the tile shape or the cache policy (the per-node arithmetic is one
 function), only the speed does.
@@ -28,8 +28,9 @@ def size_class(n: int) -> int:
     return c
 
 
-def key(device_name: str, precision: str, nx: int, ny: int, porosity_field: bool) -> str:
-    return f"{device_name}|{precision}|{size_class(nx)}x{size_class(ny)}|{'field' if porosity_field else 'uniform'}"
+def key(device_name: str, precision: str, nx: int, ny: int, porosity_field: bool, node_walls: bool = False) -> str:
+    k = f"{device_name}|{precision}|{size_class(nx)}x{size_class(ny)}|{'field' if porosity_field else 'uniform'}"
+    return k + "|node-walls" if node_walls else k
 
 
 def load(path: str | None = None) -> dict:
@@ -52,11 +53,11 @@ def store(entries: dict, path: str | None = None) -> None:
 
 
 def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: str | None = None,
-         force: bool = False):
-    """Apply the cached tile shape and cache policy for this solver's class, or time all of them
-    and cache the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the
-    cache)."""
-    k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field)
+         force: bool = False, node_walls: bool = False):
+    """Apply the cached tile shape, cache policy and steps per launch for this solver's class
+    (walls through the boundary nodes are a class of their own), or time all of them and cache
+    the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
+    k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field, node_walls)
     entries = load(path)
     if not force and k in entries:
         tx, ty = entries[k]["tile"]

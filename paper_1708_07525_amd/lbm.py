@@ -158,6 +158,15 @@ def make_params(p: dict, precision: str = "fp32") -> Params:
     return s
 
 
+def node_walls(params: dict) -> bool:
+    """True when a side of the problem is a wall through the boundary nodes (side kinds 4-7,
+    by name or number)."""
+    for k in params.get("sides", ()):
+        if (isinstance(k, str) and k.startswith("nee_")) or (not isinstance(k, str) and int(k) >= 4):
+            return True
+    return False
+
+
 def footprint_bytes(p: dict, precision: str = "fp32") -> int:
     s = make_params(p, precision)
     return int(lib().lbm_footprint_bytes(ctypes.byref(s)))
@@ -204,7 +213,8 @@ class Solver:
             _check(lib().lbm_set_fields(self._h, *[_ptr(a) for a in arrs]), self._h, "lbm_set_fields")
             if tile == "auto":
                 from . import autotune
-                autotune.tune(self, torch.cuda.get_device_name(self.device), phi is not None)
+                autotune.tune(self, torch.cuda.get_device_name(self.device), phi is not None,
+                              node_walls=node_walls(params))
             elif tile is not None:
                 self.set_tile(*tile)
 

@@ -52,13 +52,6 @@ class Result:
         return self.finished - self.arrival
 
 
-def node_walls(params: dict) -> bool:
-    """True when a side of the problem is a wall through the boundary nodes (side kinds 4-7,
-    by name or number); such cavities are not batched and advance with their own launches."""
-    for k in params.get("sides", ()):
-        if (isinstance(k, str) and k.startswith("nee_")) or (not isinstance(k, str) and int(k) >= 4):
-            return True
-    return False
 
 
 def converged(ob: dict, tol: float, quiet_speed: float) -> bool:
@@ -98,7 +91,7 @@ class Server:
         if len(self.active) >= self.max_slots or self.used + need > self.budget:
             return False
         s = self.be.Solver(req.params, phi=req.phi, T=req.T, C=req.C, precision=req.precision)
-        if node_walls(req.params):
+        if _lbm.node_walls(req.params):
             self.solo.add(id(s))           # walls through the nodes: stepped on its own
         else:
             self.batch.attach(s)

@@ -34,6 +34,7 @@ class FakeSolver:
 def test_size_class_and_key():
     assert [autotune.size_class(n) for n in (1, 3, 64, 65, 2048)] == [1, 4, 64, 128, 2048]
     assert autotune.key("MI355X", "fp32", 100, 200, True) == "MI355X|fp32|128x256|field"
+    assert autotune.key("MI355X", "fp32", 100, 200, True, node_walls=True) == "MI355X|fp32|128x256|field|node-walls"
 
 
 def test_tune_times_once_per_class(tmp_path):
@@ -57,3 +58,12 @@ def test_corrupt_cache_is_ignored(tmp_path):
     s = FakeSolver(64, 64)
     autotune.tune(s, "gpu", True, path=str(path))
     assert s.timed == 1 and autotune.load(str(path))
+
+
+def test_wall_families_are_tuned_apart(tmp_path):
+    path = str(tmp_path / "cache.json")
+    a = FakeSolver(100, 100)
+    autotune.tune(a, "gpu", False, path=path)
+    b = FakeSolver(100, 100)
+    autotune.tune(b, "gpu", False, path=path, node_walls=True)
+    assert a.timed == 1 and b.timed == 1 and len(autotune.load(path)) == 2

@@ -151,7 +151,7 @@ def test_chunk_must_divide_check_interval():
 def test_node_wall_cavities_step_beside_the_batch():
     """A cavity with walls through the boundary nodes is never attached to the batch; it is
     stepped by itself each chunk and stops at the same step as when served alone."""
-    from paper_1708_07525_amd.serving import node_walls
+    from paper_1708_07525_amd.lbm import node_walls
     assert node_walls(dict(sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
     assert node_walls(dict(sides=(4, 5, 6, 6)))
     assert not node_walls(dict(sides=("hot", "cold", "adiabatic", "periodic")))
