@@ -31,12 +31,13 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32", "fp16s"))
     ap.add_argument("--n", type=int, default=2048, help="lattice side")
     ap.add_argument("--variant-steps", type=int, default=2000,
-                    help="steps for the FP64 and FP16-storage side measurements (0: skip)")
+                    help="steps for the side measurements: FP64 and FP16 storage, walls through the "
+                         "nodes, and (4x the steps) the 512^2 porosity-field cavity (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="auto",
-                    help="tile_x,tile_y, 'default' (library rule) or 'auto' (time every tile shape and cache "
-                         "policy on the workload before the timed region; default)")
+                    help="tile_x,tile_y, 'default' (library rule) or 'auto' (time every tile shape, cache "
+                         "policy and steps per launch on the workload before the timed region; default)")
     ap.add_argument("--policy", type=int, default=-1, help="cache policy 0/1/2 with an explicit --tile (-1: rule)")
     ap.add_argument("--spl", type=int, default=0, help="steps per launch 1/2/3 with an explicit --tile (0: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
