@@ -474,6 +474,13 @@ def main():
         "wall_s": round(wall, 3),
         "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0],
     }
+    # the measured HBM traffic of a launch (rocprofv3 counters, when they match this kernel and
+    # launch) over the launch's time from the timed region: the real bandwidth the kernel draws
+    tr = out["roofline"]["traffic"]
+    if tr is not None:
+        launch_s = ms * 1e-3 / a.steps * tile_used[3]
+        out["roofline"]["traffic_GB_s"] = round(tr / launch_s / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(tr / launch_s / 1e9 / PEAK_HBM_GBS, 4)
     if a.variant_steps > 0:
         var = {}
         for prec in ("fp64", "fp32", "fp16s"):
