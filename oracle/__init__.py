@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
         "nee_hot": 4, "nee_cold": 5, "nee_adiabatic": 6, "nee_robin": 7}
 MUTATION = {"none": 0, "no_source": 1, "no_half_force": 2, "rho_in_meq": 3, "buoy_sign": 4,
-            "model_a_diff": 5, "no_forch": 6, "wall_const": 7}
+            "model_a_diff": 5, "no_forch": 6, "wall_const": 7, "ergun_exp": 8, "wall_vel": 9,
+            "model_a_map": 10}
 
 # Section 4 constants: rho0 = J = sigma = 1, varpi = 2/5 (here: automatic, see varpi),
 # s_rho = s_j = 1, s_e = s_eps = 1.1, s_q = 1.2, zeta0 = eta0 = 1, zeta_e,eps = eta_e,eps = 1.5.
@@ -34,6 +35,7 @@ DEFAULTS = dict(
     Th=1.0, Tl=0.0, Ch=1.0, Cl=0.0,
     Fphi=-1.0, g_ext=(0.0, 0.0), wall_u=(0.0, 0.0, 0.0, 0.0),
     direct=0, nu=0.0, alpha_e=0.0, D_e=0.0, K=0.0, gbT=0.0, gbC=0.0, Bi_T=0.0, Bi_C=0.0,
+    Re=0.0, Gr=0.0, U0=0.0,
 )
 
 
@@ -55,6 +57,7 @@ class _Params(ctypes.Structure):
         ("nu", ctypes.c_double), ("alpha_e", ctypes.c_double), ("D_e", ctypes.c_double),
         ("K", ctypes.c_double), ("gbT", ctypes.c_double), ("gbC", ctypes.c_double),
         ("Bi_T", ctypes.c_double), ("Bi_C", ctypes.c_double),
+        ("Re", ctypes.c_double), ("Gr", ctypes.c_double), ("U0", ctypes.c_double),
     ]
 
 
@@ -101,6 +104,7 @@ def lib():
         L.orc_ngeq.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int, _D]
         L.orc_source5.argtypes = [ctypes.c_double] * 3 + [_D]
         L.orc_velocity.argtypes = [ctypes.c_double] * 4 + [_D, _D]
+        L.orc_node_coeffs.argtypes = [ctypes.c_void_p, ctypes.c_long, _D]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
@@ -186,6 +190,13 @@ class Oracle:
         d = _Derived()
         lib().orc_derived_values(self._h, ctypes.byref(d))
         return {n: getattr(d, n) for n, _ in _Derived._fields_}
+
+    def node_coeffs(self, x: int, y: int) -> dict:
+        """Porous coefficients at node (x, y): K, F_phi (Eq. 7) and l0, l1 (Eq. 19)."""
+        out = np.empty(4)
+        if lib().orc_node_coeffs(self._h, int(y) * self.nx + int(x), _ptr(out)) != 0:
+            raise ValueError("orc_node_coeffs failed")
+        return dict(zip(("K", "Fphi", "l0", "l1"), out.tolist()))
 
     def populations(self):
         nn = self.nx * self.ny

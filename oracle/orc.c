@@ -272,7 +272,21 @@ static int derive(orc *o) {
   o->T0 = 0.5 * (p->Th + p->Tl);
   o->dC = p->Ch - p->Cl;
   o->C0 = 0.5 * (p->Ch + p->Cl);
-  if (p->direct) {
+  if (p->direct == 2) {
+    /* section 4.3, mixed convection in a lid-driven cavity: Re = U0 L/nu, so that
+       1/s_v = 1/2 + J L U0/(c_s^2 Re); Gr = g beta_T dT L^3/nu^2; Pr = nu/alpha_e,
+       Le = alpha_e/D_e, Da = K/L^2 and N = beta_C dC/(beta_T dT) as in section 2 */
+    if (!(o->dT > 0) || !(o->dC > 0) || !(p->Re > 0) || !(p->Gr >= 0) || !(p->U0 > 0) || !(p->Pr > 0) ||
+        !(p->Le > 0) || !(p->Da > 0))
+      return -1;
+    o->U = p->U0;
+    o->nu = p->U0 * o->L / p->Re;
+    o->alpha_e = o->nu / p->Pr;
+    o->D_e = o->alpha_e / p->Le;
+    o->K_mean = p->Da * o->L * o->L;
+    o->gbT = p->Gr * o->nu * o->nu / (o->L * o->L * o->L * o->dT);
+    o->gbC = p->N * o->gbT * o->dT / o->dC;
+  } else if (p->direct) {
     o->nu = p->nu;
     o->alpha_e = p->alpha_e;
     o->D_e = p->D_e;
@@ -301,7 +315,7 @@ static int derive(orc *o) {
   o->phi_min = pmin;
   o->varpi = p->varpi > 0 ? p->varpi : (pmin < 0.4 ? pmin : 0.4);
   o->csT2 = 0.5 * o->varpi;
-  int coupled = (p->model == 1) || (p->mutation == ORC_MUT_MODEL_A_DIFF);
+  int coupled = (p->model == 1 && p->mutation != ORC_MUT_MODEL_A_MAP) || (p->mutation == ORC_MUT_MODEL_A_DIFF);
   if (!coupled) {
     o->zeta_a = 1.0 / (0.5 + o->alpha_e / o->csT2);   /* Eq. (29) */
     o->eta_D = 1.0 / (0.5 + o->D_e / o->csT2);
@@ -350,7 +364,8 @@ int orc_set_fields(orc *o, const double *phi, const double *T, const double *C,
   }
   for (long k = 0; k < nn; ++k) {
     double q = o->phi[k];
-    o->Fphi[k] = p->Fphi >= 0 ? p->Fphi : 1.75 / sqrt(150.0 * q * q * q);   /* Eq. (7) */
+    const double q3 = p->mutation == ORC_MUT_ERGUN_EXP ? q * q : q * q * q;
+    o->Fphi[k] = p->Fphi >= 0 ? p->Fphi : 1.75 / sqrt(150.0 * q3);   /* Eq. (7) */
   }
   /* initial populations: Eq. (20) with rho = rho0 and Eq. (28) */
   for (long k = 0; k < nn; ++k) {
@@ -380,6 +395,14 @@ typedef struct {
   double rho, T, C, ux, uy, Gx, Gy, Fx, Fy;
 } node_macro;
 
+/* Darcy and Forchheimer coefficients of Eq. (5) at node k: a = phi nu/K, b = phi F_phi/sqrt(K) */
+static void porous_ab(const orc *o, long k, double *a, double *b) {
+  const double phi = o->phi[k];
+  *a = phi * o->nu / o->K[k];
+  *b = phi * o->Fphi[k] / sqrt(o->K[k]);
+  if (o->p.mutation == ORC_MUT_NO_FORCH) *b = 0.0;
+}
+
 static void node_fields(const orc *o, long k, node_macro *q) {
   const orc_params *p = &o->p;
   long nn = o->nn;
@@ -400,9 +423,8 @@ static void node_fields(const orc *o, long k, node_macro *q) {
   double buoy = o->gbT * (T - o->T0) + o->gbC * (C - o->C0);   /* Eq. (6) */
   if (p->mutation == ORC_MUT_BUOY_SIGN) buoy = -buoy;
   double Gx = p->g_ext[0], Gy = p->g_ext[1] + buoy;
-  double a = phi * o->nu / o->K[k];                  /* Darcy coefficient of Eq. (5) */
-  double b = phi * o->Fphi[k] / sqrt(o->K[k]);       /* Forchheimer coefficient of Eq. (5) */
-  if (p->mutation == ORC_MUT_NO_FORCH) b = 0.0;
+  double a, b;
+  porous_ab(o, k, &a, &b);
   double ux, uy;
   if (p->mutation == ORC_MUT_NO_HALF_FORCE) {
     ux = jx / p->rho0;
@@ -517,7 +539,8 @@ static void stream_node(orc *o, int x, int y) {
       double uwx = 0, uwy = 0;
       if (outy) uwx = p->wall_u[sy < 0 ? ORC_BOTTOM : ORC_TOP];
       else uwy = p->wall_u[sx < 0 ? ORC_LEFT : ORC_RIGHT];
-      o->f[i * nn + k] = o->fs[OPP[i] * nn + k] + 2.0 * W9[i] * p->rho0 * (EX[i] * uwx + EY[i] * uwy) / cs2;
+      const double mw = p->mutation == ORC_MUT_WALL_VEL ? 1.0 : 2.0;
+      o->f[i * nn + k] = o->fs[OPP[i] * nn + k] + mw * W9[i] * p->rho0 * (EX[i] * uwx + EY[i] * uwy) / cs2;
     } else {
       o->f[i * nn + k] = o->fs[i * nn + (long)sy * nx + sx];
     }
@@ -656,11 +679,14 @@ static void apply_nee(orc *o) {
 int orc_step(orc *o, int64_t nsteps) {
   if (!o || !o->ready) return -1;
   const int nx = o->nx, ny = o->ny;
+  /* threads only pay off on lattices large enough to amortise the fork and barrier of a
+     parallel loop; tiny lattices (the pins) stay on one thread */
+  const int par = (long)nx * ny >= 16384;
   for (int64_t s = 0; s < nsteps; ++s) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) collide_node(o, (long)y * nx + x);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) stream_node(o, x, y);
     if (o->nee) apply_nee(o);
@@ -812,6 +838,17 @@ int orc_derived_values(const orc *o, orc_derived *d) {
   d->varpi = o->varpi; d->csT2 = o->csT2; d->gbT = o->gbT; d->gbC = o->gbC;
   d->T0 = o->T0; d->C0 = o->C0; d->dT = o->dT; d->dC = o->dC; d->K_mean = o->K_mean;
   d->phi_min = o->phi_min;
+  return 0;
+}
+
+int orc_node_coeffs(const orc *o, long k, double *out) {
+  if (!o || !o->ready || k < 0 || k >= o->nn || !out) return -1;
+  double a, b;
+  porous_ab(o, k, &a, &b);
+  out[0] = o->K[k];
+  out[1] = o->Fphi[k];
+  out[2] = 0.5 * (1.0 + 0.5 * a);   /* Eq. (19), delta_t = 1 */
+  out[3] = 0.5 * b;
   return 0;
 }
 

@@ -40,7 +40,10 @@ enum {
   ORC_MUT_BUOY_SIGN = 4,      /* flip the sign of the buoyancy of Eq. (6)               */
   ORC_MUT_MODEL_A_DIFF = 5,   /* present equilibria but Model-A diffusivity mapping     */
   ORC_MUT_NO_FORCH = 6,       /* drop the Forchheimer term of Eq. (5)                   */
-  ORC_MUT_WALL_CONST = 7      /* anti-bounce-back constant w_i*T_w instead of 2*w_i*T_w */
+  ORC_MUT_WALL_CONST = 7,     /* anti-bounce-back constant w_i*T_w instead of 2*w_i*T_w */
+  ORC_MUT_ERGUN_EXP = 8,      /* phi^2 instead of phi^3 under the root of Eq. (7)       */
+  ORC_MUT_WALL_VEL = 9,       /* moving-wall term of the bounce-back halved             */
+  ORC_MUT_MODEL_A_MAP = 10    /* Model-A equilibria with the present diffusivity mapping */
 };
 
 typedef struct orc_params {
@@ -58,10 +61,13 @@ typedef struct orc_params {
   double g_ext[2];            /* extra constant body acceleration added to G */
   double wall_u[4];           /* tangential velocity of each side (moving lid) */
   int32_t direct;             /* 0: map Ra, Pr, Le, Da, N, Ma to lattice units as in section 4.1;
-                                 1: take the lattice values below as given */
+                                 1: take the lattice values below as given;
+                                 2: lid-driven mixed convection of section 4.3: map Re, Gr, U0
+                                    (with Pr, Le, Da, N) */
   double nu, alpha_e, D_e, K, gbT, gbC;  /* lattice viscosity, diffusivities, mean permeability,
                                             g*beta_T and g*beta_C, used when direct == 1 */
   double Bi_T, Bi_C;          /* Biot numbers of a convective side (Eq. 39); ambient Tl, Cl */
+  double Re, Gr, U0;          /* Reynolds and Grashof numbers and the lid speed (direct == 2) */
 } orc_params;
 
 typedef struct orc orc;
@@ -103,6 +109,9 @@ void orc_force_moments(double ux, double uy, double Fx, double Fy, double phi, d
 void orc_geq(double T, double ux, double uy, double cap, double varpi, int model, double *geq5);
 void orc_ngeq(double T, double ux, double uy, double cap, double varpi, int model, double *neq5);
 void orc_source5(double ax, double ay, double varpi, double *S5tilde);
+/* porous coefficients at node k (valid after orc_set_fields): out = {K, F_phi, l0, l1} with
+   l0 = (1 + phi nu/(2K))/2 and l1 = phi F_phi/(2 sqrt K) of Eq. (19) */
+int orc_node_coeffs(const orc *o, long k, double *out4);
 /* one velocity solve, Eqs. (18)-(19): v in, u out */
 void orc_velocity(double vx, double vy, double l0, double l1, double *ux, double *uy);
 int orc_threads(void);

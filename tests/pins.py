@@ -49,7 +49,8 @@ def brinkman_poiseuille(make, nx, J=2.0, nu=0.05, K16=50.0, phi=0.7, G=1e-5, ste
     return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
 
 
-def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G=(6e-4, 2e-3), **extra):
+def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G=(6e-4, 2e-3), Fphi_ref=None,
+                          **extra):
     """A fully periodic, spatially uniform state under a constant acceleration G.  Then
     streaming is the identity and the momentum obeys the trapezoidal recurrence
     u^{n+1} - F(u^{n+1})/2 = u^n + F(u^n)/2 with F(u) = -a u - b|u|u + phi G, a = phi nu/K,
@@ -57,13 +58,14 @@ def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G
     by Newton's method.  Its fixed point F = 0 is the Darcy-Forchheimer velocity
     |u| = (-a + sqrt(a^2 + 4 b phi|G|))/(2b).
     Returns (max recurrence error over ``steps`` steps, |u| after 20000 more steps, the
-    closed-form |u|)."""
+    closed-form |u|).  ``Fphi_ref`` is the Forchheimer coefficient of the reference when the
+    solver is given Fphi < 0 (the Ergun form of Eq. 7)."""
     p = dict(nx=3, ny=3, sides=PERIODIC, direct=1, nu=nu, alpha_e=0.1, D_e=0.1, K=K, gbT=0.0,
              gbC=0.0, Fphi=Fphi, phi=phi, g_ext=tuple(G))
     p.update(extra)
     s = make(p, T=0.5, C=0.5)
     a = phi * nu / K
-    b = phi * Fphi / np.sqrt(K)
+    b = phi * (Fphi if Fphi_ref is None else Fphi_ref) / np.sqrt(K)
     Gv = np.array(G, dtype=float)
 
     def force(u):
@@ -287,3 +289,37 @@ def nee_poiseuille(make, nx, J=2.0, nu=0.05, K16=50.0, phi=0.7, G=1e-5, steps=No
     r = np.sqrt(phi * nu / (J * nu * K))
     ua = (G * K / nu) * (1.0 - np.cosh(r * (x - W / 2.0)) / np.cosh(r * W / 2.0))
     return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
+
+
+def couette(make, ny=16, U=0.01, phi=0.7, nu=0.1, steps=20000, **extra):
+    """Plane Couette flow: x periodic, a no-slip bottom wall at y = -1/2 and a top wall at
+    y = ny - 1/2 moving with U (the moving-wall term of the half-way bounce-back), no force
+    and no drag.  The steady profile is linear, u_x = U (y + 1/2)/ny, and the scheme is exact
+    for it.  Returns max |u_x - exact| / U and max |u_y|."""
+    p = dict(nx=3, ny=ny, sides=("periodic", "periodic", "adiabatic", "adiabatic"), wall_u=(0.0, 0.0, 0.0, U),
+             phi=phi, nu=nu, alpha_e=0.1, D_e=0.1, K=1e30, **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    exact = U * (np.arange(ny) + 0.5) / ny
+    return float(np.abs(F["ux"] - exact[:, None]).max() / U), float(np.abs(F["uy"]).max())
+
+
+def layered_darcy(make, nx=80, ny=3, phis=(0.4, 0.8), K_mean=1.0, nu=0.05, G=1e-5, steps=3000, **extra):
+    """Flow along two porous layers (x < nx/2 and x >= nx/2, periodic in x and y), driven by a
+    constant acceleration G along y, without Forchheimer term.  Far from the interface each
+    layer carries the Darcy velocity u = G K/nu of its own permeability (Eq. 5 with the
+    Brinkman term negligible: the layers are 20 Brinkman lengths wide or more).  Returns, per
+    layer, the measured velocity at its centre over G K/nu - 1 with K(phi) from the
+    Kozeny-Carman form of Eq. (7) scaled so that its mean over the lattice is K_mean."""
+    phi = np.where(np.arange(nx) < nx // 2, phis[0], phis[1])[None, :].repeat(ny, 0)
+    p = dict(nx=nx, ny=ny, sides=PERIODIC, direct=1, nu=nu, alpha_e=0.1, D_e=0.1, K=K_mean, gbT=0.0,
+             gbC=0.0, Fphi=0.0, phi=0.6, g_ext=(0.0, G))
+    p.update(extra)
+    s = make(p, phi=phi, T=0.5, C=0.5)
+    s.step(steps)
+    u = s.fields()["uy"][ny // 2]
+    kc = [q ** 3 / (1 - q) ** 2 for q in phis]
+    mean = (kc[0] + kc[1]) / 2
+    return [float(u[xc] / (G * K_mean * k / mean / nu) - 1.0) for xc, k in ((nx // 4, kc[0]), (3 * nx // 4, kc[1]))]

@@ -147,6 +147,34 @@ def test_parameter_mapping_small_cavity():
     assert CS2 * (1 / d["s_v"] - 0.5) == pytest.approx(d["nu_e"], rel=1e-12)
     assert d["csT2"] * (1 / d["zeta_a"] - 0.5) == pytest.approx(d["alpha_e"], rel=1e-12)
     assert d["csT2"] * (1 / d["eta_D"] - 0.5) == pytest.approx(d["D_e"], rel=1e-12)
+    # Eq. (7) (Ergun, F_phi = 1.75/sqrt(150 phi^3)) and the coefficients of Eq. (19) at a node,
+    # worked out by hand: F_phi(0.6) = 0.307444, l0 = (1 + phi nu/(2K))/2 = 0.500135,
+    # l1 = phi F_phi/(2 sqrt K) = 0.014411
+    c = o.node_coeffs(17, 40)
+    assert c["K"] == pytest.approx(40.96, rel=1e-12)
+    assert c["Fphi"] == pytest.approx(0.307444, rel=2e-6)
+    assert c["l0"] == pytest.approx(0.500135, rel=2e-6)
+    assert c["l1"] == pytest.approx(0.014411, rel=3e-5)
+
+
+def test_lid_driven_mapping():
+    """Section 4.3 (mixed convection, lid-driven cavity, Table 4 case): 128^2, Re = 100, U0 = 0.1,
+    Gr = 100, Pr = Le = 1, Da = 0.1, N = -500, J = 1.  By hand: nu = U0 L/Re = 0.128,
+    1/s_v = 1/2 + J L U0/(c_s^2 Re) = 0.884, g beta_T dT = Gr nu^2/L^3 = 7.8125e-7, K = Da L^2 =
+    1638.4, zeta_alpha = 1/(1/2 + alpha_e/c_sT^2) = 1/1.14 (varpi = 0.4).  The groups come back
+    from the lattice values."""
+    p = dict(nx=128, ny=128, sides=("adiabatic", "adiabatic", "cold", "hot"), direct=2, Re=100.0, Gr=100.0,
+             U0=0.1, Pr=1.0, Le=1.0, Da=0.1, N=-500.0, phi=0.95, wall_u=(0.0, 0.0, 0.0, 0.1))
+    d = Oracle(p, T=0.5, C=0.5).derived()
+    hand = dict(nu=0.128, s_v=1 / 0.884, gbT=7.8125e-7, gbC=-500 * 7.8125e-7, K_mean=1638.4, zeta_a=1 / 1.14,
+                eta_D=1 / 1.14, alpha_e=0.128)
+    for k, v in hand.items():
+        assert d[k] == pytest.approx(v, rel=1e-12), k
+    L = 128
+    assert 0.1 * L / d["nu"] == pytest.approx(100.0, rel=1e-12)
+    assert d["gbT"] * d["dT"] * L ** 3 / d["nu"] ** 2 == pytest.approx(100.0, rel=1e-12)
+    with pytest.raises(ValueError):
+        Oracle(dict(p, Re=0.0), T=0.5, C=0.5)
 
 
 def test_varpi_follows_the_smallest_porosity():
@@ -192,6 +220,39 @@ def test_uniform_force_recurrence_and_darcy_forchheimer_limit():
     err, got, closed = pins.uniform_force_history(make_oracle)
     assert err < 1e-14
     assert got == pytest.approx(closed, rel=1e-12)
+
+
+def test_ergun_forchheimer_coefficient_in_the_force():
+    """The Ergun form of Eq. (7) used by the force of Eq. (5): the uniform-force recurrence and
+    its Darcy-Forchheimer limit with F_phi(0.6) = 0.30744366, a value worked out by hand to 8
+    digits (so the bars are 1e-8 of the velocity, about 0.27 here)."""
+    err, got, closed = pins.uniform_force_history(make_oracle, phi=0.6, Fphi=-1.0, Fphi_ref=0.30744366,
+                                                  G=(3e-3, 4e-3))
+    assert err < 1e-8 * got
+    assert got == pytest.approx(closed, rel=1e-8)
+
+
+def test_couette_flow_is_exact():
+    """The moving-wall term of the half-way bounce-back, 2 w_i rho0 e_i.u_w/c_s^2: plane Couette
+    flow has the exact linear profile."""
+    e, uy = pins.couette(make_oracle)
+    assert e < 1e-11 and uy < 1e-13
+
+
+@pytest.mark.parametrize("which,kw", [("T", dict(sigma=3.0)), ("C", dict(phi=0.5))])
+def test_model_a_diffusivity(which, kw):
+    """Model-A (Eqs. 30-32): with its coupled equilibria the diffusivity is alpha_e =
+    sigma c_sT^2 (1/zeta_alpha - 1/2) (Eq. 32), and a T mode decays at alpha_e k^2/sigma (a C
+    mode at D_e k^2/phi) when zeta_alpha is mapped by Eq. (32)."""
+    assert abs(pins.sine_decay(make_oracle, which=which, model=1, **kw)) < 2e-3
+
+
+def test_heterogeneous_permeability_gives_layer_darcy_velocities():
+    """A porosity field sets K(x) by the Kozeny-Carman form of Eq. (7) (scaled to the mean
+    permeability): two layers driven along their interface each carry the Darcy velocity
+    G K(phi)/nu of their own porosity."""
+    errs = pins.layered_darcy(make_oracle)
+    assert max(abs(e) for e in errs) < 1e-5, errs
 
 
 @pytest.mark.parametrize("sigma", [1.0, 3.0])
@@ -350,6 +411,24 @@ def test_mutation_model_a_diffusivity_is_caught():
 def test_mutation_wall_constant_is_caught():
     eT, _, _, _ = pins.conduction_profile(make_mutant("wall_const"))
     assert eT > 1e-2
+
+
+def test_mutation_ergun_exponent_is_caught():
+    c = make_mutant("ergun_exp")(dict(nx=64, ny=64), T=0.5, C=0.5).node_coeffs(17, 40)
+    assert abs(c["Fphi"] / 0.307444 - 1) > 0.1
+    err, got, closed = pins.uniform_force_history(make_mutant("ergun_exp"), phi=0.6, Fphi=-1.0,
+                                                  Fphi_ref=0.30744366, G=(3e-3, 4e-3))
+    assert abs(got / closed - 1) > 1e-3
+
+
+def test_mutation_moving_wall_term_is_caught():
+    e, _ = pins.couette(make_mutant("wall_vel"))
+    assert e > 0.1
+
+
+def test_mutation_model_a_mapping_is_caught():
+    assert abs(pins.sine_decay(make_mutant("model_a_map"), which="T", model=1, sigma=3.0)) > 0.5
+    assert abs(pins.sine_decay(make_mutant("model_a_map"), which="C", model=1, phi=0.5)) > 0.3
 
 
 # ---------------------------------------------------------------- the paper's Table 1

@@ -144,3 +144,19 @@ def request_stream(count: int = 10000, seed: int = 4, rate: float = 1.0,
 
 def lattice_updates(nx: int, ny: int, steps: int) -> int:
     return int(nx) * int(ny) * int(steps)
+
+
+def sample_nodes(nx: int, ny: int, count: int = 2048, seed: int = 12345):
+    """``count`` distinct lattice nodes drawn uniformly without replacement (seeded), as
+    (x, y) integer arrays: the nodes at which a stored reference keeps its fields."""
+    rng = np.random.default_rng(seed)
+    k = rng.choice(nx * ny, size=min(count, nx * ny), replace=False)
+    k.sort()
+    return (k % nx).astype(np.int64), (k // nx).astype(np.int64)
+
+
+def band_rows(ny: int, nbands: int = 8):
+    """Row index ranges [start, stop) of ``nbands`` horizontal bands (the last takes any
+    remainder), as used by ``band_porosity``."""
+    rows = np.minimum(np.arange(ny) * nbands // ny, nbands - 1)
+    return [(int(np.flatnonzero(rows == b)[0]), int(np.flatnonzero(rows == b)[-1]) + 1) for b in range(nbands)]
