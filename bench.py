@@ -17,10 +17,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per lattice update: 19 population loads + 19 stores, 4 + 4 previous-step
-# field accesses, 1 porosity load (the porosity is a field here)
+# algorithmic bytes of one node of one launch: the populations and fields of the level the
+# launch starts from are read once (19 populations, 4 previous-step fields, 1 porosity) and
+# those of the level it ends on are written once (19 + 4); a launch that advances k steps keeps
+# the k - 1 levels in between on chip, so the bytes it must move do not grow with k.  For one
+# step per launch this is the per-lattice-update figure (188 B in FP32).
 BYTES_PER_LU = {"fp64": 19 * 8 * 2 + 4 * 8 * 2 + 8, "fp32": 19 * 4 * 2 + 4 * 4 * 2 + 4,
                 "fp16s": 19 * 2 * 2 + 4 * 4 * 2 + 4}
+
+
+def roofline_fields(prec, nodes, ms_per_step, spl):
+    """Bandwidth of a launch against the HBM peak: ``achieved`` is the bytes a launch must move
+    (BYTES_PER_LU per node) over the average launch time (ms_per_step x steps per launch), so
+    frac <= 1 whatever the steps per launch; ``effective_per_step`` counts BYTES_PER_LU per
+    node and step instead (the bandwidth a one-step kernel would need for the same rate, above
+    the peak when a launch advances several steps)."""
+    launch_s = ms_per_step * 1e-3 * spl
+    ach = BYTES_PER_LU[prec] * nodes / launch_s / 1e9
+    return {"achieved": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
+            "effective_per_step_GB_s": round(ach * spl, 1),
+            "effective_per_step_frac": round(ach * spl / PEAK_HBM_GBS, 4), "launch_us": round(launch_s * 1e6, 2)}
 
 
 def parse():
@@ -43,7 +59,10 @@ def parse():
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
-                         "precision: FP64/FP32/FP16-storage errors on the 512^2 and 2048^2 cavities")
+                         "precision: FP64/FP32/FP16-storage errors against the FP64 oracle on the 512^2 and "
+                         "2048^2 cavities")
+    ap.add_argument("--precision-case", default="all", choices=("all", "grf512", "band2048"),
+                    help="precision: which workload")
     ap.add_argument("--cavities", type=int, default=256, help="sweep: number of cavities")
     ap.add_argument("--until-converged", action="store_true",
                     help="sweep: run every cavity to steady state (residual 1e-8) or --max-steps, "
@@ -52,9 +71,6 @@ def parse():
     ap.add_argument("--max-steps", type=int, default=0,
                     help="step cap per solve (serve: default 20000; sweep --until-converged: 100000)")
     ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
-    ap.add_argument("--stream-probe", action="store_true",
-                    help="instead of the solver, time the step kernel's memory access pattern without its "
-                         "arithmetic (FP32, aligned and with the pull shifts) on the same lattice")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -109,26 +125,6 @@ def kernel_code_hash():
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
     return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
-
-
-def stream_probe(n, reps=200):
-    import ctypes
-    import torch
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1708_07525_amd", "libstreamprobe.so"))
-    lib.stream_probe_run.restype = ctypes.c_double
-    lib.stream_probe_run.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int] * 6
-    pitch = (n + 63) // 64 * 64
-    plane = (pitch * n + 1023) // 1024 * 1024 + 256
-    src = torch.zeros(19 * plane, device="cuda")
-    dst = torch.zeros(19 * plane, device="cuda")
-    d4 = torch.zeros(4 * plane, device="cuda")
-    phi = torch.full((plane,), 0.5, device="cuda")
-    out = {"stream_probe": f"{n}x{n} FP32, 19+4 planes read and written, 1 plane read"}
-    for mode, name in ((0, "aligned"), (1, "pull_shifted"), (2, "pull_shifted_blocked64")):
-        ms = lib.stream_probe_run(src.data_ptr(), dst.data_ptr(), d4.data_ptr(), phi.data_ptr(), n, n, pitch, plane,
-                                  mode, reps)
-        out[name] = {"ms": ms, "GB_s": round(BYTES_PER_LU["fp32"] * n * n / (ms * 1e-3) / 1e9, 1)}
-    print(json.dumps(out), flush=True)
 
 
 def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0):
@@ -260,51 +256,63 @@ def sweep(a):
 
 
 def precision_report(a):
-    """The 512^2 Gaussian-random-field cavity (50000 steps) and the 2048^2 banded cavity
-    (20000 steps) run with FP64, FP32 and FP16 storage.  The FP64 GPU path, itself held to
-    1e-10 of the FP64 oracle by the parity tests, is the reference here (the oracle would
-    need 8.4e10 node updates on the host for the large case).  Reports MLUPS, the HBM
-    roofline fraction, the largest field errors and the Nu/Sh errors at the hot wall."""
+    """The 512^2 Gaussian-random-field cavity (50000 steps) and the 2048^2 banded cavity (20000
+    steps), run on the GPU with FP64, FP32 and FP16 storage and compared with the FP64 CPU
+    oracle's result after the same steps (tests/golden/precision_<case>.json, written by
+    tests/golden/precision_reference.py from the oracle alone): Nu and Sh at both held sides,
+    the fields at the 2048 seeded sample nodes the reference keeps (relative to the largest
+    |T|, |C| and speed over the lattice; rho absolute), and the band means of T and C.  Also
+    MLUPS and the HBM roofline fraction of each run."""
     import torch
     import workloads
     from paper_1708_07525_amd import Solver
 
-    def errs(F, R):
-        speed = float(np.hypot(R["ux"], R["uy"]).max())
-        e = {k: float(np.abs(F[k] - R[k]).max() / np.abs(R[k]).max()) for k in ("T", "C")}
-        e.update({k: float(np.abs(F[k] - R[k]).max() / speed) for k in ("ux", "uy")})
-        e["rho"] = float(np.abs(F["rho"] - R["rho"]).max())
-        return e
-
-    out = {"metric": "field and Nu/Sh error by storage precision (reference: FP64 GPU path)", "data": "synthetic",
+    golden = os.path.join(ROOT, "tests", "golden")
+    cases = [("grf512", workloads.grf_cavity(seed=1, n=512)), ("band2048", workloads.band_cavity(seed=2, n=2048))]
+    if a.precision_case != "all":
+        cases = [c for c in cases if c[0] == a.precision_case]
+    out = {"metric": "field and Nu/Sh error by storage precision against the FP64 CPU oracle", "data": "synthetic",
            "cases": []}
-    for case, steps in ((workloads.grf_cavity(seed=1, n=512), a.steps if a.steps != 20000 else 50000),
-                        (workloads.band_cavity(seed=2, n=2048), 20000)):
+    for name, case in cases:
+        path = os.path.join(golden, f"precision_{name}.json")
+        if not os.path.exists(path):
+            raise SystemExit(f"{path} is missing: write it with tests/golden/precision_reference.py {name}")
+        ref = json.load(open(path))
+        steps = ref["steps"]
         n = case["params"]["nx"]
-        res = {}
+        xs, ys = np.array(ref["samples"]["x"]), np.array(ref["samples"]["y"])
+        rob = ref["observables"]
+        c = {"case": case["name"], "steps": steps, "reference": f"FP64 oracle ({os.path.basename(path)})",
+             "oracle_Nu": rob["Nu"][:2], "oracle_Sh": rob["Sh"][:2]}
         for prec in ("fp64", "fp32", "fp16s"):
             s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec)
+            s.step(2)                               # first launches and graph capture
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.step(steps)
+            s.step(steps - 2)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ob = s.observables()
-            res[prec] = (s.fields(), ob, n * n * steps / dt / 1e6)
+            F = s.fields()
+            spl = s.get_steps_per_launch()
             s.close()
-        ref_F, ref_ob, _ = res["fp64"]
-        c = {"case": case["name"], "steps": steps}
-        for prec, (F, ob, ml) in res.items():
-            gbs = BYTES_PER_LU[prec] * ml * 1e6 / 1e9
-            row = {"MLUPS": round(ml, 1), "GB_s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                   "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0]}
-            if prec != "fp64":
-                row["field_err"] = errs(F, ref_F)
-                row["Nu_rel_err"] = abs(ob["Nu"][0] - ref_ob["Nu"][0]) / abs(ref_ob["Nu"][0])
-                row["Sh_rel_err"] = abs(ob["Sh"][0] - ref_ob["Sh"][0]) / abs(ref_ob["Sh"][0])
+            ml = n * n * (steps - 2) / dt / 1e6
+            rf = roofline_fields(prec, n * n, dt * 1e3 / (steps - 2), spl)
+            fm = ref["field_max"]
+            err = {k: float(np.abs(F[k][ys, xs] - np.array(ref["samples"][k])).max() / fm[k]) for k in ("T", "C")}
+            err.update({k: float(np.abs(F[k][ys, xs] - np.array(ref["samples"][k])).max() / fm["speed"])
+                        for k in ("ux", "uy")})
+            err["rho"] = float(np.abs(F["rho"][ys, xs] - np.array(ref["samples"]["rho"])).max())
+            band = {k: float(max(abs(F[k][lo:hi].mean() - m) for (lo, hi), m in zip(ref["band_rows"], ref["band_mean"][k])))
+                    for k in ("T", "C")}
+            row = {"MLUPS": round(ml, 1), "frac": rf["frac"], "effective_per_step_frac": rf["effective_per_step_frac"],
+                   "steps_per_launch": spl, "Nu": ob["Nu"][:2], "Sh": ob["Sh"][:2],
+                   "Nu_rel_err": [abs(ob["Nu"][i] - rob["Nu"][i]) / abs(rob["Nu"][i]) for i in (0, 1)],
+                   "Sh_rel_err": [abs(ob["Sh"][i] - rob["Sh"][i]) / abs(rob["Sh"][i]) for i in (0, 1)],
+                   "sample_field_err": err, "band_mean_abs_err": band}
             c[prec] = row
+            print(json.dumps({"case": name, prec: row}), flush=True)
         out["cases"].append(c)
-        print(json.dumps(c), flush=True)
     print(json.dumps(out), flush=True)
 
 
@@ -428,9 +436,6 @@ def main():
     if a.copy_probe:
         copy_probe(a.copy_probe)
         return
-    if a.stream_probe:
-        stream_probe(a.n)
-        return
     if a.workload == "sweep":
         sweep(a)
         return
@@ -446,7 +451,9 @@ def main():
     ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile,
                                         a.policy if a.policy >= 0 else None, a.spl)
     mlups = nodes * a.steps / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_LU[a.precision] * nodes / (ms * 1e-3 / a.steps) / 1e9
+    spl = tile_used[3]
+    rf = roofline_fields(a.precision, nodes, ms / a.steps, spl)
+    kernel = {2: "step2_kernel", 3: "step3_kernel"}.get(spl, "step_kernel")
     out = {
         "metric": "MLUPS (D2Q9+2xD2Q5) & % HBM roofline; batched p50/p99 solve latency",
         "value": round(mlups, 1),
@@ -465,12 +472,14 @@ def main():
                    "nx": a.n, "ny": a.n, "precision": a.precision, "tile": tile_used[:2],
                    "cache_policy": tile_used[2], "steps_per_launch": tile_used[3],
                    "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": rf["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": rf["frac"],
                      "traffic": profiled_traffic(a.precision, a.n, tile_used), "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes * tile_used[3],
-                     "bytes_per_lu": BYTES_PER_LU[a.precision], "steps_per_launch": tile_used[3],
-                     "kernel": {2: "step2_kernel", 3: "step3_kernel"}.get(tile_used[3], "step_kernel")},
+                     "kernel": kernel, "steps_per_launch": spl, "launch_us": rf["launch_us"],
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU[a.precision] * nodes,
+                     "bytes_per_node_and_launch": BYTES_PER_LU[a.precision],
+                     "effective_per_step_GB_s": rf["effective_per_step_GB_s"],
+                     "effective_per_step_frac": rf["effective_per_step_frac"]},
         "wall_s": round(wall, 3),
         "Nu_hot": ob["Nu"][0], "Sh_hot": ob["Sh"][0],
     }
@@ -478,7 +487,7 @@ def main():
     # launch) over the launch's time from the timed region: the real bandwidth the kernel draws
     tr = out["roofline"]["traffic"]
     if tr is not None:
-        launch_s = ms * 1e-3 / a.steps * tile_used[3]
+        launch_s = rf["launch_us"] * 1e-6
         out["roofline"]["traffic_GB_s"] = round(tr / launch_s / 1e9, 1)
         out["roofline"]["traffic_frac"] = round(tr / launch_s / 1e9 / PEAK_HBM_GBS, 4)
     if a.variant_steps > 0:
@@ -488,9 +497,10 @@ def main():
                 continue
             vms, _, vob, vt = timed_run(case, prec, a.variant_steps, a.warmup, tile)
             v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
-            ach = BYTES_PER_LU[prec] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
-            var[prec] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                         "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3]}
+            vr = roofline_fields(prec, nodes, vms / a.variant_steps, vt[3])
+            var[prec] = {"MLUPS": round(v, 1), "GB_s": vr["achieved"], "frac": vr["frac"],
+                         "effective_per_step_frac": vr["effective_per_step_frac"], "steps": a.variant_steps,
+                         "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3]}
         out["precisions"] = var
         # the same cavity with the walls through the boundary nodes (Eqs. 33-37): the boundary
         # rule inside the tiles (two steps per launch) or perimeter work-groups (one step);
@@ -498,10 +508,11 @@ def main():
         nee = dict(case, params=dict(case["params"], sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
         vms, _, vob, vt = timed_run(nee, a.precision, a.variant_steps, a.warmup, tile)
         v = nodes * a.variant_steps / (vms * 1e-3) / 1e6
-        ach = BYTES_PER_LU[a.precision] * nodes / (vms * 1e-3 / a.variant_steps) / 1e9
-        out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4),
-                             "steps": a.variant_steps, "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "precision": a.precision,
-                             "Nu_hot": vob["Nu"][0]}
+        vr = roofline_fields(a.precision, nodes, vms / a.variant_steps, vt[3])
+        out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": vr["achieved"], "frac": vr["frac"],
+                             "effective_per_step_frac": vr["effective_per_step_frac"], "steps": a.variant_steps,
+                             "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3],
+                             "precision": a.precision, "Nu_hot": vob["Nu"][0]}
         # the 512^2 Gaussian-random-field cavity (FP32): its 53 MB stay in the 256 MB Infinity
         # Cache, so its bytes per second are not HBM bandwidth; the HBM roofline is quoted at
         # 2048^2 only

@@ -55,8 +55,9 @@ typedef enum lbm_status {
 /* Storage of the populations.  Arithmetic is FP64 for LBM_FP64 and FP32 otherwise.
  * Populations are stored as deviations from the rest state at (rho0, T0, C0): f_i - w_i rho0,
  * g_i - g_i^eq(T0, 0), h_i - h_i^eq(C0, 0).  LBM_FP16S stores them in IEEE binary16 with a
- * power-of-two pre-scale (round to nearest even); the previous-step fields (T, C, u) used by
- * the source term of Eq. (27) stay FP32. */
+ * power-of-two pre-scale, rounded stochastically (unbiased; the random bits are a function of
+ * node and step, so results are reproducible); the previous-step fields (T - T0, C - C0, u)
+ * used by the source term of Eq. (27) stay FP32. */
 typedef enum lbm_precision { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
 
 /* Kind of a side of the rectangle.
@@ -101,10 +102,17 @@ typedef struct lbm_params {
   double Fphi;                /* < 0: Ergun, Eq. (7); >= 0: this Forchheimer coefficient  */
   double g_ext[2];            /* constant acceleration added to G of Eq. (6)              */
   double wall_u[4];           /* tangential velocity of each side (moving lid)           */
-  int32_t direct;             /* 1: take nu, alpha_e, D_e, K, gbT, gbC below as lattice values
-                                 instead of mapping Ra, Pr, Le, Da, N, Ma                 */
+  int32_t direct;             /* how the groups map to lattice units:
+                                 0: natural convection (section 4.1): Ra, Pr, Le, Da, N, Ma
+                                    with U = Ma c_s = sqrt(g beta_T dT L), nu = U L sqrt(Pr/Ra);
+                                 1: take nu, alpha_e, D_e, K, gbT, gbC below as lattice values;
+                                 2: lid-driven mixed convection (section 4.3): Re, Gr, U0 below
+                                    with Pr, Le, Da, N: nu = U0 L/Re (1/s_v = 1/2 + J L U0/(c_s^2
+                                    Re)), g beta_T dT = Gr nu^2/L^3.  The moving side's speed is
+                                    wall_u (U0 for the lid), set separately                  */
   double nu, alpha_e, D_e, K, gbT, gbC;
   double Bi_T, Bi_C;          /* Biot numbers of a NEE_ROBIN side (Eq. 39)                 */
+  double Re, Gr, U0;          /* Reynolds and Grashof numbers, lid speed (direct == 2)     */
   void *stream;               /* hipStream_t for all work of the context (NULL: null stream) */
   void *arena;                /* optional device memory for every buffer of the context   */
   uint64_t arena_bytes;       /* size of arena; must be >= lbm_footprint_bytes()          */
@@ -138,7 +146,8 @@ lbm_status lbm_set_fields(struct lbm_ctx *c, const double *phi, const double *T,
                           const double *ux, const double *uy);
 
 /* Advances nsteps >= 0 time steps (asynchronous, stream-ordered).  LBM_ESTATE before
- * lbm_set_fields or while the context is attached to a batch. */
+ * lbm_set_fields, while the context is attached to a batch, or after lbm_observables has
+ * reported LBM_EUNSTABLE (until lbm_set_fields or lbm_set_state gives it a new state). */
 lbm_status lbm_step(struct lbm_ctx *c, int64_t nsteps);
 
 typedef struct lbm_obs {
@@ -169,6 +178,11 @@ typedef struct lbm_derived {
   double gbT, gbC, T0, C0, dT, dC, K_mean, phi_min, fp16_scale;
 } lbm_derived;
 lbm_status lbm_get_derived(const struct lbm_ctx *c, lbm_derived *out);
+
+/* The same lattice values computed on the host alone, for the uniform porosity p->phi (the
+ * mapping of sections 2, 4.1 and 4.3 and Eqs. 29/32; no device is touched).  LBM_EINVAL for
+ * the parameters lbm_create would refuse, or a derived rate outside (0, 2). */
+lbm_status lbm_derive(const lbm_params *p, lbm_derived *out);
 
 /* Checkpoint: the complete state (populations, previous-step fields, residual snapshot,
  * step counter).  lbm_state_bytes gives the size; lbm_get_state copies it to host memory,

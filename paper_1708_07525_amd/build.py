@@ -12,9 +12,6 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_api.cpp"]
-# bandwidth-ceiling probe of the step kernel's access pattern, used by bench.py only
-PROBE_LIB = os.path.join(HERE, "libstreamprobe.so")
-PROBE_SOURCE = "stream_probe.hip"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -43,12 +40,6 @@ def build(verbose: bool = False, extra_flags=()) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    tmp = PROBE_LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-shared", "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

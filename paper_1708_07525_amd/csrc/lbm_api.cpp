@@ -84,6 +84,7 @@ struct lbm_ctx {
   char *base = nullptr;      // device memory (arena or owned)
   bool owned = false;
   bool ready = false;
+  bool unstable = false;     // lbm_observables found a non-finite value: lbm_step refuses to go on
   bool in_batch = false;
   int cur = 0;               // buffer holding the post-collision state of the current level
   int d4cur = 0;             // field buffer (d4 or d4b) holding the fields of the current level
@@ -96,7 +97,7 @@ struct lbm_ctx {
   bool phi_field = false;
   Desc<double> d64{};
   Desc<float> d32{};
-  double wallT[4]{}, wallC[4]{};
+  double wallT[4]{}, wallC[4]{};   // wall T and C minus T0, C0, per side
   std::string err;
   // graph of kGraphChunk steps, valid for `graph_cur` and `graph_tile`
   hipGraphExec_t graph = nullptr;
@@ -180,7 +181,13 @@ lbm_status validate(const lbm_params *p, std::string &msg) {
                           p->eta0, p->eta_e, p->eta_eps};
   for (double r : rates)
     if (!rate_ok(r)) return bad("free relaxation rates must lie in (0, 2)");
-  if (p->direct) {
+  if (p->direct < 0 || p->direct > 2) return bad("direct must be 0 (natural convection), 1 (lattice values) or 2 "
+                                                  "(lid-driven mixed convection)");
+  if (p->direct == 2) {
+    if (!(p->Re > 0) || !(p->Gr >= 0) || !(p->U0 > 0) || !(p->Pr > 0) || !(p->Le > 0) || !(p->Da > 0))
+      return bad("Re, U0, Pr, Le and Da must be positive and Gr >= 0");
+    if (!(p->Th - p->Tl > 0) || !(p->Ch - p->Cl > 0)) return bad("Th > Tl and Ch > Cl are required");
+  } else if (p->direct) {
     if (!(p->nu > 0) || !(p->alpha_e > 0) || !(p->D_e > 0) || !(p->K > 0))
       return bad("direct lattice values nu, alpha_e, D_e, K must be positive");
   } else {
@@ -239,7 +246,17 @@ void map_params(const lbm_params *p, lbm_derived &d) {
   d.T0 = 0.5 * (p->Th + p->Tl);
   d.dC = p->Ch - p->Cl;
   d.C0 = 0.5 * (p->Ch + p->Cl);
-  if (p->direct) {
+  if (p->direct == 2) {
+    // section 4.3, mixed convection in a lid-driven cavity: Re = U0 L/nu, i.e.
+    // 1/s_v = 1/2 + J L U0/(c_s^2 Re); Gr = g beta_T dT L^3/nu^2; Pr, Le, Da, N as above
+    d.U = p->U0;
+    d.nu = p->U0 * d.L / p->Re;
+    d.alpha_e = d.nu / p->Pr;
+    d.D_e = d.alpha_e / p->Le;
+    d.K_mean = p->Da * d.L * d.L;
+    d.gbT = p->Gr * d.nu * d.nu / (d.L * d.L * d.L * d.dT);
+    d.gbC = p->N * d.gbT * d.dT / d.dC;
+  } else if (p->direct) {
     d.nu = p->nu;
     d.alpha_e = p->alpha_e;
     d.D_e = p->D_e;
@@ -261,10 +278,10 @@ void map_params(const lbm_params *p, lbm_derived &d) {
   d.s_v = 1.0 / (0.5 + d.nu_e / kCs2);
 }
 
-// Everything that needs varpi (known once the porosity field is).
-lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
-  const lbm_params *p = &c->p;
-  lbm_derived &d = c->dv;
+// The relaxation rates and model parameter that need varpi, known once the smallest porosity
+// is: Eq. (29) (present model) or Eq. (32) (Model-A) with c_sT^2 = varpi/2; and the FP16
+// pre-scale.  Returns a message on an out-of-range rate.
+const char *derive_rates(const lbm_params *p, int prec, double phi_min, lbm_derived &d) {
   d.phi_min = phi_min;
   d.varpi = p->varpi > 0 ? p->varpi : std::min(0.4, phi_min);
   d.csT2 = 0.5 * d.varpi;
@@ -275,18 +292,26 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     d.zeta_a = 1.0 / (0.5 + d.alpha_e / (p->sigma * d.csT2));  // Eq. (32)
     d.eta_D = 1.0 / (0.5 + d.D_e / (p->phi * d.csT2));
   }
-  if (!rate_ok(d.s_v)) return fail(c, LBM_EINVAL, "derived s_v = %g outside (0, 2)", d.s_v);
-  if (!rate_ok(d.zeta_a)) return fail(c, LBM_EINVAL, "derived zeta_alpha = %g outside (0, 2)", d.zeta_a);
-  if (!rate_ok(d.eta_D)) return fail(c, LBM_EINVAL, "derived eta_D = %g outside (0, 2)", d.eta_D);
-  if (p->varpi > phi_min)
-    c->err = "note: varpi exceeds the smallest porosity; the concentration scheme may be unstable";
-
   // FP16 pre-scale: a power of two that keeps deviations of size up to 16x the wall
   // contrast inside the binary16 range
   double B = 0.5;
   B = std::max(B, std::max(p->sigma, 1.0) * std::max(std::fabs(p->Th - d.T0), std::fabs(p->Tl - d.T0)));
   B = std::max(B, std::max(std::fabs(p->Ch - d.C0), std::fabs(p->Cl - d.C0)));
-  d.fp16_scale = c->prec == PREC_FP16S ? std::ldexp(1.0, (int)std::floor(std::log2(4096.0 / B))) : 1.0;
+  d.fp16_scale = prec == PREC_FP16S ? std::ldexp(1.0, (int)std::floor(std::log2(4096.0 / B))) : 1.0;
+  if (!rate_ok(d.s_v)) return "derived s_v outside (0, 2)";
+  if (!rate_ok(d.zeta_a)) return "derived zeta_alpha outside (0, 2)";
+  if (!rate_ok(d.eta_D)) return "derived eta_D outside (0, 2)";
+  return nullptr;
+}
+
+// Everything that needs varpi (known once the porosity field is).
+lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
+  const lbm_params *p = &c->p;
+  lbm_derived &d = c->dv;
+  if (const char *m = derive_rates(p, c->prec, phi_min, d))
+    return fail(c, LBM_EINVAL, "%s (s_v = %g, zeta_alpha = %g, eta_D = %g)", m, d.s_v, d.zeta_a, d.eta_D);
+  if (p->varpi > phi_min)
+    c->err = "note: varpi exceeds the smallest porosity; the concentration scheme may be unstable";
 
   // fill both descriptor types from FP64 values
   auto fill = [&](auto &D) {
@@ -376,8 +401,9 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
   fill(c->d32);
   for (int s = 0; s < 4; ++s) {
     const bool hot = p->side[s] == SIDE_HOT || p->side[s] == SIDE_NEE_HOT;
-    c->wallT[s] = hot ? p->Th : p->Tl;
-    c->wallC[s] = hot ? p->Ch : p->Cl;
+    // wall values minus T0, C0: the wall-gradient stencils act on the stored deviations
+    c->wallT[s] = (hot ? p->Th : p->Tl) - d.T0;
+    c->wallC[s] = (hot ? p->Ch : p->Cl) - d.C0;
   }
   return LBM_OK;
 }
@@ -451,6 +477,17 @@ LBM_API void lbm_params_default(lbm_params *p) {
 LBM_API uint64_t lbm_footprint_bytes(const lbm_params *p) {
   if (!p || p->nx < 3 || p->ny < 3 || p->precision < 0 || p->precision > 2) return 0;
   return plan_layout(p->nx, p->ny, p->precision).total;
+}
+
+LBM_API lbm_status lbm_derive(const lbm_params *p, lbm_derived *out) {
+  if (!p || !out) return LBM_EINVAL;
+  std::string msg;
+  if (validate(p, msg) != LBM_OK) return LBM_EINVAL;
+  lbm_derived d{};
+  map_params(p, d);
+  if (derive_rates(p, p->precision, p->phi, d)) return LBM_EINVAL;
+  *out = d;
+  return LBM_OK;
 }
 
 LBM_API lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
@@ -576,6 +613,7 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   c->step = 0;
   c->snap_step = 0;
   c->ready = true;
+  c->unstable = false;
   return LBM_OK;
 }
 
@@ -706,6 +744,9 @@ LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (c->unstable)
+    return fail(c, LBM_ESTATE, "the fields hold a non-finite value (reported at step %lld); restart with "
+                "lbm_set_fields or restore a state with lbm_set_state", (long long)c->step);
   int64_t left = nsteps;
   int gspl = 1, gsteps = 0;
   graph_plan(c, &gspl, &gsteps);
@@ -777,7 +818,10 @@ LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
     out->Sh[s] = r[16 + s];
   }
   c->snap_step = c->step;
-  if (out->nonfinite) return fail(c, LBM_EUNSTABLE, "non-finite value in the fields at step %lld", (long long)c->step);
+  if (out->nonfinite) {
+    c->unstable = true;
+    return fail(c, LBM_EUNSTABLE, "non-finite value in the fields at step %lld", (long long)c->step);
+  }
   return LBM_OK;
 }
 
@@ -810,7 +854,7 @@ LBM_API lbm_status lbm_get_state(lbm_ctx *c, void *host, uint64_t bytes) {
   if (!c->ready) return fail(c, LBM_ESTATE, "no state before lbm_set_fields");
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h{};
-  std::memcpy(h.magic, "LBMDDPS2", 8);
+  std::memcpy(h.magic, "LBMDDPS3", 8);
   h.nx = c->p.nx;
   h.ny = c->p.ny;
   h.precision = c->prec;
@@ -839,7 +883,7 @@ LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h;
   std::memcpy(&h, host, sizeof h);
-  if (std::memcmp(h.magic, "LBMDDPS2", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
+  if (std::memcmp(h.magic, "LBMDDPS3", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
     return fail(c, LBM_EINVAL, "state does not match this context");
   const char *src = (const char *)host + sizeof h;
   drop_graph(c);
@@ -855,6 +899,7 @@ LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   HIP_CHECK(c, hipStreamSynchronize(c->stream), "state sync");
   c->step = h.step;
   c->snap_step = h.snap_step;
+  c->unstable = false;
   return LBM_OK;
 }
 
@@ -1226,6 +1271,7 @@ LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   if (!b || !c) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "attach before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context already in a batch");
+  if (c->unstable) return fail(c, LBM_ESTATE, "the fields hold a non-finite value");
   if ((int)b->ctx.size() >= b->cap) return fail(c, LBM_ENOMEM, "batch is full");
   if (node_walls(&c->p)) return fail(c, LBM_EINVAL, "walls through the boundary nodes are not batched");
   // make prior work of the context visible to the batch stream

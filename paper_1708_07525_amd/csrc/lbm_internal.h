@@ -6,12 +6,12 @@
 //           (pitch >= nx, a multiple of 64), planes are `plane` elements apart
 //           (plane >= ny*pitch, padded so that planes do not alias on the same HBM
 //           channels).  Element (x, y) of plane i is at i*plane + y*pitch + x.
-//   d4[2]   two buffers of 4 planes, the fields of the previous step: T, C, ux, uy (FP64 for
-//           FP64 storage, FP32 otherwise).  The one-step kernel reads and rewrites the current
+//   d4[2]   two buffers of 4 planes, the fields of the previous step: T - T0, C - C0, ux, uy
+//           (FP64 for FP64 storage, FP32 otherwise).  The one-step kernel reads and rewrites the current
 //           one in place (each node its own values); the multi-step kernels read one and write
 //           the other (their halo nodes are read by neighbouring work-groups).
 //   phi     1 plane of porosity (only when the porosity is a field).
-//   snap    4 planes: residual snapshot of T, C, ux, uy.
+//   snap    4 planes: residual snapshot of T - T0, C - C0, ux, uy.
 //   counter 2 words: the step count, kept beside the state it belongs to (index = buffer).
 //   Populations are stored as deviations from the rest state (rho0, T0, C0).
 #pragma once
@@ -37,7 +37,7 @@ struct Desc {
   int kind[4];
   int base_parity, pad_[3];
   void *pop0, *pop1;       // population buffers (storage type)
-  void *d4;                // fields T, C, ux, uy of the current level (type R)
+  void *d4;                // fields T - T0, C - C0, ux, uy of the current level (type R)
   void *d4b;               // the other field buffer (written by the two-step kernel)
   void *phi;               // porosity plane (type R), when phi_field
   unsigned *counter;       // step counters [2]: counter[cur] is the step count of the state in

@@ -68,8 +68,8 @@ __device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
 
 // ---------------------------------------------------------------- collision of one node
 // Inputs: the pulled deviations fd[9], gd[5], hd[5]; node porosity; the previous-step
-// fields (T, C, ux, uy) in prev[4].  Outputs: post-collision deviations (in place) and the
-// fields of this level in prev[4].
+// fields (T - T0, C - C0, ux, uy) in prev[4].  Outputs: post-collision deviations (in place)
+// and the fields of this level in prev[4], in the same form.
 template <typename R>
 __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd, R *gd, R *hd, R *prev) {
   const R one = R(1), half = R(0.5);
@@ -84,7 +84,6 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R inv_phi = d.phi_field ? one / phi : d.inv_phi_u;
   const R dT = sg * d.inv_sigma;          // T - T0
   const R dC = sh * inv_phi;              // C - C0
-  const R T = d.T0 + dT, C = d.C0 + dC;
   // buoyancy (Eq. 6) plus any constant acceleration.  Both products are rounded before the
   // sum (no fused multiply-add), so that equal and opposite thermal and solutal terms cancel
   // exactly, as they do in Eq. (6)
@@ -168,10 +167,15 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   fd[0] = drho - ((fd[1] + fd[2]) + (fd[3] + fd[4])) - ((fd[5] + fd[6]) + (fd[7] + fd[8]));
 
   // ---- D2Q5 for T (Eq. 21) and C (Eq. 22)
-  // source moments N S~ = (0, d(T ux)/dt, d(T uy)/dt, 0, 0) from Eq. (27)
-  const R TuX = T * ux, TuY = T * uy, CuX = C * ux, CuY = C * uy;
-  const R STx = TuX - prev[0] * prev[2], STy = TuY - prev[0] * prev[3];
-  const R SCx = CuX - prev[1] * prev[2], SCy = CuY - prev[1] * prev[3];
+  // equilibrium fluxes T u, C u (Eqs. 24-25), formed as T0 u + (T - T0) u so that the rounding
+  // of T itself does not enter; source moments N S~ = (0, d(T ux)/dt, d(T uy)/dt, 0, 0) from
+  // Eq. (27) with d(T u)/dt = T0 (u - u_prev) + ((T - T0) u - (T - T0)_prev u_prev): the
+  // difference of two nearly equal products T u is never formed
+  const R TuX = d.T0 * ux + dT * ux, TuY = d.T0 * uy + dT * uy;
+  const R CuX = d.C0 * ux + dC * ux, CuY = d.C0 * uy + dC * uy;
+  const R dux = ux - prev[2], duy = uy - prev[3];
+  const R STx = d.T0 * dux + (dT * ux - prev[0] * prev[2]), STy = d.T0 * duy + (dT * uy - prev[0] * prev[3]);
+  const R SCx = d.C0 * dux + (dC * ux - prev[1] * prev[2]), SCy = d.C0 * duy + (dC * uy - prev[1] * prev[3]);
   const R kh3 = !d.phi_field ? d.kh3_u : (d.model == 0 ? (d.c5v - R(4) * phi) : (d.c5v - R(4)) * phi);
   {
     const R n0 = sg;
@@ -206,8 +210,8 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
     hd[4] = b0 - b2 + b3 - b4;
     hd[0] = n0 - ((hd[1] + hd[2]) + (hd[3] + hd[4]));
   }
-  prev[0] = T;
-  prev[1] = C;
+  prev[0] = dT;
+  prev[1] = dC;
   prev[2] = ux;
   prev[3] = uy;
 }
@@ -1358,8 +1362,8 @@ __global__ void __launch_bounds__(256) init_kernel(Desc<typename St<S>::R> d, co
     gd[i] = (R)(0.25 * varpi * capT * dT + 0.5 * T * eu);
     hd[i] = (R)(0.25 * varpi * capC * dC + 0.5 * C * eu);
   }
-  prev[0] = (R)T;
-  prev[1] = (R)C;
+  prev[0] = (R)dT;
+  prev[1] = (R)dC;
   prev[2] = (R)ux;
   prev[3] = (R)uy;
   // the stored populations of level 0 are rounded to the storage type before colliding,
@@ -1419,24 +1423,26 @@ __global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename 
       double drho = 0.0;
       for (int i = 0; i < 9; ++i) drho += (double)St<S>::ld(pop + i * P + c, d.inv_scale);
       const double rho = (double)d.rho0 + drho;
-      const double T = d4[c], C = d4[P + c], ux = d4[2 * P + c], uy = d4[3 * P + c];
+      // the field buffer holds T - T0 and C - C0
+      const double dT = d4[c], dC = d4[P + c], ux = d4[2 * P + c], uy = d4[3 * P + c];
+      const double T = (double)d.T0 + dT, C = (double)d.C0 + dC;
       const double phi = d.phi_field ? (double)((const R *)d.phi)[c] : (double)d.phi_u;
       acc[0] += rho;
       acc[1] += (double)d.sigma * T;
       acc[2] += phi * C;
-      const double sT = snap[c], sC = snap[P + c], sx = snap[2 * P + c], sy = snap[3 * P + c];
+      const double sT = snap[c], sC = snap[P + c], sx = snap[2 * P + c], sy = snap[3 * P + c];   // deviations
       acc[3] += (ux - sx) * (ux - sx) + (uy - sy) * (uy - sy);
       acc[4] += ux * ux + uy * uy;
-      acc[5] += (T - sT) * (T - sT);
+      acc[5] += (dT - sT) * (dT - sT);
       acc[6] += T * T;
-      acc[7] += (C - sC) * (C - sC);
+      acc[7] += (dC - sC) * (dC - sC);
       acc[8] += C * C;
       acc[9] = fmax(acc[9], fabs(ux));
       acc[10] = fmax(acc[10], fabs(uy));
       const bool bad = !(isfinite(rho) && isfinite(T) && isfinite(C) && isfinite(ux) && isfinite(uy));
       acc[11] += bad ? 1.0 : 0.0;
-      snap[c] = (R)T;
-      snap[P + c] = (R)C;
+      snap[c] = (R)dT;
+      snap[P + c] = (R)dC;
       snap[2 * P + c] = (R)ux;
       snap[3 * P + c] = (R)uy;
     }
@@ -1459,6 +1465,8 @@ __global__ void __launch_bounds__(OBS_THREADS) obs_partial_kernel(Desc<typename 
 // Mean Nusselt / Sherwood numbers of Eq. (38) at the four sides; one block per side.
 // Half-way wall: gradient along the inward normal (-8 s_w + 9 s_0 - s_1)/3, mean over the
 // nodes.  Wall through the nodes: (-3 s_b + 4 s_1 - s_2)/2, trapezoidal mean along the wall.
+// Both stencils sum to zero, so they act on the stored deviations T - T0, C - C0 (wT, wC: the
+// wall values minus T0, C0) unchanged.
 // Heat entering through a hot side or leaving through a cold or convective side is positive.
 template <typename R>
 __global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__restrict__ wT,
@@ -1507,16 +1515,27 @@ __global__ void __launch_bounds__(256) wall_kernel(Desc<R> d, const double *__re
   }
 }
 
-__global__ void __launch_bounds__(64) obs_final_kernel(const double *__restrict__ partials, int nblocks,
-                                                       double *__restrict__ out) {
-  const int s = threadIdx.x;
-  if (s >= NSLOT) return;
-  double v = partials[s];
-  for (int b = 1; b < nblocks; ++b) {
+// One work-group per slot: thread t combines the partials t, t + 256, ... in index order, then
+// the waves reduce with lane shuffles and the four wave results are combined in wave order (a
+// fixed tree: the result depends on the number of partials only).
+__global__ void __launch_bounds__(OBS_THREADS) obs_final_kernel(const double *__restrict__ partials, int nblocks,
+                                                                double *__restrict__ out) {
+  const int s = blockIdx.x;
+  const bool is_max = s == 9 || s == 10;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += OBS_THREADS) {
     const double p = partials[(long long)b * NSLOT + s];
-    v = (s == 9 || s == 10) ? fmax(v, p) : v + p;
+    v = is_max ? fmax(v, p) : v + p;
   }
-  out[s] = v;
+  v = is_max ? wave_max(v) : wave_sum(v);
+  __shared__ double red[OBS_THREADS / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < OBS_THREADS / 64; ++w) r = is_max ? fmax(r, red[w]) : r + red[w];
+    out[s] = r;
+  }
 }
 
 // FP64 fields rho, ux, uy, T, C of the current level (5 planes of nx*ny, x fastest)
@@ -1537,8 +1556,8 @@ __global__ void __launch_bounds__(256) export_kernel(Desc<typename St<S>::R> d, 
   f[k] = (double)d.rho0 + drho;
   f[n + k] = d4[2 * P + c];
   f[2 * n + k] = d4[3 * P + c];
-  f[3 * n + k] = d4[c];
-  f[4 * n + k] = d4[P + c];
+  f[3 * n + k] = (double)d.T0 + d4[c];
+  f[4 * n + k] = (double)d.C0 + d4[P + c];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1739,7 +1758,7 @@ static int obs_t(const void *desc, int parity, void *snap, double *partials, int
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(obs_partial_kernel<S>, dim3(nblocks), dim3(OBS_THREADS), 0, s, d, parity, (R *)snap,
                      partials);
-  hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, out);
+  hipLaunchKernelGGL(obs_final_kernel, dim3(NSLOT), dim3(OBS_THREADS), 0, s, partials, nblocks, out);
   hipLaunchKernelGGL(wall_kernel<R>, dim3(4), dim3(256), 0, s, d, wT, wC, LdT, LdC, out);
   return (int)hipGetLastError();
 }

@@ -24,7 +24,8 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-    "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
+    "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_derive", "lbm_state_bytes", "lbm_get_state",
+    "lbm_set_state",
     "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_steps_per_launch",
     "lbm_get_steps_per_launch", "lbm_set_graph_chunk",
     "lbm_autotune", "lbm_last_error", "lbm_destroy",
@@ -57,6 +58,7 @@ class Params(ctypes.Structure):
         ("nu", ctypes.c_double), ("alpha_e", ctypes.c_double), ("D_e", ctypes.c_double),
         ("K", ctypes.c_double), ("gbT", ctypes.c_double), ("gbC", ctypes.c_double),
         ("Bi_T", ctypes.c_double), ("Bi_C", ctypes.c_double),
+        ("Re", ctypes.c_double), ("Gr", ctypes.c_double), ("U0", ctypes.c_double),
         ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
     ]
 
@@ -97,6 +99,7 @@ def lib():
         L.lbm_observables.argtypes = [_VP, ctypes.POINTER(Obs), _D]
         L.lbm_get_fields.argtypes = [_VP, _D]
         L.lbm_get_derived.argtypes = [_VP, ctypes.POINTER(Derived)]
+        L.lbm_derive.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Derived)]
         L.lbm_state_bytes.argtypes = [_VP]
         L.lbm_state_bytes.restype = ctypes.c_uint64
         L.lbm_get_state.argtypes = [_VP, _VP, ctypes.c_uint64]
@@ -165,6 +168,15 @@ def node_walls(params: dict) -> bool:
         if (isinstance(k, str) and k.startswith("nee_")) or (not isinstance(k, str) and int(k) >= 4):
             return True
     return False
+
+
+def derive(p: dict, precision: str = "fp32") -> dict:
+    """lbm_derive: the lattice values of a problem statement for its uniform porosity, computed
+    on the host (no device needed)."""
+    s = make_params(p, precision)
+    d = Derived()
+    _check(lib().lbm_derive(ctypes.byref(s), ctypes.byref(d)), None, "lbm_derive")
+    return {n: getattr(d, n) for n, _ in Derived._fields_}
 
 
 def footprint_bytes(p: dict, precision: str = "fp32") -> int:

@@ -64,6 +64,8 @@ def test_footprint_scales_with_precision():
     {"sides": ("nee_hot", "nee_robin", "nee_adiabatic", "nee_adiabatic"), "Bi_C": -0.5},
     {"nx": 4, "sides": ("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")},
     {"direct": 1, "nu": 0.0, "alpha_e": 0.1, "D_e": 0.1, "K": 1.0},
+    {"direct": 2, "Re": 0.0, "Gr": 100.0, "U0": 0.1}, {"direct": 2, "Re": 100.0, "Gr": -1.0, "U0": 0.1},
+    {"direct": 2, "Re": 100.0, "Gr": 100.0, "U0": 0.0}, {"direct": 3},
     # population planes beyond the 4 GiB range of one buffer resource
     {"nx": 8192, "ny": 8192, "precision": "fp32"}, {"nx": 6144, "ny": 6144, "precision": "fp64"},
     {"nx": 11264, "ny": 11264, "precision": "fp16s"},
@@ -122,3 +124,31 @@ def test_largest_lattice_is_accepted_and_the_next_row_refused(prec, nx, ny):
         assert (rc != lbm.EINVAL) if ok else (rc == lbm.EINVAL)
         if h.value:
             lbm.lib().lbm_destroy(h)
+
+
+def test_derived_values_of_the_natural_convection_mapping():
+    """lbm_derive (host only) on the 64x64 porous cavity: the hand values of section 4.1 and
+    Eq. (29) (the same numbers pin the oracle's own mapping)."""
+    d = lbm.derive({})
+    hand = dict(U=0.0577350, nu=0.0369504, s_v=1.637060, zeta_a=1.460383, eta_D=1.688117, gbT=5.208333e-5,
+                gbC=5.208333e-5, K_mean=40.96, varpi=0.4, L=64.0)
+    for k, v in hand.items():
+        assert d[k] == pytest.approx(v, rel=2e-6), k
+
+
+def test_derived_values_of_the_lid_driven_mapping():
+    """Section 4.3 (Table 4 case, 128^2, Re = Gr = 100, U0 = 0.1, Da = 0.1, N = -500): nu =
+    U0 L/Re = 0.128, 1/s_v = 1/2 + J L U0/(c_s^2 Re) = 0.884, g beta_T dT = Gr nu^2/L^3 =
+    7.8125e-7, K = 1638.4, zeta_alpha = eta_D = 1/1.14; with walls through the nodes L = 128
+    on 129 nodes gives the same values."""
+    base = dict(sides=("adiabatic", "adiabatic", "cold", "hot"), direct=2, Re=100.0, Gr=100.0, U0=0.1, Pr=1.0,
+                Le=1.0, Da=0.1, N=-500.0, phi=0.95, wall_u=(0.0, 0.0, 0.0, 0.1))
+    hand = dict(nu=0.128, s_v=1 / 0.884, gbT=7.8125e-7, gbC=-500 * 7.8125e-7, K_mean=1638.4, zeta_a=1 / 1.14,
+                eta_D=1 / 1.14, U=0.1, L=128.0)
+    for p in (dict(base, nx=128, ny=128),
+              dict(base, nx=129, ny=129, sides=("nee_adiabatic", "nee_adiabatic", "nee_cold", "nee_hot"))):
+        d = lbm.derive(p, "fp64")
+        for k, v in hand.items():
+            assert d[k] == pytest.approx(v, rel=1e-12), (p["nx"], k)
+    with pytest.raises(lbm.LbmError):
+        lbm.derive(dict(base, nx=128, ny=128, Re=-1.0))

@@ -28,16 +28,14 @@ def run_to_steady(s, chunk=5000, tol=1e-9, cap=400000, scalars=False):
     return ob, steps
 
 
-def lid_driven_params(N, phi=0.95, model=0, n=128, Gr=1e2, Re=100.0, Da=0.1, Pr=1.0, Le=1.0, U0=0.1, L=None):
-    """Section 4.3: nu = U0 L/Re (1/s_v = 1/2 + J L U0/(c_s^2 Re)), alpha_e = nu/Pr,
-    D_e = alpha_e/Le, K = Da L^2, g beta_T dT = Gr nu^2/L^3, beta_C dC = N beta_T dT.  L is
-    the wall-to-wall distance: n with half-way walls, n - 1 with walls through the nodes."""
-    L = n if L is None else L
-    nu = U0 * L / Re
-    gbT = Gr * nu * nu / L ** 3
-    return dict(nx=n, ny=n, sides=("adiabatic", "adiabatic", "cold", "hot"), direct=1, nu=nu, alpha_e=nu / Pr,
-                D_e=nu / Pr / Le, K=Da * L * L, gbT=gbT, gbC=N * gbT, phi=phi, model=model,
-                wall_u=(0.0, 0.0, 0.0, U0), Th=1.0, Tl=0.0, Ch=1.0, Cl=0.0)
+def lid_driven_params(N, phi=0.95, model=0, n=128, Gr=1e2, Re=100.0, Da=0.1, Pr=1.0, Le=1.0, U0=0.1):
+    """Section 4.3, through the library's lid-driven mapping (direct = 2): nu = U0 L/Re
+    (1/s_v = 1/2 + J L U0/(c_s^2 Re)), alpha_e = nu/Pr, D_e = alpha_e/Le, K = Da L^2,
+    g beta_T dT = Gr nu^2/L^3, beta_C dC = N beta_T dT, with L the wall-to-wall distance (n with
+    half-way walls, n - 1 with walls through the nodes); the top wall moves with U0."""
+    return dict(nx=n, ny=n, sides=("adiabatic", "adiabatic", "cold", "hot"), direct=2, Re=Re, Gr=Gr, U0=U0, Pr=Pr,
+                Le=Le, Da=Da, N=N, phi=phi, model=model, wall_u=(0.0, 0.0, 0.0, U0), Th=1.0, Tl=0.0, Ch=1.0,
+                Cl=0.0)
 
 
 def test_table1_pure_fluid_enclosure():
@@ -167,7 +165,7 @@ def test_table4_with_extrapolation_walls():
     for branch in ([0, -100, -250, -500, -750], [100, 500]):
         init = dict(T=0.5, C=0.5) if branch[0] == 0 else start
         for N in branch:
-            p = lid_driven_params(N, n=129, L=128)
+            p = lid_driven_params(N, n=129)
             p["sides"] = ("nee_adiabatic", "nee_adiabatic", "nee_cold", "nee_hot")
             s = Solver(p, precision="fp64", **init)
             ob, steps = run_to_steady(s, chunk=5000, tol=1e-10, cap=600000, scalars=True)
