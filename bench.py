@@ -67,9 +67,9 @@ def parse():
     ap.add_argument("--until-converged", action="store_true",
                     help="sweep: run every cavity to steady state (residual 1e-8) or --max-steps, "
                          "batched through the serving loop and one by one with plain launches")
-    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=256, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=0,
-                    help="step cap per solve (serve: default 20000; sweep --until-converged: 100000)")
+                    help="step cap per solve (serve and sweep --until-converged: default 100000)")
     ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
@@ -241,6 +241,10 @@ def sweep(a):
     b = Batch(len(solvers), chunk=100)
     for s in solvers:
         b.attach(s)
+    t0 = time.perf_counter()
+    chosen = b.autotune(20)
+    out["batch_autotune"] = {"seconds": round(time.perf_counter() - t0, 2),
+                             "choices": {f"{p}|{c}": {"shape": v[0], "policy": v[1]} for (p, c), v in chosen.items()}}
     b.step(200)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -330,7 +334,8 @@ def sweep_until_converged(a, cav):
     for i, e in enumerate(cav):
         T, C = workloads.cavity_fields(e)
         reqs.append(Request(i, 0.0, e["params"], "fp32", None, T, C))
-    srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
+    srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=100, check_every=1000, tol=1e-8, max_steps=cap,
+                 autotune_steps=20)
 
     def note(d):
         print("progress", json.dumps(d), file=sys.stderr, flush=True)
@@ -388,15 +393,18 @@ def serve(a):
     budget = 200 * 10 ** 9
     # closed-loop capacity with everything arriving at once, to set the arrival rate
     cal = build(workloads.request_stream(count=max(8, a.requests // 4), seed=40, rate=1e9))
-    cap = a.max_steps or 20000
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
-    _, cs = srv.run(cal)
+    cap = a.max_steps or 100000
+    def note(d):
+        print("progress", json.dumps(d), file=sys.stderr, flush=True)
+
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap, autotune_steps=20)
+    _, cs = srv.run(cal, progress=note)
     srv.close()
     capacity = cs["requests"] / cs["wall_s"]
     rate = 0.8 * capacity
     reqs = build(workloads.request_stream(count=a.requests, seed=4, rate=rate))
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap)
-    results, summ = srv.run(reqs)
+    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap, autotune_steps=20)
+    results, summ = srv.run(reqs, progress=note)
     srv.close()
     torch.cuda.synchronize()
     out = {"metric": "batched p50/p99 solve latency and aggregate MLUPS (continuous batching)",

@@ -238,16 +238,20 @@ void lbm_destroy(struct lbm_ctx *c);
 
 /* ---- batched stepping of many independent cavities --------------------------------
  * A batch advances every attached context (any size, parameters and precision).  The
- * attached contexts are split, in attach order and per precision, into groups whose step
- * touches at most 200 MB together (a larger context is a group of its own); each group
- * advances `chunk` steps with one kernel launch per step before the next group starts, so
- * its data stays in the 256 MB Infinity Cache from step to step.  Each group's launch takes
- * the default cache-policy rule of lbm_set_cache_policy for the group's bytes.  The launches
- * use a fixed grid that walks a device-side table of (cavity, tile) work items and are
- * replayed from a captured HIP graph; attaching or detaching contexts rewrites the tables
- * between replays and re-captures only when the groups' number, precisions or policies
- * change.  Per-node arithmetic is the same code as lbm_step: a cavity's state after n
- * batched steps is bitwise the state after lbm_step(c, n). */
+ * attached contexts are split per precision and size class (width <= 64, <= 128, <= 256 or
+ * wider; attach order within a class) into groups whose step touches at most 200 MB together
+ * (a larger context is a group of its own); each group advances `chunk` steps before the next
+ * group starts, so its data stays in the 256 MB Infinity Cache from step to step.  With an
+ * even chunk that is a multiple of 4 a launch advances two steps (the two-step kernel over
+ * tiles of the group's shape: 64 x 8, 32 x 16 or 32 x 8 nodes; FP64 32 x 8, 16 x 16 or 16 x 8),
+ * otherwise one.  A group takes the tile shape and cache policy lbm_batch_autotune chose for
+ * its precision and size class, or by default the first shape and the default cache-policy
+ * rule of lbm_set_cache_policy for the group's bytes.  Each launch walks a device-side table of
+ * (cavity, tile) work items and the launches are replayed from a captured HIP graph;
+ * attaching or detaching contexts rewrites the tables between replays and re-captures only
+ * when the groups' number, precisions, shapes, policies or grids change.  Per-node arithmetic
+ * is the same code as lbm_step: a cavity's state after n batched steps is bitwise the state
+ * after lbm_step(c, n), whatever the tile shape. */
 typedef struct lbm_batch lbm_batch;
 
 /* max_cavities: capacity of the table; chunk: steps per graph replay (even, >= 2);
@@ -261,6 +265,18 @@ lbm_status lbm_batch_attach(lbm_batch *b, struct lbm_ctx *c);
 lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
 /* Advances every attached context by nsteps (asynchronous). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+/* Autotuner of the batched launch: for every precision and size class present, times each
+ * tile shape of the two-step launch and each cache policy on that class's groups (`steps`
+ * steps, rounded up to a multiple of 4, after a warm-up), keeps the fastest, and restores
+ * every attached state it started from.  shape_out and policy_out (each 12 int32, index
+ * precision * 4 + size class; may be NULL) receive the choices of the classes present.
+ * Synchronises; allocates a temporary device copy of the attached states. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, int32_t *policy_out);
+/* Sets the launch choice of one precision (lbm_precision) and size class (0-3: width <= 64,
+ * <= 128, <= 256, wider) without timing (e.g. from a cache of lbm_batch_autotune results):
+ * shape 0-2, policy 0-2 or -1 for the default rule.  Takes effect at the next lbm_batch_step.
+ * LBM_EINVAL for an index out of range. */
+lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape, int32_t policy);
 int32_t lbm_batch_size(const lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);
 

@@ -39,9 +39,13 @@ size_t real_size(int prec) { return prec == PREC_FP64 ? 8 : 4; }
 struct Layout {
   int pitch;
   long long plane;
-  size_t off_pop0, off_pop1, off_d4, off_d4b, off_phi, off_snap, off_counter, off_small, total;
+  size_t off_pop0, off_pop1, off_d4, off_d4b, off_phi, off_snap, off_counter, off_desc, off_small, total;
   int nblocks_obs;
 };
+
+// device copies of the descriptor, one per (population buffer, field buffer) of a launch
+constexpr size_t kDescSlot = 1024;
+static_assert(sizeof(Desc<double>) <= kDescSlot && sizeof(Desc<float>) <= kDescSlot, "descriptor slot");
 
 // Planes of ny rows of `pitch` elements; the plane stride is padded by 256 elements past a
 // 1024-element boundary so that the 19 + 4 concurrent streams do not start on the same
@@ -67,6 +71,7 @@ Layout plan_layout(int nx, int ny, int prec) {
   L.off_phi = take((size_t)L.plane * rs);
   L.off_snap = take((size_t)ND4 * L.plane * rs);
   L.off_counter = take(2 * sizeof(unsigned));
+  L.off_desc = take(4 * kDescSlot);
   // small: wall T (4), wall C (4), obs out (32), partials
   L.off_small = take((8 + 32 + (size_t)L.nblocks_obs * 12) * sizeof(double));
   L.total = off;
@@ -117,6 +122,8 @@ struct lbm_ctx {
   double *obs_out() const { return wall_dev() + 8; }
   double *partials() const { return wall_dev() + 40; }
   const void *desc() const { return prec == PREC_FP64 ? (const void *)&d64 : (const void *)&d32; }
+  // the device copy of the descriptor for population buffer `pc` and field buffer `fc`
+  const void *desc_dev(int pc, int fc) const { return base + lay.off_desc + (size_t)(2 * pc + fc) * kDescSlot; }
 };
 
 namespace {
@@ -377,12 +384,18 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
       const double Cw = p->side[s] == SIDE_HOT ? p->Ch : p->Cl;
       // anti-bounce-back: g_i = -g*_opp + g^eq_i(w) + g^eq_opp(w) = -g*_opp + (varpi/2) cap T_w,
       // in deviation form -gd*_opp + (varpi/2) cap (T_w - T0)
-      D.wT[s] = (R)(0.5 * d.varpi * capT * (Tw - d.T0));
-      D.wC[s] = (R)(0.5 * d.varpi * capC * (Cw - d.C0));
-      D.uw[s] = (R)(6.0 * p->rho0 * p->wall_u[s]);
+      // (in the units of the FP16 pre-scale, as the populations they are added to)
+      D.wT[s] = (R)(0.5 * d.varpi * capT * (Tw - d.T0) * d.fp16_scale);
+      D.wC[s] = (R)(0.5 * d.varpi * capC * (Cw - d.C0) * d.fp16_scale);
+      D.uw[s] = (R)(6.0 * p->rho0 * p->wall_u[s] * d.fp16_scale);
+      D.uwall[s] = (R)p->wall_u[s];
     }
     D.scale = (R)d.fp16_scale;
     D.inv_scale = (R)(1.0 / d.fp16_scale);
+    D.rho0_s = (R)(p->rho0 * d.fp16_scale);
+    D.inv_rho0_s = (R)(1.0 / (p->rho0 * d.fp16_scale));
+    D.T0_s = (R)(d.T0 * d.fp16_scale);
+    D.C0_s = (R)(d.C0 * d.fp16_scale);
     D.nee = node_walls(p);
     for (int s = 0; s < 4; ++s) {
       const bool hot = p->side[s] == SIDE_NEE_HOT;
@@ -603,6 +616,17 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   }
   if (e == hipSuccess) e = (hipError_t)launch_init(c->prec, c->desc(), stage, stage + n, stage + 2 * n, stage + 3 * n, c->stream);
+  // the four device copies of the descriptor the step kernels read
+  std::vector<char> dslots(4 * kDescSlot, 0);
+  for (int pc = 0; pc < 2; ++pc)
+    for (int fc = 0; fc < 2; ++fc) {
+      set_parity(c, pc, fc);
+      std::memcpy(dslots.data() + (2 * pc + fc) * kDescSlot, c->desc(),
+                  c->prec == PREC_FP64 ? sizeof(Desc<double>) : sizeof(Desc<float>));
+    }
+  set_parity(c, 0, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->base + c->lay.off_desc, dslots.data(), dslots.size(), hipMemcpyHostToDevice, c->stream);
   // the residual snapshot starts at level 0
   if (e == hipSuccess) e = hipMemcpyAsync(c->snap(), c->d4(), 4 * plane_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->wall_dev(), c->wallT, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream);
@@ -654,17 +678,17 @@ static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   while (n > 0) {
     set_parity(c, c->cur);
     if (spl == 3 && n >= 3) {
-      int e = launch_step3(c->prec, c->desc(), cp, 0, c->stream);
+      int e = launch_step3(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "three-step kernel launch");
       c->d4cur ^= 1;
       n -= 3;
     } else if (spl >= 2 && n >= 2) {
-      int e = launch_step2(c->prec, c->desc(), cp, 0, c->stream);
+      int e = launch_step2(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "two-step kernel launch");
       c->d4cur ^= 1;
       n -= 2;
     } else {
-      int e = launch_step(c->prec, c->desc(), c->tile, cp, 0, c->stream);
+      int e = launch_step(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), c->tile, cp, 0, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "step kernel launch");
       n -= 1;
     }
@@ -711,13 +735,13 @@ static lbm_status ensure_graph(lbm_ctx *c) {
     for (int k = 0; k < gsteps / spl && e == hipSuccess; ++k) {
       set_parity(c, cur, d4);
       if (spl == 3) {
-        e = (hipError_t)launch_step3(c->prec, c->desc(), cp, 0, cs);
+        e = (hipError_t)launch_step3(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, cs);
         d4 ^= 1;
       } else if (spl == 2) {
-        e = (hipError_t)launch_step2(c->prec, c->desc(), cp, 0, cs);
+        e = (hipError_t)launch_step2(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, cs);
         d4 ^= 1;
       } else {
-        e = (hipError_t)launch_step(c->prec, c->desc(), c->tile, cp, 0, cs);
+        e = (hipError_t)launch_step(c->prec, c->desc(), c->desc_dev(cur, d4), c->tile, cp, 0, cs);
       }
       cur ^= 1;
     }
@@ -764,15 +788,17 @@ LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   return LBM_OK;
 }
 
-static lbm_status export_fields(lbm_ctx *c, double *fields) {
+// FP64 fields of the current level into host memory through a device staging buffer: `stage`
+// (5 nx ny doubles), or one allocated for the call when stage is NULL
+static lbm_status export_fields(lbm_ctx *c, double *fields, double *stage = nullptr) {
   set_parity(c, c->cur);
   const size_t n = (size_t)c->p.nx * c->p.ny;
-  double *stage = nullptr;
-  HIP_CHECK(c, hipMalloc((void **)&stage, 5 * n * sizeof(double)), "hipMalloc export");
+  const bool own = stage == nullptr;
+  if (own) HIP_CHECK(c, hipMalloc((void **)&stage, 5 * n * sizeof(double)), "hipMalloc export");
   hipError_t he = (hipError_t)launch_export(c->prec, c->desc(), 0, stage, c->stream);
   if (he == hipSuccess) he = hipMemcpyAsync(fields, stage, 5 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-  (void)hipFree(stage);
+  if (own) (void)hipFree(stage);
   if (he != hipSuccess) return hip_fail(c, he, "field export");
   return LBM_OK;
 }
@@ -783,19 +809,21 @@ LBM_API lbm_status lbm_get_fields(lbm_ctx *c, double *fields) {
   return export_fields(c, fields);
 }
 
-LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
-  if (!c || !out) return LBM_EINVAL;
-  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables before lbm_set_fields");
+// The observables of the current level, with the per-block partial sums in `partials`, the 20
+// result slots in `slots` and, when fields is not NULL, the field export staged in `stage`
+// (NULL: allocated for the call).
+static lbm_status observe(lbm_ctx *c, lbm_obs *out, double *fields, double *partials, double *slots,
+                          double *stage) {
   set_parity(c, c->cur);
   const int nb = c->lay.nblocks_obs;
-  int e = launch_observables(c->prec, c->desc(), 0, c->snap(), c->partials(), nb, c->obs_out(), c->wall_dev(),
+  int e = launch_observables(c->prec, c->desc(), 0, c->snap(), partials, nb, slots, c->wall_dev(),
                              c->wall_dev() + 4, c->dv.dT != 0 ? c->dv.L / c->dv.dT : 0.0,
                              c->dv.dC != 0 ? c->dv.L / c->dv.dC : 0.0, c->stream);
   if (e) return hip_fail(c, (hipError_t)e, "observables launch");
   double r[20];
-  HIP_CHECK(c, hipMemcpyAsync(r, c->obs_out(), sizeof r, hipMemcpyDeviceToHost, c->stream), "observables copy");
+  HIP_CHECK(c, hipMemcpyAsync(r, slots, sizeof r, hipMemcpyDeviceToHost, c->stream), "observables copy");
   if (fields) {
-    lbm_status fs = export_fields(c, fields);
+    lbm_status fs = export_fields(c, fields, stage);
     if (fs != LBM_OK) return fs;
   }
   HIP_CHECK(c, hipStreamSynchronize(c->stream), "observables sync");
@@ -823,6 +851,12 @@ LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
     return fail(c, LBM_EUNSTABLE, "non-finite value in the fields at step %lld", (long long)c->step);
   }
   return LBM_OK;
+}
+
+LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables before lbm_set_fields");
+  return observe(c, out, fields, c->partials(), c->obs_out(), nullptr);
 }
 
 LBM_API lbm_status lbm_get_derived(const lbm_ctx *c, lbm_derived *out) {
@@ -1042,10 +1076,21 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
 // that they stay in the Infinity Cache while the group advances a chunk of steps; items
 // [first, first + count) of the precision's item table.
 struct BatchGroup {
-  int prec, cp, first, count, first2, count2;   // one-step items, two-step items
+  int prec, cls, cp, first, count, first2, count2;   // one-step items, two-step items
   int grid2;   // work-groups of the two-step launch (one per item; count2 rounded up to a
                // power of two, so that a graph survives small changes of the group)
+  int shape;   // tile shape of the two-step launch (batch_tile_shape)
 };
+
+// Launch choice of the groups of one precision and size class: the two-step tile shape and
+// the cache policy (-1: the default rule), set by lbm_batch_autotune.
+struct BatchChoice {
+  int shape = 0, cp = -1;
+};
+
+// size classes of cavities in a batch, by width: <= 64, <= 128, <= 256, wider
+constexpr int kBatchClasses = 4;
+int batch_class(int nx) { return nx <= 64 ? 0 : nx <= 128 ? 1 : nx <= 256 ? 2 : 3; }
 
 struct lbm_batch {
   int cap = 0;
@@ -1060,6 +1105,7 @@ struct lbm_batch {
   int item_cap[3] = {0, 0, 0};
   int item2_cap[3] = {0, 0, 0};
   std::vector<BatchGroup> groups;
+  BatchChoice choice[3][kBatchClasses];   // per precision and size class
   int *ranges = nullptr;     // device: {first, count, first2, count2} per group
   int range_cap = 0;
   int grid = 2048;           // work-groups of the one-step batched launch
@@ -1082,26 +1128,32 @@ lbm_status batch_upload(lbm_batch *b) {
   b->groups.clear();
   for (int prec = 0; prec < 3; ++prec) {
     std::vector<Item> items, items2;
-    int w2 = 0, h2 = 0;
-    two_step_tile_shape(prec, &w2, &h2);
     std::vector<Desc<double>> d64;
     std::vector<Desc<float>> d32;
     double gnodes = 0;
-    for (lbm_ctx *c : b->ctx) {
-      if (c->prec != prec) continue;
+    // cavities of this precision by size class (attach order within a class)
+    std::vector<lbm_ctx *> order;
+    for (int cls = 0; cls < kBatchClasses; ++cls)
+      for (lbm_ctx *c : b->ctx)
+        if (c->prec == prec && batch_class(c->p.nx) == cls) order.push_back(c);
+    for (lbm_ctx *c : order) {
+      const int cls = batch_class(c->p.nx);
+      const BatchChoice &ch = b->choice[prec][cls];
       const int idx = prec == PREC_FP64 ? (int)d64.size() : (int)d32.size();
       set_parity(c, c->cur);
       if (prec == PREC_FP64) d64.push_back(c->d64);
       else d32.push_back(c->d32);
-      // groups in attach order, closed when the next cavity would take the group past
+      // groups per size class, closed when the next cavity would take the group past
       // kGroupBytes (a larger cavity is a group of its own)
       const double nodes = (double)c->p.nx * c->p.ny;
-      if (b->groups.empty() || b->groups.back().prec != prec ||
+      if (b->groups.empty() || b->groups.back().prec != prec || b->groups.back().cls != cls ||
           (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
-        b->groups.push_back(BatchGroup{prec, 0, (int)items.size(), 0, (int)items2.size(), 0, 1});
+        b->groups.push_back(BatchGroup{prec, cls, 0, (int)items.size(), 0, (int)items2.size(), 0, 1, ch.shape});
         gnodes = 0;
       }
       gnodes += nodes;
+      int w2 = 0, h2 = 0;
+      batch_tile_shape(prec, ch.shape, &w2, &h2);
       // 256-thread tiles of tw x (256/tw) nodes; tw in {256, 128, 64} wastes the fewest
       // lanes on the ragged right edge (ties go to the wider tile)
       int tw = 256;
@@ -1119,7 +1171,7 @@ lbm_status batch_upload(lbm_batch *b) {
       g.count2 = (int)items2.size() - g.first2;
       g.grid2 = 1;
       while (g.grid2 < g.count2) g.grid2 *= 2;
-      g.cp = default_policy(prec, gnodes, b->chunk % 4 == 0 ? 2 : 1);   // steps per launch as batch_spl
+      g.cp = ch.cp >= 0 ? ch.cp : default_policy(prec, gnodes, b->chunk % 4 == 0 ? 2 : 1);   // spl as batch_spl
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {
@@ -1183,6 +1235,7 @@ std::vector<int> batch_key(const lbm_batch *b) {
     k.push_back(g.prec);
     k.push_back(g.cp);
     k.push_back(g.grid2);
+    k.push_back(g.shape);
   }
   return k;
 }
@@ -1191,30 +1244,36 @@ std::vector<int> batch_key(const lbm_batch *b) {
 // flips the population and field buffers an even number of times), else 1.
 int batch_spl(const lbm_batch *b) { return b->chunk % 4 == 0 ? 2 : 1; }
 
-// n steps of every group, group after group (a group's cavities stay cache resident while
-// it advances; groups are independent, so the order changes no result): pairs of steps in
-// the two-step kernel, an odd step in the one-step kernel (with the field buffer the pairs
-// left current: parity bit 1)
-hipError_t batch_launch_steps(lbm_batch *b, int64_t n, hipStream_t s) {
+// n steps of group gi: pairs of steps in the two-step kernel, an odd step in the one-step
+// kernel (with the field buffer the pairs left current: parity bit 1)
+hipError_t batch_launch_group(lbm_batch *b, size_t gi, int64_t n, hipStream_t s) {
   const int spl = batch_spl(b);
-  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-    const BatchGroup &g = b->groups[gi];
-    const int *rg = b->ranges + 4 * gi;
-    int64_t k = 0;
-    if (spl == 2)
-      for (; k + 2 <= n; k += 2) {
-        const int q = (int)((k / 2) & 1);
-        int e = launch_step2_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2, g.grid2, q, s);
-        if (e) return (hipError_t)e;
-      }
-    for (; k < n; ++k) {
-      // launches so far: k / 2 two-step ones, then single steps
-      const int launches = (int)(spl == 2 ? k / 2 + (k - 2 * (k / 2)) : k);
-      const int pairs = (int)(spl == 2 ? (k / 2) & 1 : 0);
-      const int parity = (launches & 1) | (pairs << 1);
-      int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], rg, b->grid, parity, s);
+  const BatchGroup &g = b->groups[gi];
+  const int *rg = b->ranges + 4 * gi;
+  int64_t k = 0;
+  if (spl == 2)
+    for (; k + 2 <= n; k += 2) {
+      const int q = (int)((k / 2) & 1);
+      int e = launch_step2_batch(g.prec, g.cp, g.shape, b->descs[g.prec], b->items2[g.prec], rg + 2, g.grid2, q, s);
       if (e) return (hipError_t)e;
     }
+  for (; k < n; ++k) {
+    // launches so far: k / 2 two-step ones, then single steps
+    const int launches = (int)(spl == 2 ? k / 2 + (k - 2 * (k / 2)) : k);
+    const int pairs = (int)(spl == 2 ? (k / 2) & 1 : 0);
+    const int parity = (launches & 1) | (pairs << 1);
+    int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], rg, b->grid, parity, s);
+    if (e) return (hipError_t)e;
+  }
+  return hipSuccess;
+}
+
+// n steps of every group, group after group (a group's cavities stay cache resident while it
+// advances; groups are independent, so the order changes no result)
+hipError_t batch_launch_steps(lbm_batch *b, int64_t n, hipStream_t s) {
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const hipError_t e = batch_launch_group(b, gi, n, s);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1297,6 +1356,99 @@ LBM_API lbm_status lbm_batch_detach(lbm_batch *b, lbm_ctx *c) {
 }
 
 LBM_API int32_t lbm_batch_size(const lbm_batch *b) { return b ? (int32_t)b->ctx.size() : 0; }
+
+LBM_API lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape,
+                                      int32_t policy) {
+  if (!b || precision < 0 || precision > 2 || size_class < 0 || size_class >= kBatchClasses || shape < 0 ||
+      shape >= batch_tile_shapes() || policy < -1 || policy >= CP_COUNT)
+    return LBM_EINVAL;
+  b->choice[precision][size_class] = BatchChoice{shape, policy};
+  b->dirty = true;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, int32_t *policy_out) {
+  if (!b || steps < 1) return LBM_EINVAL;
+  if (b->ctx.empty()) return LBM_OK;
+  const int64_t n = (steps + 3) / 4 * 4;   // whole pairs of two-step launches: buffers end where they began
+  // save every attached state (current populations, fields, step counters) on the device
+  std::vector<size_t> off;
+  size_t total = 0;
+  for (lbm_ctx *c : b->ctx) {
+    off.push_back(total);
+    total += round_up((size_t)NPOP * c->lay.plane * store_size(c->prec), 256) +
+             round_up((size_t)ND4 * c->lay.plane * real_size(c->prec), 256) + 256;
+  }
+  char *save = nullptr;
+  if (hipMalloc((void **)&save, total) != hipSuccess) return LBM_ENOMEM;
+  auto copy_states = [&](bool restore) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < b->ctx.size() && e == hipSuccess; ++i) {
+      lbm_ctx *c = b->ctx[i];
+      const size_t pb = (size_t)NPOP * c->lay.plane * store_size(c->prec);
+      const size_t fb = (size_t)ND4 * c->lay.plane * real_size(c->prec);
+      char *dst = save + off[i];
+      char *pop = (char *)c->pop(c->cur), *d4 = (char *)c->d4(), *cnt = (char *)c->counter();
+      const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+      e = restore ? hipMemcpyAsync(pop, dst, pb, k, b->stream) : hipMemcpyAsync(dst, pop, pb, k, b->stream);
+      dst += round_up(pb, 256);
+      if (e == hipSuccess)
+        e = restore ? hipMemcpyAsync(d4, dst, fb, k, b->stream) : hipMemcpyAsync(dst, d4, fb, k, b->stream);
+      dst += round_up(fb, 256);
+      if (e == hipSuccess)
+        e = restore ? hipMemcpyAsync(cnt, dst, 2 * sizeof(unsigned), k, b->stream)
+                    : hipMemcpyAsync(dst, cnt, 2 * sizeof(unsigned), k, b->stream);
+    }
+    return e;
+  };
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = copy_states(false);
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  lbm_status st = LBM_OK;
+  const int shapes = batch_spl(b) == 2 ? batch_tile_shapes() : 1;   // one step per launch: no two-step tile
+  for (int prec = 0; prec < 3 && e == hipSuccess && st == LBM_OK; ++prec)
+    for (int cls = 0; cls < kBatchClasses && e == hipSuccess && st == LBM_OK; ++cls) {
+      bool present = false;
+      for (lbm_ctx *c : b->ctx) present |= c->prec == prec && batch_class(c->p.nx) == cls;
+      if (!present) continue;
+      float best = 3e38f;
+      BatchChoice keep = b->choice[prec][cls];
+      for (int shape = 0; shape < shapes && e == hipSuccess && st == LBM_OK; ++shape)
+        for (int cp = 0; cp < CP_COUNT && e == hipSuccess && st == LBM_OK; ++cp) {
+          b->choice[prec][cls] = BatchChoice{shape, cp};
+          st = batch_upload(b);
+          if (st != LBM_OK) break;
+          // warm-up, then the timed steps, of this class's groups only
+          for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            if (pass == 1) e = hipEventRecord(t0, b->stream);
+            for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi)
+              if (b->groups[gi].prec == prec && b->groups[gi].cls == cls)
+                e = batch_launch_group(b, gi, pass == 0 ? 4 : n, b->stream);
+          }
+          if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(t1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+          if (e == hipSuccess) e = copy_states(true);
+          if (e == hipSuccess && ms < best) {
+            best = ms;
+            keep = b->choice[prec][cls];
+          }
+        }
+      b->choice[prec][cls] = keep;
+      if (shape_out) shape_out[prec * kBatchClasses + cls] = keep.shape;
+      if (policy_out) policy_out[prec * kBatchClasses + cls] = keep.cp;
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(save);
+  drop_batch_graph(b);
+  b->dirty = true;
+  if (st != LBM_OK) return st;
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
 
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;

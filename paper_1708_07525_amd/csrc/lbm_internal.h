@@ -51,9 +51,12 @@ struct Desc {
                            // or cb (1-phi)/sqrt(phi) (fixed F_phi)
   R kg3, c5v;              // n3eq - n3ref = kg3 (T - T0) for g; c5v = 5 varpi
   R inv_phi_u, kh3_u;      // uniform porosity: 1/phi and the h energy factor (as kg3 for g)
-  R wT[4], wC[4];          // anti-bounce-back constants (deviation form) per side
-  R uw[4];                 // 6 rho0 u_wall per side (moving-wall term of the bounce-back)
+  R wT[4], wC[4];          // anti-bounce-back constants (deviation form, pre-scaled) per side
+  R uw[4];                 // 6 rho0 u_wall per side (moving-wall term of the bounce-back, pre-scaled)
+  R uwall[4];              // tangential wall velocity per side
   R scale, inv_scale;      // FP16 pre-scale (1 for FP32/FP64)
+  R rho0_s, inv_rho0_s;    // rho0 scale and 1/(rho0 scale): the collision's constants in the units
+  R T0_s, C0_s;            // of the pre-scale (T0 scale, C0 scale; unscaled for FP32/FP64)
   // walls through the boundary nodes (side kinds 4-7)
   int nee, pad2_[3];
   R Tfix[4], Cfix[4];      // fixed T - T0, C - C0 of each side (kinds 4, 5)
@@ -75,26 +78,30 @@ struct Tile {
 // All take a hipStream_t as void*; return a hipError_t as int.
 int launch_init(int prec, const void *desc, const double *T, const double *C, const double *ux,
                 const double *uy, void *stream);
-// cp: cache policy CP_*
-int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream);
+// desc: the host copy of the descriptor (launch geometry); ddev: the same descriptor in device
+// memory, which the step kernels read.  cp: cache policy CP_*
+int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp, int parity, void *stream);
 // two time steps per launch (tiles with a one-node halo staged in LDS); fields read from d4,
 // written to d4b;
 // cavities without walls through the nodes only
-int launch_step2(int prec, const void *desc, int cp, int parity, void *stream);
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream);
 // three time steps per launch (tiles with a two-node halo staged in LDS); FP32 and FP64
 // storage, walls half a spacing outside; fields read from d4, written to d4b
-int launch_step3(int prec, const void *desc, int cp, int parity, void *stream);
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream);
 // range: device pointer to {first item, item count} of the group to step; parity bit 0
 // selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
                       void *stream);
-// two steps per launch over items of two-step tiles (item.tw = tile width), one item per
-// work-group: grid >= the group's item count; parity as above for both the population and
-// the field buffers
-int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+// two steps per launch over items of two-step tiles of shape `shape` (0 .. batch_tile_shapes()-1;
+// item.tw = tile width), one item per work-group: grid >= the group's item count; parity as
+// above for both the population and the field buffers
+int launch_step2_batch(int prec, int cp, int shape, const void *descs, const Item *items, const int *range, int grid,
                        int parity, void *stream);
-// tile of the two-step kernels for a storage precision
+// tile of the single-cavity two-step kernels for a storage precision
 void two_step_tile_shape(int prec, int *w, int *h);
+// tile shapes of the batched two-step kernel
+int batch_tile_shapes();
+void batch_tile_shape(int prec, int shape, int *w, int *h);
 // observables: partial sums per block, then a final fixed-order reduction.
 // out: 16 doubles + Nu[4] + Sh[4] (see lbm_api.cpp for the slots)
 int launch_observables(int prec, const void *desc, int parity, void *snap, double *partials,
@@ -102,5 +109,6 @@ int launch_observables(int prec, const void *desc, int parity, void *snap, doubl
                        double L_over_dT, double L_over_dC, void *stream);
 int launch_export(int prec, const void *desc, int parity, double *fields, void *stream);
 int observables_blocks(int ny);
+
 
 }  // namespace lbmk

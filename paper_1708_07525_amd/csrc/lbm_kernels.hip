@@ -26,6 +26,8 @@
 // one step's loads and stores per launch.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 
 namespace lbmk {
@@ -66,12 +68,48 @@ __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
 template <>
 __device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
 
-// ---------------------------------------------------------------- collision of one node
-// Inputs: the pulled deviations fd[9], gd[5], hd[5]; node porosity; the previous-step
-// fields (T - T0, C - C0, ux, uy) in prev[4].  Outputs: post-collision deviations (in place)
-// and the fields of this level in prev[4], in the same form.
+// ---------------------------------------------------------------- explicit velocity
+// Eqs. (18)-(19): u = v / (l0 + sqrt(l0^2 + l1 |v|)), l0 = (1 + a/2)/2, l1 = b/2, and |u|.
+// In FP32 the denominator is written as 1 + e, e = a/2 + l1 |v| / (l0 + sqrt(l0^2 + l1 |v|))
+// (the same number), and u = v - v e/(1 + e): 1 + e is never rounded into the result.  A
+// relative bias c of the velocity solve shifts the Darcy-damped steady velocity by about c/a
+// (a ~ 1e-3 per step is common), so rounding the constant l0 to FP32 (c up to 6e-8) costs
+// 1e-5 - 1e-4 of the velocity after some thousand steps; this form keeps c at the size of
+// the rounding of e, a ten-thousandth of that.  FP64 keeps the direct form.
 template <typename R>
-__device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd, R *gd, R *hd, R *prev) {
+__device__ __forceinline__ void velocity_solve(R a, R b, R vx, R vy, R &ux, R &uy, R &un) {
+  const R half = R(0.5);
+  const R l0 = half + R(0.25) * a;
+  const R l1 = half * b;
+  const R vn = sqrt_(vx * vx + vy * vy);
+  if constexpr (sizeof(R) == 4) {
+    const R l1v = l1 * vn;
+    const R e = half * a + l1v / (l0 + sqrt_(l0 * l0 + l1v));
+    const R w = e / (R(1) + e);
+    ux = vx - vx * w;
+    uy = vy - vy * w;
+    un = vn - vn * w;
+  } else {
+    const R inv_den = R(1) / (l0 + sqrt_(l0 * l0 + l1 * vn));
+    ux = vx * inv_den;
+    uy = vy * inv_den;
+    un = vn * inv_den;
+  }
+}
+
+// ---------------------------------------------------------------- collision of one node
+// Inputs: the pulled deviations fd[9], gd[5], hd[5]; node porosity phi and 1/phi; the Darcy
+// and Forchheimer coefficients a, b of Eq. (5); the previous-step fields (T - T0, C - C0, ux,
+// uy) in prev[4].  Outputs: post-collision deviations (in place) and the fields of this level in
+// prev[4], in the same form.
+// SC (FP16 storage): the populations stay in the units of the power-of-two pre-scale from
+// load to store, and the constants that enter the moments (rho0, T0, C0) carry the scale
+// (rho0_s, T0_s, C0_s); only the fields (T - T0, C - C0 and the velocity) are formed in
+// physical units.  A power of two commutes with every rounding here, so the arithmetic is that
+// of physical units, scaled exactly, without a multiply per population.
+template <typename R, bool SC>
+__device__ __forceinline__ void collide(const Desc<R> &d, R phi, R inv_phi, R a, R b, R *fd, R *gd, R *hd,
+                                        R *prev) {
   const R one = R(1), half = R(0.5);
   // density, momentum and scalars (Eqs. 16, 17, 26), deviation form
   const R sA = fd[1] + fd[2] + fd[3] + fd[4];
@@ -81,9 +119,10 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R jy = (fd[2] - fd[4]) + (fd[5] + fd[6]) - (fd[7] + fd[8]);
   const R sg = gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
   const R sh = hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
-  const R inv_phi = d.phi_field ? one / phi : d.inv_phi_u;
-  const R dT = sg * d.inv_sigma;          // T - T0
-  const R dC = sh * inv_phi;              // C - C0
+  const R dTs = sg * d.inv_sigma;         // T - T0 (scaled with SC)
+  const R dCs = sh * inv_phi;             // C - C0 (scaled with SC)
+  const R dT = SC ? dTs * d.inv_scale : dTs;
+  const R dC = SC ? dCs * d.inv_scale : dCs;
   // buoyancy (Eq. 6) plus any constant acceleration.  Both products are rounded before the
   // sum (no fused multiply-add), so that equal and opposite thermal and solutal terms cancel
   // exactly, as they do in Eq. (6)
@@ -96,15 +135,11 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
     Gy = d.gy + (bT + bC);
   }
   // explicit velocity (Eqs. 18-19), delta_t = 1
-  const R vx = jx * d.inv_rho0 + half * phi * Gx;
-  const R vy = jy * d.inv_rho0 + half * phi * Gy;
-  const R l0 = half + R(0.25) * a;
-  const R l1 = half * b;
-  const R vn = sqrt_(vx * vx + vy * vy);
-  const R inv_den = one / (l0 + sqrt_(l0 * l0 + l1 * vn));
-  const R ux = vx * inv_den, uy = vy * inv_den;
+  const R vx = jx * d.inv_rho0_s + half * phi * Gx;
+  const R vy = jy * d.inv_rho0_s + half * phi * Gy;
+  R ux, uy, un;
+  velocity_solve(a, b, vx, vy, ux, uy, un);
   const R u2 = ux * ux + uy * uy;
-  const R un = sqrt_(u2);
   // total force (Eq. 5)
   const R drag = a + b * un;
   const R Fx = phi * Gx - drag * ux;
@@ -118,7 +153,7 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   const R m7 = (fd[1] + fd[3]) - (fd[2] + fd[4]);
   const R m8 = (fd[5] + fd[7]) - (fd[6] + fd[8]);
   // equilibrium moments (Eq. 14, alpha1 = 1, alpha2 = -3) minus those of the rest state
-  const R r0 = d.rho0;
+  const R r0 = d.rho0_s;
   const R r0p = r0 * inv_phi;
   const R e1 = R(-2) * drho + R(3) * r0p * u2;
   const R e2 = drho - R(3) * r0p * u2;
@@ -171,44 +206,52 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   // of T itself does not enter; source moments N S~ = (0, d(T ux)/dt, d(T uy)/dt, 0, 0) from
   // Eq. (27) with d(T u)/dt = T0 (u - u_prev) + ((T - T0) u - (T - T0)_prev u_prev): the
   // difference of two nearly equal products T u is never formed
-  const R TuX = d.T0 * ux + dT * ux, TuY = d.T0 * uy + dT * uy;
-  const R CuX = d.C0 * ux + dC * ux, CuY = d.C0 * uy + dC * uy;
+  const R TuX = d.T0_s * ux + dTs * ux, TuY = d.T0_s * uy + dTs * uy;
+  const R CuX = d.C0_s * ux + dCs * ux, CuY = d.C0_s * uy + dCs * uy;
   const R dux = ux - prev[2], duy = uy - prev[3];
-  const R STx = d.T0 * dux + (dT * ux - prev[0] * prev[2]), STy = d.T0 * duy + (dT * uy - prev[0] * prev[3]);
-  const R SCx = d.C0 * dux + (dC * ux - prev[1] * prev[2]), SCy = d.C0 * duy + (dC * uy - prev[1] * prev[3]);
+  const R pT = SC ? prev[0] * d.scale : prev[0], pC = SC ? prev[1] * d.scale : prev[1];
+  const R STx = d.T0_s * dux + (dTs * ux - pT * prev[2]), STy = d.T0_s * duy + (dTs * uy - pT * prev[3]);
+  const R SCx = d.C0_s * dux + (dCs * ux - pC * prev[2]), SCy = d.C0_s * duy + (dCs * uy - pC * prev[3]);
   const R kh3 = !d.phi_field ? d.kh3_u : (d.model == 0 ? (d.c5v - R(4) * phi) : (d.c5v - R(4)) * phi);
+  // Both scalars collide as increments: the moment changes n* - n = -Theta (n - n^eq) +
+  // (I - Theta/2) S (the conserved zeroth moment does not change), taken back to populations by
+  // N^-1 and added to the pulled ones.  The rest population then gives up exactly what the other
+  // four gained, measured on their rounded values, so the stored sum (sigma T, phi C) keeps its
+  // value up to one rounding per step instead of one per addition of the whole populations.
   {
-    const R n0 = sg;
     const R n1 = gd[1] - gd[3], n2 = gd[2] - gd[4];
     const R n3 = R(-4) * gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
     const R n4 = gd[1] - gd[2] + gd[3] - gd[4];
-    const R q1 = n1 - d.z_a * (n1 - TuX) + (one - half * d.z_a) * STx;
-    const R q2 = n2 - d.z_a * (n2 - TuY) + (one - half * d.z_a) * STy;
-    const R q3 = n3 - d.z_e * (n3 - d.kg3 * dT);
-    const R q4 = n4 - d.z_eps * n4;
-    const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
-    gd[1] = b0 + b1 + b3 + b4;
-    gd[2] = b0 + b2 + b3 - b4;
-    gd[3] = b0 - b1 + b3 + b4;
-    gd[4] = b0 - b2 + b3 - b4;
-    gd[0] = n0 - ((gd[1] + gd[2]) + (gd[3] + gd[4]));   // conserved scalar, as for f
+    const R c1 = (one - half * d.z_a) * STx - d.z_a * (n1 - TuX);
+    const R c2 = (one - half * d.z_a) * STy - d.z_a * (n2 - TuY);
+    const R c3 = -d.z_e * (n3 - d.kg3 * dTs);
+    const R c4 = -d.z_eps * n4;
+    const R a13 = R(0.05) * c3 + R(0.25) * c4, a24 = R(0.05) * c3 - R(0.25) * c4;
+    const R g1 = gd[1] + (a13 + half * c1), g3 = gd[3] + (a13 - half * c1);
+    const R g2 = gd[2] + (a24 + half * c2), g4 = gd[4] + (a24 - half * c2);
+    gd[0] = gd[0] - (((g1 - gd[1]) + (g2 - gd[2])) + ((g3 - gd[3]) + (g4 - gd[4])));
+    gd[1] = g1;
+    gd[2] = g2;
+    gd[3] = g3;
+    gd[4] = g4;
   }
   {
     const R eD = d.e_D;
-    const R n0 = sh;
     const R n1 = hd[1] - hd[3], n2 = hd[2] - hd[4];
     const R n3 = R(-4) * hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
     const R n4 = hd[1] - hd[2] + hd[3] - hd[4];
-    const R q1 = n1 - eD * (n1 - CuX) + (one - half * eD) * SCx;
-    const R q2 = n2 - eD * (n2 - CuY) + (one - half * eD) * SCy;
-    const R q3 = n3 - d.e_e * (n3 - kh3 * dC);
-    const R q4 = n4 - d.e_eps * n4;
-    const R b0 = n0 * R(0.2), b1 = q1 * half, b2 = q2 * half, b3 = q3 * R(0.05), b4 = q4 * R(0.25);
-    hd[1] = b0 + b1 + b3 + b4;
-    hd[2] = b0 + b2 + b3 - b4;
-    hd[3] = b0 - b1 + b3 + b4;
-    hd[4] = b0 - b2 + b3 - b4;
-    hd[0] = n0 - ((hd[1] + hd[2]) + (hd[3] + hd[4]));
+    const R c1 = (one - half * eD) * SCx - eD * (n1 - CuX);
+    const R c2 = (one - half * eD) * SCy - eD * (n2 - CuY);
+    const R c3 = -d.e_e * (n3 - kh3 * dCs);
+    const R c4 = -d.e_eps * n4;
+    const R a13 = R(0.05) * c3 + R(0.25) * c4, a24 = R(0.05) * c3 - R(0.25) * c4;
+    const R h1 = hd[1] + (a13 + half * c1), h3 = hd[3] + (a13 - half * c1);
+    const R h2 = hd[2] + (a24 + half * c2), h4 = hd[4] + (a24 - half * c2);
+    hd[0] = hd[0] - (((h1 - hd[1]) + (h2 - hd[2])) + ((h3 - hd[3]) + (h4 - hd[4])));
+    hd[1] = h1;
+    hd[2] = h2;
+    hd[3] = h3;
+    hd[4] = h4;
   }
   prev[0] = dT;
   prev[1] = dC;
@@ -216,12 +259,13 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R a, R b, R *fd
   prev[3] = uy;
 }
 
-// Darcy and Forchheimer coefficients of Eq. (5) at a node
+// Darcy and Forchheimer coefficients of Eq. (5) at a node, and 1/phi
 template <typename R>
-__device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &b) {
+__device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &b, R &inv_phi) {
   if (!d.phi_field) {
     a = d.a_u;
     b = d.b_u;
+    inv_phi = d.inv_phi_u;
     return;
   }
   // K = Kscale phi^3/(1-phi)^2 (Kozeny-Carman shape of Eq. 7);
@@ -231,6 +275,7 @@ __device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &
   const R ip = R(1) / phi;
   a = d.ca * q * q * ip * ip;
   b = d.ergun ? d.cb * q * ip * ip : d.cb * q * rsqrt_(phi);
+  inv_phi = ip;
 }
 
 // ---------------------------------------------------------------- buffer memory access
@@ -328,8 +373,9 @@ template <>
 __device__ __forceinline__ double to_real(double v, double) { return v; }
 template <>
 __device__ __forceinline__ float to_real(float v, float) { return v; }
+// FP16 storage: the value stays in the units of the pre-scale (see collide)
 template <>
-__device__ __forceinline__ float to_real(_Float16 v, float inv_scale) { return (float)v * inv_scale; }
+__device__ __forceinline__ float to_real(_Float16 v, float) { return (float)v; }
 
 template <typename S>
 __device__ __forceinline__ S from_real(typename St<S>::R v, typename St<S>::R scale);
@@ -338,7 +384,11 @@ __device__ __forceinline__ double from_real(double v, double) { return v; }
 template <>
 __device__ __forceinline__ float from_real(float v, float) { return v; }
 template <>
-__device__ __forceinline__ _Float16 from_real(float v, float scale) { return (_Float16)(v * scale); }
+__device__ __forceinline__ _Float16 from_real(float v, float) { return (_Float16)v; }
+
+// populations of storage type S are collided in pre-scaled units (FP16 storage)
+template <typename S>
+constexpr bool kScaled = __is_same(S, _Float16);
 
 // ---------------------------------------------------------------- FP16 stochastic rounding
 // Round-to-nearest binary16 storage stagnates: a population that changes by less than half a
@@ -359,23 +409,21 @@ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
 }
 
 struct Dither {
-  uint32_t s, pool;
+  uint32_t s;
   int left;
-  __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step)) | 1u), pool(0), left(0) {}
-  // 13 fresh random bits in bits 19-31 (two values per xorshift32 draw: its bits 0-12,
-  // then 13-25)
+  __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step)) | 1u), left(0) {}
+  // 13 fresh random bits in bits 19-31, where the conversion reads them: two values per
+  // xorshift32 draw, its bits 19-31 as they stand, then its bits 6-18 shifted up
   __device__ __forceinline__ uint32_t next13() {
     if (left == 0) {
       s ^= s << 13;
       s ^= s >> 17;
       s ^= s << 5;
-      pool = s;
-      left = 2;
+      left = 1;
+      return s;
     }
-    const uint32_t r = pool << 19;
-    pool >>= 13;
-    --left;
-    return r;
+    left = 0;
+    return s << 13;
   }
 };
 
@@ -407,7 +455,8 @@ template <typename S, int CP>
 __device__ __forceinline__ void store_pop(typename St<S>::R v, typename St<S>::R scale, rsrc_t r, uint32_t voff,
                                           uint32_t soff, Dither &dz) {
   if constexpr (__is_same(S, _Float16)) {
-    PopIO<S, CP>::st(half_stochastic(v * scale, dz.next13()), r, voff, soff);
+    (void)scale;   // v is already in the units of the pre-scale
+    PopIO<S, CP>::st(half_stochastic(v, dz.next13()), r, voff, soff);
   } else {
     (void)dz;
     PopIO<S, CP>::st(from_real<S>(v, scale), r, voff, soff);
@@ -469,10 +518,8 @@ __device__ __forceinline__ void node_fields(const Desc<R> &d, R phi, R a, R b, c
   }
   const R vx = jx * d.inv_rho0 + half * phi * d.gx;
   const R vy = jy * d.inv_rho0 + half * phi * Gy;
-  const R l0 = half + R(0.25) * a, l1 = half * b;
-  const R inv_den = R(1) / (l0 + sqrt_(l0 * l0 + l1 * sqrt_(vx * vx + vy * vy)));
-  ux = vx * inv_den;
-  uy = vy * inv_den;
+  R un;
+  velocity_solve(a, b, vx, vy, ux, uy, un);
 }
 
 // deviation-form equilibria: Eq. (20) minus w_i rho0; Eq. (28) (or the Model-A form) minus
@@ -536,7 +583,7 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   } else {
     side = bx ? sx : sy;
     kind = pick(k0, k1, k2, k3, side);
-    const R uw = pick(d.uw[0], d.uw[1], d.uw[2], d.uw[3], side) * R(1.0 / 6.0);
+    const R uw = pick(d.uwall[0], d.uwall[1], d.uwall[2], d.uwall[3], side);
     if (bx) uby = uw;
     else ubx = uw;
   }
@@ -549,6 +596,21 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   R ff[9], gf[5], hf[5], f2[9], g2[5], h2[5];
   pull(xf, yf, ff, gf, hf);
   pull(xff, yff, f2, g2, h2);
+  if constexpr (kScaled<S>) {
+    // the rule works in physical units; FP16 pulls carry the pre-scale
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      ff[i] *= d.inv_scale;
+      f2[i] *= d.inv_scale;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      gf[i] *= d.inv_scale;
+      hf[i] *= d.inv_scale;
+      g2[i] *= d.inv_scale;
+      h2[i] *= d.inv_scale;
+    }
+  }
   R phif = d.phi_u, phiff = d.phi_u;
   phib = d.phi_u;
   if (d.phi_field) {
@@ -560,8 +622,8 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
 #pragma unroll
     for (int k = 0; k < 4; ++k) prev[k] = FieldIO<S, CP>::ld(rs.d4, cb, (uint32_t)k * PR);
   }
-  R af, bf;
-  porous_coeffs(d, phif, af, bf);
+  R af, bf, ipf;
+  porous_coeffs(d, phif, af, bf, ipf);
   R drho, uxf, uyf, dTf, dCf;
   node_fields(d, phif, af, bf, ff, gf, hf, drho, uxf, uyf, dTf, dCf);
   R dTb = pick(d.Tfix[0], d.Tfix[1], d.Tfix[2], d.Tfix[3], side);
@@ -591,6 +653,15 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
   seq_dev(d, dCf, d.C0 + dCf, uxf, uyf, h0f, d.model == 0 ? R(1) : phif, sf);
 #pragma unroll
   for (int i = 0; i < 5; ++i) hd[i] = sb[i] + (hf[i] - sf[i]);
+  if constexpr (kScaled<S>) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fd[i] *= d.scale;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      gd[i] *= d.scale;
+      hd[i] *= d.scale;
+    }
+  }
 }
 
 // Second half of a node update: collision (moment space) with the previous-step fields
@@ -598,15 +669,16 @@ __device__ __forceinline__ void nee_boundary(const Desc<typename St<S>::R> &d, c
 // stores.
 template <typename S, int CP>
 __device__ __forceinline__ void collide_store_ab(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
-                                                 uint32_t step, typename St<S>::R phi, typename St<S>::R a,
-                                                 typename St<S>::R b, typename St<S>::R *fd, typename St<S>::R *gd,
-                                                 typename St<S>::R *hd, typename St<S>::R *prev) {
+                                                 uint32_t step, typename St<S>::R phi, typename St<S>::R inv_phi,
+                                                 typename St<S>::R a, typename St<S>::R b, typename St<S>::R *fd,
+                                                 typename St<S>::R *gd, typename St<S>::R *hd,
+                                                 typename St<S>::R *prev) {
   using R = typename St<S>::R;
   constexpr uint32_t ES = sizeof(S), RS = sizeof(R);
   const uint32_t PB = (uint32_t)d.plane * ES;
   const uint32_t PR = (uint32_t)d.plane * RS;
   const uint32_t cr = c * RS;
-  collide(d, phi, a, b, fd, gd, hd, prev);
+  collide<R, kScaled<S>>(d, phi, inv_phi, a, b, fd, gd, hd, prev);
   const R sc = d.scale;
   const uint32_t co = c * ES;
   Dither dz(c, step);
@@ -628,9 +700,9 @@ template <typename S, int CP>
 __device__ __forceinline__ void collide_store(const Desc<typename St<S>::R> &d, const StepRes &rs, uint32_t c,
                                               uint32_t step, typename St<S>::R phi, typename St<S>::R *fd,
                                               typename St<S>::R *gd, typename St<S>::R *hd, typename St<S>::R *prev) {
-  typename St<S>::R a, b;
-  porous_coeffs(d, phi, a, b);
-  collide_store_ab<S, CP>(d, rs, c, step, phi, a, b, fd, gd, hd, prev);
+  typename St<S>::R a, b, ip;
+  porous_coeffs(d, phi, a, b, ip);
+  collide_store_ab<S, CP>(d, rs, c, step, phi, ip, a, b, fd, gd, hd, prev);
 }
 
 // Second half of an interior or half-way-wall node update: previous-step fields, then
@@ -832,8 +904,11 @@ __host__ __device__ inline int nee_nodes(int nx, int ny, bool perx, bool pery) {
 // are the tiles.  Both read only the previous level and write disjoint nodes, so the
 // perimeter work overlaps the tiles within the one launch.
 template <typename S, int CP>
-__global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, int tile_y, int ntx, int parity,
-                                                   int nperim) {
+__global__ void __launch_bounds__(256) step_kernel(const Desc<typename St<S>::R> *__restrict__ dp, int tile_y, int ntx,
+                                                   int parity, int nperim) {
+  // the descriptor is read from device memory as fields are needed (passed by value, all of it
+  // would be loaded into scalar registers at entry and spilled)
+  const Desc<typename St<S>::R> &d = *dp;
   const int cur = (d.base_parity ^ parity) & 1;
   const StepRes rs = step_resources<S>(d, cur);
   if ((int)blockIdx.x < nperim) {
@@ -862,21 +937,41 @@ __global__ void __launch_bounds__(256) step_kernel(Desc<typename St<S>::R> d, in
 // FP32 64 x 8 51.3 GLUPS against 46.9 for 32 x 16 and 43.7 for 32 x 8; FP16 64 x 8 60.5
 // against 52.2; FP64 32 x 8 24.9 against 21.8 for 32 x 16 and 22.9 for 64 x 8, its LDS being
 // twice as large)
-template <typename S>
-struct TwoStep {
-  static constexpr int W = 64, H = 8;
+template <int W_, int H_>
+struct Shape2 {
+  static constexpr int W = W_, H = H_;
   static constexpr int RW = W + 2, RH = H + 2, RN = RW * RH, THREADS = W * H;
+};
+template <typename S>
+struct TwoStepOf {
+  using T = Shape2<64, 8>;
 };
 template <>
-struct TwoStep<double> {
-  static constexpr int W = 32, H = 8;
-  static constexpr int RW = W + 2, RH = H + 2, RN = RW * RH, THREADS = W * H;
+struct TwoStepOf<double> {
+  using T = Shape2<32, 8>;
 };
+template <typename S>
+using TwoStep = typename TwoStepOf<S>::T;
+// The tile shapes a batched two-step launch may take (chosen per group by the batch
+// autotuner; the first is the single-cavity tile): narrower tiles waste fewer lanes on
+// cavities whose width is not a multiple of 64 (32) nodes.
+template <typename S, int K>
+struct BatchShape {
+  using T = typename std::conditional<K == 0, Shape2<64, 8>,
+                                      typename std::conditional<K == 1, Shape2<32, 16>, Shape2<32, 8>>::type>::type;
+};
+template <int K>
+struct BatchShape<double, K> {
+  using T = typename std::conditional<K == 0, Shape2<32, 8>,
+                                      typename std::conditional<K == 1, Shape2<16, 16>, Shape2<16, 8>>::type>::type;
+};
+constexpr int kBatchShapes = 3;
 
 template <typename S>
 __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R scale, Dither &dz) {
   if constexpr (__is_same(S, _Float16)) {
-    return half_stochastic(v * scale, dz.next13());
+    (void)scale;   // v is already in the units of the pre-scale
+    return half_stochastic(v, dz.next13());
   } else {
     (void)dz;
     return from_real<S>(v, scale);
@@ -891,13 +986,13 @@ __device__ __forceinline__ S to_store(typename St<S>::R v, typename St<S>::R sca
 // its f and ff and their upstream nodes (up to three nodes inward and one along the wall)
 // lie in the tile's region, which the caller guarantees by placing the last tile of a row or
 // column against the far wall (tiles then overlap and write equal values twice).
-template <typename S, int CP, bool NEE>
+template <typename S, int CP, bool NEE, typename SH = TwoStep<S>>
 __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
-                                              S (*lpop)[TwoStep<S>::RN]) {
+                                              S (*lpop)[SH::RN]) {
   using R = typename St<S>::R;
   using FIO = FieldIO<S, CP>;
-  constexpr int TS_W = TwoStep<S>::W, TS_H = TwoStep<S>::H, TS_RW = TwoStep<S>::RW, TS_RH = TwoStep<S>::RH;
-  constexpr int TS_THREADS = TwoStep<S>::THREADS;
+  constexpr int TS_W = SH::W, TS_H = SH::H, TS_RW = SH::RW, TS_RH = SH::RH;
+  constexpr int TS_THREADS = SH::THREADS;
   constexpr uint32_t RS = sizeof(R);
   const uint32_t PR = (uint32_t)d.plane * RS;
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -942,12 +1037,13 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
 #pragma unroll
       for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
     }
-    R a, bb;
-    porous_coeffs(d, phi, a, bb);
+    R a, bb, ip;
+    porous_coeffs(d, phi, a, bb, ip);
     pab[0] = phi;
     pab[1] = a;
     pab[2] = bb;
-    collide(d, phi, a, bb, fd, gd, hd, prev);
+    pab[3] = ip;
+    collide<R, kScaled<S>>(d, phi, ip, a, bb, fd, gd, hd, prev);
     Dither dz(c, step);
 #pragma unroll
     for (int i = 0; i < 9; ++i) lpop[i][r] = to_store<S>(fd[i], sc, dz);
@@ -960,7 +1056,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
   // most one node of the halo ring: rows ly = 0 and TS_RH - 1, then columns lx = 0 and
   // TS_RW - 1 without the corners
   const int tx = (int)threadIdx.x % TS_W, ty = (int)threadIdx.x / TS_W;
-  R prev[4], pab[3];
+  R prev[4], pab[4];
   step_one(tx + 1, ty + 1, prev, pab);
   constexpr int NHALO = 2 * TS_RW + 2 * TS_H;
   static_assert(NHALO <= TS_THREADS, "one halo node per thread at most");
@@ -975,7 +1071,7 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
       hx = q < TS_H ? 0 : TS_RW - 1;
       hy = 1 + q % TS_H;
     }
-    R unused[4], unused_pab[3];
+    R unused[4], unused_pab[4];
     step_one(hx, hy, unused, unused_pab);
   }
   __syncthreads();
@@ -1047,14 +1143,16 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
     // the node's porosity and porous coefficients, as step one computed them (a boundary
     // node's too: the rule reads the same porosity)
     rs.d4 = fwrite;
-    collide_store_ab<S, CP>(d, rs, c, step + 1u, pab[0], pab[1], pab[2], fd, gd, hd, prev);
+    collide_store_ab<S, CP>(d, rs, c, step + 1u, pab[0], pab[3], pab[1], pab[2], fd, gd, hd, prev);
   }
 }
 
 // NEE: the last tile of each row and column is placed against the far side (nx >= W and
 // ny >= H, checked by the launcher)
 template <typename S, int CP, bool NEE>
-__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(Desc<typename St<S>::R> d, int ntx, int parity) {
+__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
+                                                                    int ntx, int parity) {
+  const Desc<typename St<S>::R> &d = *dp;
   __shared__ S lpop[NPOP][TwoStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int x0 = (b % ntx) * TwoStep<S>::W, y0 = (b / ntx) * TwoStep<S>::H;
@@ -1145,12 +1243,13 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
     else gather_global<S, CP, false>(d, rs, X, Y, fd, gd, hd);
 #pragma unroll
     for (int k = 0; k < 4; ++k) prev[k] = FIO::ld(fread, c * RS, (uint32_t)k * PR);
-    R a, bb;
-    porous_coeffs(d, phi, a, bb);
+    R a, bb, ip;
+    porous_coeffs(d, phi, a, bb, ip);
     pab[0] = phi;
     pab[1] = a;
     pab[2] = bb;
-    collide(d, phi, a, bb, fd, gd, hd, prev);
+    pab[3] = ip;
+    collide<R, kScaled<S>>(d, phi, ip, a, bb, fd, gd, hd, prev);
     lds_store(ly * RW + lx, c, step, fd, gd, hd);
   };
   // pulls of region node (lx, ly) = domain node (X, Y) from LDS, with the wall rules
@@ -1224,7 +1323,7 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   }
 
   // step one: own node, then the ring node
-  R prev[4], pab[3], prev1[4], pab1[3];
+  R prev[4], pab[4], prev1[4], pab1[4];
   step_one(tx + 2, ty + 2, prev, pab);
   if (ring1 || ring2) step_one(rx, ry, prev1, pab1);
   __syncthreads();
@@ -1240,11 +1339,11 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   if (r1_in) lds_pulls(rx, ry, X1, Y1, f1, g1, h1);
   __syncthreads();
   if (own_in) {
-    collide(d, pab[0], pab[1], pab[2], fd, gd, hd, prev);
+    collide<R, kScaled<S>>(d, pab[0], pab[3], pab[1], pab[2], fd, gd, hd, prev);
     lds_store((ty + 2) * RW + tx + 2, (uint32_t)Y * pitch + X, step + 1u, fd, gd, hd);
   }
   if (r1_in) {
-    collide(d, pab1[0], pab1[1], pab1[2], f1, g1, h1, prev1);
+    collide<R, kScaled<S>>(d, pab1[0], pab1[3], pab1[1], pab1[2], f1, g1, h1, prev1);
     lds_store(ry * RW + rx, (uint32_t)Y1 * pitch + X1, step + 1u, f1, g1, h1);
   }
   __syncthreads();
@@ -1253,31 +1352,33 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   if (x0 + tx < nx && y0 + ty < ny) {
     lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd);
     rs.d4 = fwrite;
-    collide_store_ab<S, CP>(d, rs, (uint32_t)Y * pitch + X, step + 2u, pab[0], pab[1], pab[2], fd, gd, hd, prev);
+    collide_store_ab<S, CP>(d, rs, (uint32_t)Y * pitch + X, step + 2u, pab[0], pab[3], pab[1], pab[2], fd, gd, hd,
+                            prev);
   }
 }
 
 template <typename S, int CP>
-__global__ void __launch_bounds__(ThreeStep<S>::THREADS) step3_kernel(Desc<typename St<S>::R> d, int ntx,
-                                                                      int parity) {
+__global__ void __launch_bounds__(ThreeStep<S>::THREADS) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
+                                                                      int ntx, int parity) {
+  const Desc<typename St<S>::R> &d = *dp;
   __shared__ S lpop[NPOP][ThreeStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   three_step_tile<S, CP>(d, (b % ntx) * ThreeStep<S>::W, (b / ntx) * ThreeStep<S>::H, parity, lpop);
 }
 
-// Batched two steps over items of W x H tiles (item.tw = W): one item per work-group (a
-// loop over items keeps values live across iterations and costs a third of the occupancy);
-// the grid may exceed the item count, the extra work-groups exit at once.
-template <typename S, int CP>
-__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_batch_kernel(
-    const Desc<typename St<S>::R> *__restrict__ descs, const Item *__restrict__ items,
-    const int *__restrict__ range, int parity) {
-  __shared__ S lpop[NPOP][TwoStep<S>::RN];
+// Batched two steps over items of W x H tiles (item.tw = W, the group's shape SH): one item per
+// work-group (a loop over items keeps values live across iterations and costs a third of the
+// occupancy); the grid may exceed the item count, the extra work-groups exit at once.
+template <typename S, int CP, typename SH>
+__global__ void __launch_bounds__(SH::THREADS) step2_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs,
+                                                                  const Item *__restrict__ items,
+                                                                  const int *__restrict__ range, int parity) {
+  __shared__ S lpop[NPOP][SH::RN];
   const int first = range[0], n = range[1];
   if ((int)blockIdx.x >= n) return;
   const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
   const Item item = items[first + it];
-  two_step_tile<S, CP, false>(descs[item.cavity], item.x0, item.y0, parity, lpop);
+  two_step_tile<S, CP, false, SH>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1367,19 +1468,20 @@ __global__ void __launch_bounds__(256) init_kernel(Desc<typename St<S>::R> d, co
   prev[2] = (R)ux;
   prev[3] = (R)uy;
   // the stored populations of level 0 are rounded to the storage type before colliding,
-  // exactly as a pulled value would be
+  // exactly as a pulled value would be (FP16: in the units of the pre-scale, as the step
+  // kernels collide them)
   const R is = d.inv_scale, sc = d.scale;
-  S tmp;
-  for (int i = 0; i < 9; ++i) { St<S>::st(&tmp, fd[i], sc); fd[i] = St<S>::ld(&tmp, is); }
-  for (int i = 0; i < 5; ++i) { St<S>::st(&tmp, gd[i], sc); gd[i] = St<S>::ld(&tmp, is); }
-  for (int i = 0; i < 5; ++i) { St<S>::st(&tmp, hd[i], sc); hd[i] = St<S>::ld(&tmp, is); }
-  R a, b;
-  porous_coeffs(d, (R)phi, a, b);
-  collide(d, (R)phi, a, b, fd, gd, hd, prev);
+  auto rnd = [&](R v) -> R { return to_real<S>(from_real<S>(kScaled<S> ? v * sc : v, sc), is); };
+  for (int i = 0; i < 9; ++i) fd[i] = rnd(fd[i]);
+  for (int i = 0; i < 5; ++i) gd[i] = rnd(gd[i]);
+  for (int i = 0; i < 5; ++i) hd[i] = rnd(hd[i]);
+  R a, b, ip;
+  porous_coeffs(d, (R)phi, a, b, ip);
+  collide<R, kScaled<S>>(d, (R)phi, ip, a, b, fd, gd, hd, prev);
   S *dst = (S *)(d.base_parity ? d.pop1 : d.pop0);
-  for (int i = 0; i < 9; ++i) St<S>::st(dst + i * P + c, fd[i], sc);
-  for (int i = 0; i < 5; ++i) St<S>::st(dst + (9 + i) * P + c, gd[i], sc);
-  for (int i = 0; i < 5; ++i) St<S>::st(dst + (14 + i) * P + c, hd[i], sc);
+  for (int i = 0; i < 9; ++i) dst[i * P + c] = from_real<S>(fd[i], sc);
+  for (int i = 0; i < 5; ++i) dst[(9 + i) * P + c] = from_real<S>(gd[i], sc);
+  for (int i = 0; i < 5; ++i) dst[(14 + i) * P + c] = from_real<S>(hd[i], sc);
   R *d4 = (R *)d.d4;
   d4[c] = prev[0];
   d4[P + c] = prev[1];
@@ -1580,7 +1682,7 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
 }
 
 template <typename S, int CP>
-static void step_cp(const Desc<typename St<S>::R> &d, Tile tile, int parity, hipStream_t stream) {
+static void step_cp(const Desc<typename St<S>::R> &d, const void *ddev, Tile tile, int parity, hipStream_t stream) {
   // with walls through the nodes the last column / row is perimeter work: the tiles need
   // only cover [0, n - 1) (node 0 is skipped inside its tile)
   const int ex = d.nee && !d.perx ? 1 : 0, ey = d.nee && !d.pery ? 1 : 0;
@@ -1588,33 +1690,34 @@ static void step_cp(const Desc<typename St<S>::R> &d, Tile tile, int parity, hip
   const int nty = (d.ny - ey + tile.ty - 1) / tile.ty;
   int nperim = 0;
   if (d.nee) nperim = ((nee_nodes(d.nx, d.ny, d.perx != 0, d.pery != 0) + tile.tx - 1) / tile.tx + 7) / 8 * 8;
-  hipLaunchKernelGGL((step_kernel<S, CP>), dim3(nperim + ntx * nty), dim3(tile.tx), 0, stream, d, tile.ty, ntx,
-                     parity, nperim);
+  hipLaunchKernelGGL((step_kernel<S, CP>), dim3(nperim + ntx * nty), dim3(tile.tx), 0, stream,
+                     (const Desc<typename St<S>::R> *)ddev, tile.ty, ntx, parity, nperim);
 }
 
 template <typename S>
-static int step_t(const void *desc, Tile tile, int cp, int parity, void *stream) {
+static int step_t(const void *desc, const void *ddev, Tile tile, int cp, int parity, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   hipStream_t s = (hipStream_t)stream;
   switch (cp) {
-    case CP_STREAM: step_cp<S, CP_STREAM>(d, tile, parity, s); break;
-    case CP_RESIDENT: step_cp<S, CP_RESIDENT>(d, tile, parity, s); break;
-    default: step_cp<S, CP_TUNED>(d, tile, parity, s); break;
+    case CP_STREAM: step_cp<S, CP_STREAM>(d, ddev, tile, parity, s); break;
+    case CP_RESIDENT: step_cp<S, CP_RESIDENT>(d, ddev, tile, parity, s); break;
+    default: step_cp<S, CP_TUNED>(d, ddev, tile, parity, s); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step(int prec, const void *desc, Tile tile, int cp, int parity, void *stream) {
+int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp, int parity, void *stream) {
   switch (prec) {
-    case PREC_FP64: return step_t<double>(desc, tile, cp, parity, stream);
-    case PREC_FP32: return step_t<float>(desc, tile, cp, parity, stream);
-    default: return step_t<_Float16>(desc, tile, cp, parity, stream);
+    case PREC_FP64: return step_t<double>(desc, ddev, tile, cp, parity, stream);
+    case PREC_FP32: return step_t<float>(desc, ddev, tile, cp, parity, stream);
+    default: return step_t<_Float16>(desc, ddev, tile, cp, parity, stream);
   }
 }
 
 template <typename S>
-static int step2_t(const void *desc, int cp, int parity, void *stream) {
+static int step2_t(const void *desc, const void *ddev, int cp, int parity, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
   constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
@@ -1628,88 +1731,99 @@ static int step2_t(const void *desc, int cp, int parity, void *stream) {
       if (d.nx < W || d.ny < H) return (int)hipErrorInvalidValue;
       switch (cp) {
         case CP_STREAM:
-          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, d, ntx, parity);
+          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, dp, ntx, parity);
           break;
         case CP_RESIDENT:
-          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, d, ntx, parity);
+          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, dp, ntx, parity);
           break;
-        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, d, ntx, parity); break;
+        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, dp, ntx, parity); break;
       }
       return (int)hipGetLastError();
     }
   }
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, dp, ntx, parity); break;
     case CP_RESIDENT:
-      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, d, ntx, parity);
+      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, dp, ntx, parity);
       break;
-    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, d, ntx, parity); break;
+    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, dp, ntx, parity); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step2(int prec, const void *desc, int cp, int parity, void *stream) {
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream) {
   switch (prec) {
-    case PREC_FP64: return step2_t<double>(desc, cp, parity, stream);
-    case PREC_FP32: return step2_t<float>(desc, cp, parity, stream);
-    default: return step2_t<_Float16>(desc, cp, parity, stream);
+    case PREC_FP64: return step2_t<double>(desc, ddev, cp, parity, stream);
+    case PREC_FP32: return step2_t<float>(desc, ddev, cp, parity, stream);
+    default: return step2_t<_Float16>(desc, ddev, cp, parity, stream);
   }
 }
 
 template <typename S>
-static int step3_t(const void *desc, int cp, int parity, void *stream) {
+static int step3_t(const void *desc, const void *ddev, int cp, int parity, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
+  const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
   constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H;
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
   const dim3 grid(ntx * nty), block(ThreeStep<S>::THREADS);
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, d, ntx, parity); break;
-    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, d, ntx, parity); break;
-    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, d, ntx, parity); break;
+    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, dp, ntx, parity); break;
+    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, dp, ntx, parity); break;
+    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, dp, ntx, parity); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step3(int prec, const void *desc, int cp, int parity, void *stream) {
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream) {
   const auto nee = [&](auto *dp) { return dp->nee != 0; };
   switch (prec) {
     case PREC_FP64:
       if (nee((const Desc<double> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<double>(desc, cp, parity, stream);
+      return step3_t<double>(desc, ddev, cp, parity, stream);
     case PREC_FP32:
       if (nee((const Desc<float> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<float>(desc, cp, parity, stream);
+      return step3_t<float>(desc, ddev, cp, parity, stream);
     default: return (int)hipErrorInvalidValue;   // FP16 storage: one or two steps per launch
   }
 }
 
-template <typename S>
-static void batch2_t(int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
-                     hipStream_t s) {
-  using D = Desc<typename St<S>::R>;
-  const D *dd = (const D *)descs;
-  const dim3 block(TwoStep<S>::THREADS);
+template <typename S, typename SH>
+static void batch2_shape(int cp, const Desc<typename St<S>::R> *dd, const Item *items, const int *range, int grid,
+                         int parity, hipStream_t s) {
+  const dim3 block(SH::THREADS);
   switch (cp) {
     case CP_STREAM:
-      hipLaunchKernelGGL((step2_batch_kernel<S, CP_STREAM>), dim3(grid), block, 0, s, dd, items, range, parity);
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_STREAM, SH>), dim3(grid), block, 0, s, dd, items, range, parity);
       break;
     case CP_RESIDENT:
-      hipLaunchKernelGGL((step2_batch_kernel<S, CP_RESIDENT>), dim3(grid), block, 0, s, dd, items, range, parity);
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_RESIDENT, SH>), dim3(grid), block, 0, s, dd, items, range, parity);
       break;
     default:
-      hipLaunchKernelGGL((step2_batch_kernel<S, CP_TUNED>), dim3(grid), block, 0, s, dd, items, range, parity);
+      hipLaunchKernelGGL((step2_batch_kernel<S, CP_TUNED, SH>), dim3(grid), block, 0, s, dd, items, range, parity);
       break;
   }
 }
 
-int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+template <typename S>
+static void batch2_t(int cp, int shape, const void *descs, const Item *items, const int *range, int grid, int parity,
+                     hipStream_t s) {
+  using D = Desc<typename St<S>::R>;
+  const D *dd = (const D *)descs;
+  switch (shape) {
+    case 1: batch2_shape<S, typename BatchShape<S, 1>::T>(cp, dd, items, range, grid, parity, s); break;
+    case 2: batch2_shape<S, typename BatchShape<S, 2>::T>(cp, dd, items, range, grid, parity, s); break;
+    default: batch2_shape<S, typename BatchShape<S, 0>::T>(cp, dd, items, range, grid, parity, s); break;
+  }
+}
+
+int launch_step2_batch(int prec, int cp, int shape, const void *descs, const Item *items, const int *range, int grid,
                        int parity, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
-    case PREC_FP64: batch2_t<double>(cp, descs, items, range, grid, parity, s); break;
-    case PREC_FP32: batch2_t<float>(cp, descs, items, range, grid, parity, s); break;
-    default: batch2_t<_Float16>(cp, descs, items, range, grid, parity, s); break;
+    case PREC_FP64: batch2_t<double>(cp, shape, descs, items, range, grid, parity, s); break;
+    case PREC_FP32: batch2_t<float>(cp, shape, descs, items, range, grid, parity, s); break;
+    default: batch2_t<_Float16>(cp, shape, descs, items, range, grid, parity, s); break;
   }
   return (int)hipGetLastError();
 }
@@ -1717,6 +1831,27 @@ int launch_step2_batch(int prec, int cp, const void *descs, const Item *items, c
 void two_step_tile_shape(int prec, int *w, int *h) {
   *w = prec == PREC_FP64 ? TwoStep<double>::W : TwoStep<float>::W;
   *h = prec == PREC_FP64 ? TwoStep<double>::H : TwoStep<float>::H;
+}
+
+template <typename S, int K>
+static void shape_of(int *w, int *h) {
+  *w = BatchShape<S, K>::T::W;
+  *h = BatchShape<S, K>::T::H;
+}
+
+int batch_tile_shapes() { return kBatchShapes; }
+
+void batch_tile_shape(int prec, int shape, int *w, int *h) {
+  const int k = shape < 0 || shape >= kBatchShapes ? 0 : shape;
+  if (prec == PREC_FP64) {
+    if (k == 0) shape_of<double, 0>(w, h);
+    else if (k == 1) shape_of<double, 1>(w, h);
+    else shape_of<double, 2>(w, h);
+  } else {
+    if (k == 0) shape_of<float, 0>(w, h);
+    else if (k == 1) shape_of<float, 1>(w, h);
+    else shape_of<float, 2>(w, h);
+  }
 }
 
 template <typename S>

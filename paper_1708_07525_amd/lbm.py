@@ -24,14 +24,17 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-    "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_derive", "lbm_state_bytes", "lbm_get_state",
+    "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_derive",
+    "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state",
     "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_steps_per_launch",
     "lbm_get_steps_per_launch", "lbm_set_graph_chunk",
     "lbm_autotune", "lbm_last_error", "lbm_destroy",
-    "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_size",
-    "lbm_batch_destroy",
+    "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_autotune",
+    "lbm_batch_set_tile", "lbm_batch_size", "lbm_batch_destroy",
 )
+PRECISION_NAMES = ("fp64", "fp32", "fp16s")
+BATCH_CLASSES = ("<=64", "<=128", "<=256", ">256")
 
 
 class LbmError(RuntimeError):
@@ -125,6 +128,9 @@ def lib():
         L.lbm_batch_attach.argtypes = [_VP, _VP]
         L.lbm_batch_detach.argtypes = [_VP, _VP]
         L.lbm_batch_step.argtypes = [_VP, ctypes.c_int64]
+        L.lbm_batch_autotune.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_batch_set_tile.argtypes = [_VP] + [ctypes.c_int32] * 4
         L.lbm_batch_size.argtypes = [_VP]
         L.lbm_batch_size.restype = ctypes.c_int32
         L.lbm_batch_destroy.argtypes = [_VP]
@@ -340,6 +346,23 @@ class Batch:
 
     def step(self, n: int):
         _check(lib().lbm_batch_step(self._h, int(n)), None, "lbm_batch_step")
+
+    def autotune(self, steps: int = 20) -> dict:
+        """lbm_batch_autotune: the tile shape index and cache policy chosen for each precision
+        and size class present, as {(precision, class): (shape, policy)}."""
+        shapes = (ctypes.c_int32 * 12)(*([-1] * 12))
+        pols = (ctypes.c_int32 * 12)(*([-1] * 12))
+        _check(lib().lbm_batch_autotune(self._h, int(steps), shapes, pols), None, "lbm_batch_autotune")
+        out = {}
+        for i in range(12):
+            if shapes[i] >= 0:
+                out[(PRECISION_NAMES[i // 4], BATCH_CLASSES[i % 4])] = (int(shapes[i]), int(pols[i]))
+        return out
+
+    def set_tile(self, precision: str, size_class: int, shape: int, policy: int = -1):
+        """lbm_batch_set_tile: the launch choice of one precision and size class."""
+        _check(lib().lbm_batch_set_tile(self._h, PRECISION[precision], int(size_class), int(shape), int(policy)),
+               None, "lbm_batch_set_tile")
 
     def __len__(self):
         return int(lib().lbm_batch_size(self._h))

@@ -65,11 +65,13 @@ def converged(ob: dict, tol: float, quiet_speed: float) -> bool:
 class Server:
     """budget_bytes: device memory the resident cavities may use; max_slots: batch capacity;
     chunk: steps per graph replay; check_every: steps between residual checks (a multiple of
-    chunk); tol, max_steps: stopping rule.  ``backend`` supplies Solver, Batch and
+    chunk); tol, max_steps: stopping rule; autotune_steps > 0: tune the batched launch
+    (lbm_batch_autotune) once, on the first resident set.  ``backend`` supplies Solver, Batch and
     footprint_bytes (the GPU library by default; tests of the bookkeeping pass a stand-in)."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, chunk: int = 100, check_every: int = 1000,
-                 tol: float = 1e-8, max_steps: int = 100000, keep_fields: bool = False, backend=None):
+                 tol: float = 1e-8, max_steps: int = 100000, keep_fields: bool = False, backend=None,
+                 autotune_steps: int = 0):
         self.be = backend if backend is not None else _lbm
         if check_every % chunk:
             raise ValueError("check_every must be a multiple of chunk")
@@ -80,6 +82,8 @@ class Server:
         self.tol = float(tol)
         self.max_steps = int(max_steps)
         self.keep_fields = keep_fields
+        self.autotune_steps = int(autotune_steps)
+        self.tuned = False
         self.batch = self.be.Batch(max_slots, chunk=chunk)
         self.solo = set()     # ids of resident solvers that the batch does not take
         self.used = 0
@@ -133,6 +137,11 @@ class Server:
                     time.sleep(max(0.0, min(pending[0][0] - (clock() - t0), 0.01)))
                 continue
             if len(self.solo) < len(self.active):
+                if self.autotune_steps and not self.tuned:
+                    # launch choices of the batch (tile shape, cache policy per precision and
+                    # size class), timed once on the first resident set; states are restored
+                    self.batch.autotune(self.autotune_steps)
+                    self.tuned = True
                 self.batch.step(self.chunk)
             for a in self.active:
                 if id(a[0]) in self.solo:

@@ -478,6 +478,49 @@ def test_batch_alone_vs_mix_bitwise():
     b.close()
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2, "auto"])
+def test_batch_tile_shapes_change_nothing(shape):
+    """Every tile shape of the batched two-step launch, and the autotuner's choice, gives each
+    cavity the state it reaches alone, bit for bit (cavities of all four size classes and the
+    three storage types; widths that are not multiples of the tiles)."""
+    from paper_1708_07525_amd import Batch
+    Solver = _solver()
+    specs = [(workloads.cavity_params(nx=40, ny=52), "fp32"),
+             (workloads.cavity_params(nx=96, ny=70, Ra=1e5, N=-1.0, phi=0.5), "fp32"),
+             (workloads.cavity_params(nx=200, ny=100, Ra=3e4), "fp16s"),
+             (workloads.cavity_params(nx=300, ny=45, Ra=2e4, Le=3.0), "fp64"),
+             (workloads.cavity_params(nx=72, ny=72, Ra=5e3), "fp64")]
+    steps = 208     # two replays of 100 steps and 8 more
+    alone = []
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (11, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        s.step(steps)
+        alone.append(s.get_state())
+        s.close()
+    b = Batch(len(specs), chunk=100)
+    mix = []
+    for i, (p, prec) in enumerate(specs):
+        T, C = workloads.noise_fields(p["nx"], p["ny"], (11, i))
+        s = Solver(p, T=T, C=C, precision=prec)
+        b.attach(s)
+        mix.append(s)
+    if shape == "auto":
+        chosen = b.autotune(8)
+        print("batch autotune:", chosen, flush=True)
+        assert set(chosen) == {("fp32", "<=64"), ("fp32", "<=128"), ("fp16s", "<=256"), ("fp64", ">256"),
+                               ("fp64", "<=128")}
+    else:
+        for prec in ("fp64", "fp32", "fp16s"):
+            for cls in range(4):
+                b.set_tile(prec, cls, shape, -1)
+    b.step(steps)
+    for s, ref in zip(mix, alone):
+        d = _state_diff(s.get_state(), ref)
+        assert d is None, (shape, s.nx, s.ny, s.precision, d)
+    b.close()
+
+
 def test_autotuned_tile_is_cached_and_changes_nothing(tmp_path, monkeypatch):
     from paper_1708_07525_amd import autotune
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(tmp_path / "tiles.json"))
