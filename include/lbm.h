@@ -168,6 +168,19 @@ typedef struct lbm_obs {
  * Returns LBM_EUNSTABLE (after filling *out) when a value is not finite. */
 lbm_status lbm_observables(struct lbm_ctx *c, lbm_obs *out, double *fields);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc): lbm_observables with no allocation at all.  Same arguments, results and errors
+ * as lbm_observables (the same kernels, bit for bit the same values), but the per-block partial
+ * sums, the result slots and the staging of the exported fields live in a fixed device array
+ * of the library (about 42 MB per device, held until the process ends) instead of the
+ * context's memory and a buffer allocated per call.  Limits: at most 16384 rows (partials of
+ * the reduction), and with fields != NULL at most 1048576 nodes (nx*ny); larger lattices are
+ * refused with LBM_EINVAL.  Every context on a device shares that device's array and it keeps
+ * the last call's contents (every value a call reads is written by the same call first): calls
+ * that overlap in time on one device, from several threads or on several streams, race and must
+ * be serialised by the caller.  Synchronises the context's stream. */
+lbm_status lbm_observables_static(struct lbm_ctx *c, lbm_obs *out, double *fields);
+
 /* Export of the FP64 fields rho, ux, uy, T, C of the current level (5*nx*ny doubles, in that
  * order, each ny rows of nx) without touching the residual snapshot.  Synchronises. */
 lbm_status lbm_get_fields(struct lbm_ctx *c, double *fields);

@@ -90,6 +90,7 @@ struct lbm_ctx {
   bool owned = false;
   bool ready = false;
   bool unstable = false;     // lbm_observables found a non-finite value: lbm_step refuses to go on
+  double *scratch = nullptr; // device address of the fixed scratch on this context's device
   bool in_batch = false;
   int cur = 0;               // buffer holding the post-collision state of the current level
   int d4cur = 0;             // field buffer (d4 or d4b) holding the fields of the current level
@@ -521,6 +522,11 @@ LBM_API lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
     delete c;
     return LBM_EDEVICE;
   }
+  // the fixed scratch of lbm_observables_static: its address on this (current) device
+  if (static_scratch_address(c->device, &c->scratch) != (int)hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
   if (p->arena) {
     if (p->arena_bytes < c->lay.total || ((uintptr_t)p->arena & 255)) {
       delete c;
@@ -857,6 +863,20 @@ LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
   if (!c || !out) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables before lbm_set_fields");
   return observe(c, out, fields, c->partials(), c->obs_out(), nullptr);
+}
+
+LBM_API lbm_status lbm_observables_static(lbm_ctx *c, lbm_obs *out, double *fields) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables_static before lbm_set_fields");
+  if (!c->scratch) return fail(c, LBM_EDEVICE, "no fixed scratch on this device");
+  const StaticScratchLayout L = static_scratch_layout();
+  if (c->p.ny > L.max_rows)
+    return fail(c, LBM_EINVAL, "lbm_observables_static serves lattices of at most %d rows (this one has %d)",
+                L.max_rows, c->p.ny);
+  if (fields && (long long)c->p.nx * c->p.ny > L.max_nodes)
+    return fail(c, LBM_EINVAL, "lbm_observables_static exports the fields of lattices of at most %lld nodes "
+                "(this one has %lld)", L.max_nodes, (long long)c->p.nx * c->p.ny);
+  return observe(c, out, fields, c->scratch + L.partials, c->scratch + L.out, c->scratch + L.fields);
 }
 
 LBM_API lbm_status lbm_get_derived(const lbm_ctx *c, lbm_derived *out) {

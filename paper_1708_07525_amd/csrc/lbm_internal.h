@@ -110,5 +110,15 @@ int launch_observables(int prec, const void *desc, int parity, void *snap, doubl
 int launch_export(int prec, const void *desc, int parity, double *fields, void *stream);
 int observables_blocks(int ny);
 
+// Fixed device scratch of the no-allocation observables (offsets in doubles)
+struct StaticScratchLayout {
+  int max_rows;              // tallest lattice whose observables partials fit
+  long long max_nodes;       // largest lattice whose exported fields fit
+  long long out, partials, fields, doubles;
+};
+StaticScratchLayout static_scratch_layout();
+// device address of the scratch array on `device`, which must be current (looked up once per
+// device); hipError_t as int
+int static_scratch_address(int device, double **ptr);
 
 }  // namespace lbmk

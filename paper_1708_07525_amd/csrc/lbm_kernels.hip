@@ -26,6 +26,7 @@
 // one step's loads and stores per launch.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lbm_internal.h"
@@ -1906,6 +1907,50 @@ int launch_observables(int prec, const void *desc, int parity, void *snap, doubl
     case PREC_FP32: return obs_t<float>(desc, parity, snap, partials, nblocks, out, wT, wC, LdT, LdC, stream);
     default: return obs_t<_Float16>(desc, parity, snap, partials, nblocks, out, wT, wC, LdT, LdC, stream);
   }
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of lbm_observables_static, for callers that cannot allocate: the result slots,
+// the per-block partial sums of the observables of a lattice of up to kStaticRows rows, and the
+// staging of the exported FP64 fields of a lattice of up to kStaticNodes nodes.  One copy per
+// device, held until the process ends, shared by every context on that device.
+constexpr int kStaticRows = 16384;
+constexpr long long kStaticNodes = 1LL << 20;
+constexpr long long kStaticOut = 32;
+constexpr long long kStaticPartials = (long long)((kStaticRows + OBS_ROWS - 1) / OBS_ROWS) * NSLOT;
+constexpr long long kStaticDoubles = kStaticOut + kStaticPartials + 5 * kStaticNodes;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+StaticScratchLayout static_scratch_layout() {
+  StaticScratchLayout l;
+  l.max_rows = kStaticRows;
+  l.max_nodes = kStaticNodes;
+  l.out = 0;
+  l.partials = kStaticOut;
+  l.fields = kStaticOut + kStaticPartials;
+  l.doubles = kStaticDoubles;
+  return l;
+}
+
+// The address of `scratch` on `device`, which must be the current device: looked up with
+// hipGetSymbolAddress on the first call for that device and kept per device (each device holds
+// its own copy of the array at its own address).  In host code the name `scratch` is only a
+// stand-in: the address returned here is the one kernels and copies must use.
+int static_scratch_address(int device, double **ptr) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    addr[device] = (double *)p;
+  }
+  *ptr = addr[device];
+  return (int)hipSuccess;
 }
 
 template <typename S>

@@ -24,7 +24,7 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_footprint_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-    "lbm_observables", "lbm_get_fields", "lbm_get_derived", "lbm_derive",
+    "lbm_observables", "lbm_observables_static", "lbm_get_fields", "lbm_get_derived", "lbm_derive",
     "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state",
     "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_steps_per_launch",
@@ -100,6 +100,7 @@ def lib():
         L.lbm_set_fields.argtypes = [_VP, _D, _D, _D, _D, _D]
         L.lbm_step.argtypes = [_VP, ctypes.c_int64]
         L.lbm_observables.argtypes = [_VP, ctypes.POINTER(Obs), _D]
+        L.lbm_observables_static.argtypes = [_VP, ctypes.POINTER(Obs), _D]
         L.lbm_get_fields.argtypes = [_VP, _D]
         L.lbm_get_derived.argtypes = [_VP, ctypes.POINTER(Derived)]
         L.lbm_derive.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Derived)]
@@ -243,12 +244,15 @@ class Solver:
     def step(self, n: int = 1):
         _check(lib().lbm_step(self._h, int(n)), self._h, "lbm_step")
 
-    def observables(self, fields: bool = False):
+    def observables(self, fields: bool = False, static: bool = False):
+        """lbm_observables, or with ``static`` lbm_observables_static (no device allocation;
+        the library's fixed scratch)."""
         o = Obs()
         buf = np.empty((5, self.ny, self.nx)) if fields else None
-        rc = lib().lbm_observables(self._h, ctypes.byref(o), _ptr(buf))
+        fn = lib().lbm_observables_static if static else lib().lbm_observables
+        rc = fn(self._h, ctypes.byref(o), _ptr(buf))
         if rc not in (OK, EUNSTABLE):
-            _check(rc, self._h, "lbm_observables")
+            _check(rc, self._h, "lbm_observables_static" if static else "lbm_observables")
         ob = dict(step=o.step, Nu=list(o.Nu), Sh=list(o.Sh), mass=o.mass, heat=o.heat, solute=o.solute,
                   max_ux=o.max_ux, max_uy=o.max_uy, r_u=o.r_u, r_T=o.r_T, r_C=o.r_C,
                   nonfinite=bool(o.nonfinite), status=rc)
