@@ -35,7 +35,7 @@ DEFAULTS = dict(
     Th=1.0, Tl=0.0, Ch=1.0, Cl=0.0,
     Fphi=-1.0, g_ext=(0.0, 0.0), wall_u=(0.0, 0.0, 0.0, 0.0),
     direct=0, nu=0.0, alpha_e=0.0, D_e=0.0, K=0.0, gbT=0.0, gbC=0.0, Bi_T=0.0, Bi_C=0.0,
-    Re=0.0, Gr=0.0, U0=0.0,
+    Re=0.0, Gr=0.0, U0=0.0, nee_link=0,
 )
 
 
@@ -58,6 +58,7 @@ class _Params(ctypes.Structure):
         ("K", ctypes.c_double), ("gbT", ctypes.c_double), ("gbC", ctypes.c_double),
         ("Bi_T", ctypes.c_double), ("Bi_C", ctypes.c_double),
         ("Re", ctypes.c_double), ("Gr", ctypes.c_double), ("U0", ctypes.c_double),
+        ("nee_link", ctypes.c_int32),
     ]
 
 

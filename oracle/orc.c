@@ -665,6 +665,41 @@ static void apply_nee(orc *o) {
       for (int i = 0; i < 9; ++i) val[m * 19 + i] = eb[i] + (o->f[i * nn + kf] - ef[i]);
       for (int i = 0; i < 5; ++i) val[m * 19 + 9 + i] = gb[i] + (o->g[i * nn + kf] - gf[i]);
       for (int i = 0; i < 5; ++i) val[m * 19 + 14 + i] = hb[i] + (o->h[i * nn + kf] - hf[i]);
+      if (p->nee_link) {
+        /* Eq. (33) read along each link: a population that streamed in from a node inside the
+           domain keeps its value; one that would come from outside takes the extrapolation from
+           x_f = x_b + e_i (the normal neighbour above when that node is outside too) */
+        for (int i = 0; i < 9; ++i) {
+          const int ux_ = x - EX[i], uy_ = y - EY[i];
+          const int in_up = (ux_ >= 0 && ux_ < nx) || !wx ? ((uy_ >= 0 && uy_ < ny) || !wy) : 0;
+          if (in_up) {
+            val[m * 19 + i] = o->f[i * nn + kb];
+            if (i < 5) {
+              val[m * 19 + 9 + i] = o->g[i * nn + kb];
+              val[m * 19 + 14 + i] = o->h[i * nn + kb];
+            }
+            continue;
+          }
+          const int lx = x + EX[i], ly = y + EY[i];
+          if (lx < 0 || lx >= nx || ly < 0 || ly >= ny) continue;   /* keep the normal-neighbour value */
+          const long kl = (long)ly * nx + lx;
+          node_macro ql;
+          node_fields(o, kl, &ql);
+          const double phil = o->phi[kl];
+          double el[9], e2[9], gl[5], g2[5], hl[5], h2[5];
+          feq9(ql.rho, ubx, uby, phib, p->rho0, el);
+          feq9(ql.rho, ql.ux, ql.uy, phil, p->rho0, e2);
+          val[m * 19 + i] = el[i] + (o->f[i * nn + kl] - e2[i]);
+          if (i < 5) {
+            geq5(Tb, ubx, uby, p->sigma, o->varpi, p->model, gl);
+            geq5(ql.T, ql.ux, ql.uy, p->sigma, o->varpi, p->model, g2);
+            geq5(Cb, ubx, uby, phib, o->varpi, p->model, hl);
+            geq5(ql.C, ql.ux, ql.uy, phil, o->varpi, p->model, h2);
+            val[m * 19 + 9 + i] = gl[i] + (o->g[i * nn + kl] - g2[i]);
+            val[m * 19 + 14 + i] = hl[i] + (o->h[i * nn + kl] - h2[i]);
+          }
+        }
+      }
       m++;
     }
   for (long j = 0; j < nb; ++j) {

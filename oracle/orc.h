@@ -68,6 +68,10 @@ typedef struct orc_params {
                                             g*beta_T and g*beta_C, used when direct == 1 */
   double Bi_T, Bi_C;          /* Biot numbers of a convective side (Eq. 39); ambient Tl, Cl */
   double Re, Gr, U0;          /* Reynolds and Grashof numbers and the lid speed (direct == 2) */
+  int32_t nee_link;           /* walls through the nodes, reading of Eq. (33): 0: every population
+                                 of the boundary node from the neighbour along the inward normal;
+                                 1: only the populations streaming in from outside, each from
+                                 the neighbour along its own link, x_f = x_b + e_i */
 } orc_params;
 
 typedef struct orc orc;

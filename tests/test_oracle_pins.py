@@ -483,3 +483,16 @@ def test_nee_brinkman_poiseuille_second_order():
 
 def test_nee_cavity_centro_symmetry():
     assert pins.cavity_symmetry(make_oracle, sides=pins.NODE_CAVITY) < 1e-12
+
+
+def test_node_wall_reading_along_the_normal():
+    """Reading of Eq. (33): the boundary node's populations come from the neighbour along the
+    inward normal (all nine), not from x_b + e_i for each incoming population alone (the
+    literal wording, switch nee_link).  Only the first keeps linear conduction through the walls
+    exact and node-wall Poiseuille flow at its second-order accuracy; the second leaves a 4e-3
+    error in the linear profile and a 4.5 times larger Poiseuille error."""
+    eT, _, _, _ = pins.nee_conduction(make_oracle)
+    link = lambda p, **f: Oracle(dict(p, nee_link=1), **f)
+    eT_link, _, _, _ = pins.nee_conduction(link)
+    assert eT < 1e-12 and eT_link > 1e-3
+    assert pins.nee_poiseuille(link, 17) > 3 * pins.nee_poiseuille(make_oracle, 17)
