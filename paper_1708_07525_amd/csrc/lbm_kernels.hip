@@ -77,20 +77,25 @@ __device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
 // (a ~ 1e-3 per step is common), so rounding the constant l0 to FP32 (c up to 6e-8) costs
 // 1e-5 - 1e-4 of the velocity after some thousand steps; this form keeps c at the size of
 // the rounding of e, a ten-thousandth of that.  FP64 keeps the direct form.
+// In FP32 the two quotients and the two roots use the hardware reciprocal and square root
+// (1 ulp): each result only enters as a small correction (l1 |v|/(l0 + ...), e/(1 + e) ~ a/2)
+// or as the speed of the Forchheimer term, so their last-bit errors shift the velocity by
+// about 1e-7 of a/2 (< 1e-10 relative), far below what the 1/a amplification would show.
 template <typename R>
 __device__ __forceinline__ void velocity_solve(R a, R b, R vx, R vy, R &ux, R &uy, R &un) {
   const R half = R(0.5);
   const R l0 = half + R(0.25) * a;
   const R l1 = half * b;
-  const R vn = sqrt_(vx * vx + vy * vy);
   if constexpr (sizeof(R) == 4) {
+    const R vn = __builtin_amdgcn_sqrtf(vx * vx + vy * vy);
     const R l1v = l1 * vn;
-    const R e = half * a + l1v / (l0 + sqrt_(l0 * l0 + l1v));
-    const R w = e / (R(1) + e);
+    const R e = half * a + l1v * __builtin_amdgcn_rcpf(l0 + __builtin_amdgcn_sqrtf(l0 * l0 + l1v));
+    const R w = e * __builtin_amdgcn_rcpf(R(1) + e);
     ux = vx - vx * w;
     uy = vy - vy * w;
     un = vn - vn * w;
   } else {
+    const R vn = sqrt_(vx * vx + vy * vy);
     const R inv_den = R(1) / (l0 + sqrt_(l0 * l0 + l1 * vn));
     ux = vx * inv_den;
     uy = vy * inv_den;
