@@ -413,9 +413,33 @@ def serve(a):
            "requests": summ["requests"], "converged": summ["converged"], "rate_per_s": round(rate, 3),
            "closed_loop_capacity_per_s": round(capacity, 3), "step_cap": cap, "tol": 1e-8,
            "higher_is_better": False, "data": "synthetic"}
+    # per precision: converged count, time-to-solution of the converged requests, the residual
+    # reached by the others, and the slowest diffusive time L^2 max(sigma/alpha_e, phi/D_e) of
+    # the scalars (in steps), which sets how long a request needs to settle
+    from paper_1708_07525_amd import lbm as _l
+    by_id = {r.id: r for r in reqs}
+
+    def pct(v, q):
+        return round(float(np.percentile(v, q)), 4) if len(v) else None
+
+    def t_slow(req):
+        d = _l.derive(req.params, req.precision)
+        return d["L"] ** 2 * max(req.params.get("sigma", 1.0) / d["alpha_e"], req.params.get("phi", 1.0) / d["D_e"])
+
+    out["by_precision"] = {}
+    for prec in ("fp32", "fp16s"):
+        rs = [r for r in results if r.precision == prec]
+        conv = [r for r in rs if r.converged]
+        rest = [r for r in rs if not r.converged]
+        out["by_precision"][prec] = dict(
+            requests=len(rs), converged=len(conv),
+            converged_p50_s=pct([r.latency for r in conv], 50), converged_p99_s=pct([r.latency for r in conv], 99),
+            converged_steps_p50=pct([r.steps for r in conv], 50),
+            unconverged_r_u_p10_p50_p90=[pct([r.obs["r_u"] for r in rest], q) for q in (10, 50, 90)],
+            t_slow_steps_p50_converged=pct([t_slow(by_id[r.id]) for r in conv], 50),
+            t_slow_steps_p50_unconverged=pct([t_slow(by_id[r.id]) for r in rest], 50))
     if a.oracle_samples > 0:
         import oracle
-        by_id = {r.id: r for r in reqs}
         errs = []
         picks = sorted((r for r in results if r.nodes <= 256 * 256), key=lambda r: (r.nodes, r.id))
         for res in picks[:a.oracle_samples]:

@@ -360,6 +360,13 @@ lbm_status finish_mapping(lbm_ctx *c, double phi_min, double mean_kc) {
     D.e_D = (R)d.eta_D;
     D.e_e = (R)p->eta_e;
     D.e_eps = (R)p->eta_eps;
+    D.k_e = R(1) - R(0.5) * D.s_e;
+    D.k_eps = R(1) - R(0.5) * D.s_eps;
+    D.k_j = R(1) - R(0.5) * D.s_j;
+    D.k_q = R(1) - R(0.5) * D.s_q;
+    D.k_v = R(1) - R(0.5) * D.s_v;
+    D.k_za = R(1) - R(0.5) * D.z_a;
+    D.k_eD = R(1) - R(0.5) * D.e_D;
     D.gbT = (R)d.gbT;
     D.gbC = (R)d.gbC;
     D.gx = (R)p->g_ext[0];

@@ -45,6 +45,8 @@ struct Desc {
   R rho0, inv_rho0, sigma, inv_sigma, varpi, T0, C0;
   R s_e, s_eps, s_j, s_q, s_v;
   R z_a, z_e, z_eps, e_D, e_e, e_eps;
+  R k_e, k_eps, k_j, k_q, k_v, k_za, k_eD;   // forcing weights 1 - s/2 of Eq. (10) and of the
+                                             // D2Q5 source (Eq. 27) for the rates above
   R gbT, gbC, gx, gy;
   R phi_u, a_u, b_u;       // uniform porosity: phi, Darcy a = phi nu/K, Forchheimer b = phi F/sqrt(K)
   R ca, cb;                // porosity field: a = ca (1-phi)^2/phi^2; b = cb (1-phi)/phi^2 (Ergun)

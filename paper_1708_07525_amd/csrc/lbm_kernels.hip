@@ -62,6 +62,14 @@ __device__ __forceinline__ double rsqrt_(double v) { return 1.0 / sqrt(v); }
 template <>
 __device__ __forceinline__ float rsqrt_(float v) { return 1.0f / sqrtf(v); }
 
+// 1/v and 1/sqrt(v) of a porosity in the porous coefficients: in FP32 the hardware
+// reciprocal and reciprocal square root (1 ulp), whose error is far below the storage
+// rounding of the populations; exact quotients in FP64
+__device__ __forceinline__ double recip_(double v) { return 1.0 / v; }
+__device__ __forceinline__ float recip_(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rsqrt_fast(double v) { return 1.0 / sqrt(v); }
+__device__ __forceinline__ float rsqrt_fast(float v) { return __builtin_amdgcn_rsqf(v); }
+
 template <typename R>
 __device__ __forceinline__ R sqrt_(R v);
 template <>
@@ -116,7 +124,7 @@ __device__ __forceinline__ void velocity_solve(R a, R b, R vx, R vy, R &ux, R &u
 template <typename R, bool SC>
 __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R inv_phi, R a, R b, R *fd, R *gd, R *hd,
                                         R *prev) {
-  const R one = R(1), half = R(0.5);
+  const R half = R(0.5);
   // density, momentum and scalars (Eqs. 16, 17, 26), deviation form
   const R sA = fd[1] + fd[2] + fd[3] + fd[4];
   const R sD = fd[5] + fd[6] + fd[7] + fd[8];
@@ -173,14 +181,14 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R inv_phi, R a,
   const R S8 = r0p * (ux * Fy + uy * Fx);
   // relaxation (Eq. 10): m* = m - s (m - meq) + (1 - s/2) S
   const R p0 = drho;
-  const R p1 = m1 - d.s_e * (m1 - e1) + (one - half * d.s_e) * S1;
-  const R p2 = m2 - d.s_eps * (m2 - e2) - (one - half * d.s_eps) * S1;
-  const R p3 = jx - d.s_j * (jx - jxe) + (one - half * d.s_j) * S3;
-  const R p4 = m4 - d.s_q * (m4 + jxe) - (one - half * d.s_q) * S3;
-  const R p5 = jy - d.s_j * (jy - jye) + (one - half * d.s_j) * S5;
-  const R p6 = m6 - d.s_q * (m6 + jye) - (one - half * d.s_q) * S5;
-  const R p7 = m7 - d.s_v * (m7 - e7) + (one - half * d.s_v) * S7;
-  const R p8 = m8 - d.s_v * (m8 - e8) + (one - half * d.s_v) * S8;
+  const R p1 = m1 - d.s_e * (m1 - e1) + d.k_e * S1;
+  const R p2 = m2 - d.s_eps * (m2 - e2) - d.k_eps * S1;
+  const R p3 = jx - d.s_j * (jx - jxe) + d.k_j * S3;
+  const R p4 = m4 - d.s_q * (m4 + jxe) - d.k_q * S3;
+  const R p5 = jy - d.s_j * (jy - jye) + d.k_j * S5;
+  const R p6 = m6 - d.s_q * (m6 + jye) - d.k_q * S5;
+  const R p7 = m7 - d.s_v * (m7 - e7) + d.k_v * S7;
+  const R p8 = m8 - d.s_v * (m8 - e8) + d.k_v * S8;
   // f* = M^-1 m*
   const R a0 = p0 * R(1.0 / 9.0);
   const R a1 = p1 * R(1.0 / 36.0);
@@ -228,8 +236,8 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R inv_phi, R a,
     const R n1 = gd[1] - gd[3], n2 = gd[2] - gd[4];
     const R n3 = R(-4) * gd[0] + gd[1] + gd[2] + gd[3] + gd[4];
     const R n4 = gd[1] - gd[2] + gd[3] - gd[4];
-    const R c1 = (one - half * d.z_a) * STx - d.z_a * (n1 - TuX);
-    const R c2 = (one - half * d.z_a) * STy - d.z_a * (n2 - TuY);
+    const R c1 = d.k_za * STx - d.z_a * (n1 - TuX);
+    const R c2 = d.k_za * STy - d.z_a * (n2 - TuY);
     const R c3 = -d.z_e * (n3 - d.kg3 * dTs);
     const R c4 = -d.z_eps * n4;
     const R a13 = R(0.05) * c3 + R(0.25) * c4, a24 = R(0.05) * c3 - R(0.25) * c4;
@@ -246,8 +254,8 @@ __device__ __forceinline__ void collide(const Desc<R> &d, R phi, R inv_phi, R a,
     const R n1 = hd[1] - hd[3], n2 = hd[2] - hd[4];
     const R n3 = R(-4) * hd[0] + hd[1] + hd[2] + hd[3] + hd[4];
     const R n4 = hd[1] - hd[2] + hd[3] - hd[4];
-    const R c1 = (one - half * eD) * SCx - eD * (n1 - CuX);
-    const R c2 = (one - half * eD) * SCy - eD * (n2 - CuY);
+    const R c1 = d.k_eD * SCx - eD * (n1 - CuX);
+    const R c2 = d.k_eD * SCy - eD * (n2 - CuY);
     const R c3 = -d.e_e * (n3 - kh3 * dCs);
     const R c4 = -d.e_eps * n4;
     const R a13 = R(0.05) * c3 + R(0.25) * c4, a24 = R(0.05) * c3 - R(0.25) * c4;
@@ -278,9 +286,9 @@ __device__ __forceinline__ void porous_coeffs(const Desc<R> &d, R phi, R &a, R &
   // a = phi nu/K = ca (1-phi)^2/phi^2;  Ergun F = 1.75/sqrt(150 phi^3):
   // b = phi F/sqrt(K) = cb (1-phi)/phi^2;  fixed F: b = cb (1-phi)/sqrt(phi)
   const R q = R(1) - phi;
-  const R ip = R(1) / phi;
+  const R ip = recip_(phi);
   a = d.ca * q * q * ip * ip;
-  b = d.ergun ? d.cb * q * ip * ip : d.cb * q * rsqrt_(phi);
+  b = d.ergun ? d.cb * q * ip * ip : d.cb * q * rsqrt_fast(phi);
   inv_phi = ip;
 }
 
@@ -405,9 +413,13 @@ constexpr bool kScaled = __is_same(S, _Float16);
 // bits are aligned with the dropped bits; a value of magnitude 65504 or more goes to the
 // infinity the non-finite check looks for, stochastically below 65536).  The instruction
 // takes its 13 random bits from bits 19-31 of its operand.  The random bits are a function
-// of (node, step) only -- the hash of Jarzynski & Olano, "Hash functions for GPU
-// rendering" (JCGT 2020, PCG-based), seeding Marsaglia's xorshift32 -- so results are
-// reproducible and do not depend on the launch shape or on the other cavities of a batch.
+// of (node, step, population) only, so results are reproducible and do not depend on the
+// launch shape or on the other cavities of a batch: one uniform 32-bit word per node and
+// step from the PCG-based hash of Jarzynski & Olano, "Hash functions for GPU rendering"
+// (JCGT 2020), and for the i-th stored population of the node that word plus i times the
+// 32-bit golden-ratio constant (a Weyl sequence, one addition per value).  Each value's bits
+// are uniform and independent of the value, which is all the unbiased rounding needs; the
+// values of one node share one draw, spread over the unit interval by the Weyl offsets.
 __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
   const uint32_t state = v * 747796405u + 2891336453u;
   const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
@@ -416,27 +428,17 @@ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
 
 struct Dither {
   uint32_t s;
-  int left;
-  __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step)) | 1u), left(0) {}
-  // 13 fresh random bits in bits 19-31, where the conversion reads them: two values per
-  // xorshift32 draw, its bits 19-31 as they stand, then its bits 6-18 shifted up
-  __device__ __forceinline__ uint32_t next13() {
-    if (left == 0) {
-      s ^= s << 13;
-      s ^= s >> 17;
-      s ^= s << 5;
-      left = 1;
-      return s;
-    }
-    left = 0;
-    return s << 13;
-  }
+  uint32_t k;
+  __device__ __forceinline__ Dither(uint32_t node, uint32_t step) : s(pcg_hash(node ^ pcg_hash(step))), k(0) {}
+  // random bits for the next population of the node (the calls come in population order)
+  __device__ __forceinline__ uint32_t next13() { return s + (++k) * 0x9E3779B9u; }
 };
 
 __device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r13_hi) {
   typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-  half2_t z = {(_Float16)0, (_Float16)0};
-  return __builtin_amdgcn_cvt_sr_f16_f32(z, v, r13_hi, false)[0];
+  // the conversion writes the low half and keeps the high half of its first operand, which
+  // is never read: pass the random word so that no register has to be cleared for it
+  return __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, r13_hi), v, r13_hi, false)[0];
 }
 
 // resources of one cavity for one step
