@@ -1190,11 +1190,18 @@ struct ThreeStep {
   static constexpr int RW = W + 4, RH = H + 4, RN = RW * RH, THREADS = W * H;
   static constexpr int N1 = 2 * (W + 2) + 2 * H;        // inner ring
   static constexpr int N2 = 2 * RW + 2 * (H + 2);       // outer ring
+  // FP32: 80 VGPRs and 51 KB of LDS let three work-groups (24 waves) share a CU
+  static constexpr int MIN_WAVES_PER_EU = sizeof(S) == 4 ? 6 : 1;
 };
+
+// LDS plane of moving population i (0-8 f, 9-13 g, 14-18 h) when the rest populations f0,
+// g0, h0 stay in registers: the 16 moving populations in order
+__host__ __device__ constexpr int lp(int i) { return i - 1 - (i > 9 ? 1 : 0) - (i > 14 ? 1 : 0); }
 
 template <typename S, int CP>
 __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
                                                 S (*lpop)[ThreeStep<S>::RN]) {
+  static_assert(!kScaled<S>, "three steps per launch: FP32 and FP64 storage");
   using R = typename St<S>::R;
   using FIO = FieldIO<S, CP>;
   constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H, RW = ThreeStep<S>::RW, RH = ThreeStep<S>::RH;
@@ -1210,7 +1217,7 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   rs.d4 = fread;
   const uint32_t step = d.counter[cur];
   if (x0 == 0 && y0 == 0 && threadIdx.x == 0) d.counter[cur ^ 1] = step + 3u;
-  const R is = d.inv_scale, sc = d.scale;
+
   // the region and every node it pulls from lie inside the domain
   const bool interior = x0 >= 3 && x0 + W + 2 <= nx - 1 && y0 >= 3 && y0 + H + 2 <= ny - 1;
 
@@ -1229,18 +1236,22 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
     }
     return true;
   };
-  auto lds_store = [&](int r, uint32_t c, uint32_t stp, const R *fd, const R *gd, const R *hd) {
-    Dither dz(c, stp);
+  // the rest populations f0, g0, h0 are pulled only by their own node, whose thread keeps
+  // them in registers (rest[3]); LDS holds the 16 moving populations (plane lp(i))
+  auto lds_store = [&](int r, const R *fd, const R *gd, const R *hd, R *rest) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lpop[i][r] = to_store<S>(fd[i], sc, dz);
+    for (int i = 1; i < 9; ++i) lpop[lp(i)][r] = (S)fd[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lpop[9 + i][r] = to_store<S>(gd[i], sc, dz);
+    for (int i = 1; i < 5; ++i) lpop[lp(9 + i)][r] = (S)gd[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lpop[14 + i][r] = to_store<S>(hd[i], sc, dz);
+    for (int i = 1; i < 5; ++i) lpop[lp(14 + i)][r] = (S)hd[i];
+    rest[0] = fd[0];
+    rest[1] = gd[0];
+    rest[2] = hd[0];
   };
   // step one at region node (lx, ly): populations into LDS, fields into prev, porosity and
   // porous coefficients into pab
-  auto step_one = [&](int lx, int ly, R *prev, R *pab) {
+  auto step_one = [&](int lx, int ly, R *prev, R *pab, R *rest) {
     int X, Y;
     if (!locate(lx, ly, X, Y)) return;     // beyond a wall: never read
     const uint32_t c = (uint32_t)Y * pitch + X;
@@ -1258,16 +1269,19 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
     pab[2] = bb;
     pab[3] = ip;
     collide<R, kScaled<S>>(d, phi, ip, a, bb, fd, gd, hd, prev);
-    lds_store(ly * RW + lx, c, step, fd, gd, hd);
+    lds_store(ly * RW + lx, fd, gd, hd, rest);
   };
   // pulls of region node (lx, ly) = domain node (X, Y) from LDS, with the wall rules
-  auto lds_pulls = [&](int lx, int ly, int X, int Y, R *fd, R *gd, R *hd) {
+  auto lds_pulls = [&](int lx, int ly, int X, int Y, R *fd, R *gd, R *hd, const R *rest) {
     const int r = ly * RW + lx;
-    auto L = [&](int pl, int off) -> R { return to_real<S>(lpop[pl][r + off], is); };
+    auto L = [&](int pl, int off) -> R { return (R)lpop[lp(pl)][r + off]; };
+    fd[0] = rest[0];
+    gd[0] = rest[1];
+    hd[0] = rest[2];
     if (interior) {
       const int off[5] = {0, -1, -RW, 1, RW};
 #pragma unroll
-      for (int i = 0; i < 5; ++i) {
+      for (int i = 1; i < 5; ++i) {
         fd[i] = L(i, off[i]);
         gd[i] = L(9 + i, off[i]);
         hd[i] = L(14 + i, off[i]);
@@ -1281,7 +1295,6 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
     const bool okxm = (X > 0) | d.perx, okxp = (X < nx - 1) | d.perx;
     const bool okym = (Y > 0) | d.pery, okyp = (Y < ny - 1) | d.pery;
     const bool ok5 = okxm & okym, ok6 = okxp & okym, ok7 = okxp & okyp, ok8 = okxm & okyp;
-    fd[0] = L(0, 0);
     fd[1] = okxm ? L(1, -1) : L(3, 0);
     fd[2] = okym ? L(2, -RW) : L(4, 0);
     fd[3] = okxp ? L(3, 1) : L(1, 0);
@@ -1294,7 +1307,6 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
     for (int q = 0; q < 2; ++q) {
       R *e = q ? hd : gd;
       const int p = q ? 14 : 9;
-      e[0] = L(p, 0);
       e[1] = okxm ? L(p + 1, -1) : L(p + 3, 0);
       e[2] = okym ? L(p + 2, -RW) : L(p + 4, 0);
       e[3] = okxp ? L(p + 3, 1) : L(p + 1, 0);
@@ -1331,9 +1343,9 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   }
 
   // step one: own node, then the ring node
-  R prev[4], pab[4], prev1[4], pab1[4];
-  step_one(tx + 2, ty + 2, prev, pab);
-  if (ring1 || ring2) step_one(rx, ry, prev1, pab1);
+  R prev[4], pab[4], prev1[4], pab1[4], rest[3], rest1[3];
+  step_one(tx + 2, ty + 2, prev, pab, rest);
+  if (ring1 || ring2) step_one(rx, ry, prev1, pab1, rest1);
   __syncthreads();
 
   // step two, in place: read the pulls of the own node and of an inner-ring node, then write.
@@ -1343,22 +1355,22 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   const bool own_in = locate(tx + 2, ty + 2, X, Y);
   const bool r1_in = ring1 && locate(rx, ry, X1, Y1);
   R fd[9], gd[5], hd[5], f1[9], g1[5], h1[5];
-  if (own_in) lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd);
-  if (r1_in) lds_pulls(rx, ry, X1, Y1, f1, g1, h1);
+  if (own_in) lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd, rest);
+  if (r1_in) lds_pulls(rx, ry, X1, Y1, f1, g1, h1, rest1);
   __syncthreads();
   if (own_in) {
     collide<R, kScaled<S>>(d, pab[0], pab[3], pab[1], pab[2], fd, gd, hd, prev);
-    lds_store((ty + 2) * RW + tx + 2, (uint32_t)Y * pitch + X, step + 1u, fd, gd, hd);
+    lds_store((ty + 2) * RW + tx + 2, fd, gd, hd, rest);
   }
   if (r1_in) {
     collide<R, kScaled<S>>(d, pab1[0], pab1[3], pab1[1], pab1[2], f1, g1, h1, prev1);
-    lds_store(ry * RW + rx, (uint32_t)Y1 * pitch + X1, step + 1u, f1, g1, h1);
+    lds_store(ry * RW + rx, f1, g1, h1, rest1);
   }
   __syncthreads();
 
   // step three: the tile's nodes inside the domain, pulled from LDS, stored to global memory
   if (x0 + tx < nx && y0 + ty < ny) {
-    lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd);
+    lds_pulls(tx + 2, ty + 2, X, Y, fd, gd, hd, rest);
     rs.d4 = fwrite;
     collide_store_ab<S, CP>(d, rs, (uint32_t)Y * pitch + X, step + 2u, pab[0], pab[3], pab[1], pab[2], fd, gd, hd,
                             prev);
@@ -1366,10 +1378,10 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
 }
 
 template <typename S, int CP>
-__global__ void __launch_bounds__(ThreeStep<S>::THREADS) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
+__global__ void __launch_bounds__(ThreeStep<S>::THREADS, ThreeStep<S>::MIN_WAVES_PER_EU) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
                                                                       int ntx, int parity) {
   const Desc<typename St<S>::R> &d = *dp;
-  __shared__ S lpop[NPOP][ThreeStep<S>::RN];
+  __shared__ S lpop[NPOP - 3][ThreeStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   three_step_tile<S, CP>(d, (b % ntx) * ThreeStep<S>::W, (b / ntx) * ThreeStep<S>::H, parity, lpop);
 }

@@ -433,6 +433,24 @@ def test_mutation_model_a_mapping_is_caught():
 
 # ---------------------------------------------------------------- the paper's Table 1
 
+def test_table1_pure_fluid_enclosure_coarse():
+    """Section 4.1, Table 1 on 40% of the paper's grid (40 x 80, 80000 steps; with Ma fixed the
+    diffusive time scales with the side): Nu, Sh and the largest velocities within 1% of the
+    paper's 3.402, 4.398, 39.275 and 86.375 (the oracle gives -0.24%, +0.02%, +0.28%, +0.26%;
+    on 50 x 100 after 100000 steps -0.25%, -0.13%, +0.6%, +0.4%).  Runs in the default CPU tier
+    (about a minute on one core); the full 100 x 200 grid is the opt-in test below."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "table1_pure_fluid_enclosure.json")))["quantities"]
+    o = Oracle(dict(nx=40, ny=80, Ra=1e5, Pr=1.0, Le=2.0, Da=1e8, N=-0.8, phi=1.0), T=0.5, C=0.5)
+    o.step(80000)
+    ob = o.observables()
+    scale = 40 / o.derived()["alpha_e"]
+    assert ob["Nu"][0] == pytest.approx(ref["Nu_left"], rel=0.01)
+    assert ob["Sh"][0] == pytest.approx(ref["Sh_left"], rel=0.01)
+    assert ob["max_ux"] * scale == pytest.approx(ref["max_abs_ux_in_alpha_e_over_L"], rel=0.01)
+    assert ob["max_uy"] * scale == pytest.approx(ref["max_abs_uy_in_alpha_e_over_L"], rel=0.01)
+
+
 @pytest.mark.slow
 def test_table1_pure_fluid_enclosure():
     """Section 4.1, Table 1: phi = 1, Da = 1e8, Ra = 1e5, Pr = 1, Le = 2, A = 2, N = -0.8 on
