@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=256, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=0,
                     help="step cap per solve (serve and sweep --until-converged: default 100000)")
-    ap.add_argument("--oracle-samples", type=int, default=3, help="serve: requests re-run on the oracle")
+    ap.add_argument("--oracle-samples", type=int, default=4,
+                    help="serve: requests re-run on the oracle (the smallest of each precision, alternating)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the solver, run 10 plain device-to-device copies of MIB MiB "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -420,7 +421,7 @@ def serve(a):
     by_id = {r.id: r for r in reqs}
 
     def pct(v, q):
-        return round(float(np.percentile(v, q)), 4) if len(v) else None
+        return float(f"{np.percentile(v, q):.4g}") if len(v) else None
 
     def t_slow(req):
         d = _l.derive(req.params, req.precision)
@@ -441,7 +442,10 @@ def serve(a):
     if a.oracle_samples > 0:
         import oracle
         errs = []
-        picks = sorted((r for r in results if r.nodes <= 256 * 256), key=lambda r: (r.nodes, r.id))
+        small = sorted((r for r in results if r.nodes <= 256 * 256), key=lambda r: (r.nodes, r.id))
+        # the smallest requests of each storage precision, alternating
+        by_prec = [[r for r in small if r.precision == q] for q in ("fp32", "fp16s")]
+        picks = [r for pair in zip(*by_prec) for r in pair]
         for res in picks[:a.oracle_samples]:
             req = by_id[res.id]
             o = oracle.Oracle(req.params, T=req.T, C=req.C)

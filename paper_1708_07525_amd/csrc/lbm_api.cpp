@@ -2,6 +2,7 @@
 // validation (sections 2 and 4.1, Eq. 29), device buffers, launch bookkeeping, HIP graph
 // replay of step chunks, reductions, checkpoints, the autotuner and the batch table.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -15,6 +16,17 @@
 
 #include "lbm.h"
 #include "lbm_internal.h"
+
+namespace {
+// a roctx range around each entry point that does device work, so that a profiler run
+// (rocprofv3 --marker-trace) shows steps, observables and tuning on the host timeline
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
+}  // namespace
 
 #define LBM_API extern "C" __attribute__((visibility("default")))
 
@@ -565,6 +577,7 @@ LBM_API const char *lbm_last_error(const lbm_ctx *c) {
 
 LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T, const double *C,
                                   const double *ux, const double *uy) {
+  Range range_("lbm_set_fields");
   if (!c) return LBM_EINVAL;
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   c->err.clear();
@@ -778,6 +791,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
 }
 
 LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+  Range range_("lbm_step");
   if (!c || nsteps < 0) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
@@ -867,12 +881,14 @@ static lbm_status observe(lbm_ctx *c, lbm_obs *out, double *fields, double *part
 }
 
 LBM_API lbm_status lbm_observables(lbm_ctx *c, lbm_obs *out, double *fields) {
+  Range range_("lbm_observables");
   if (!c || !out) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables before lbm_set_fields");
   return observe(c, out, fields, c->partials(), c->obs_out(), nullptr);
 }
 
 LBM_API lbm_status lbm_observables_static(lbm_ctx *c, lbm_obs *out, double *fields) {
+  Range range_("lbm_observables_static");
   if (!c || !out) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_observables_static before lbm_set_fields");
   if (!c->scratch) return fail(c, LBM_EDEVICE, "no fixed scratch on this device");
@@ -1014,6 +1030,7 @@ LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
 LBM_API int32_t lbm_get_steps_per_launch(const lbm_ctx *c) { return c ? ctx_spl(c) : 0; }
 
 LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int32_t *ty_out, double *ms_out) {
+  Range range_("lbm_autotune");
   if (!c || steps < 2) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_set_fields");
   if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
@@ -1395,6 +1412,7 @@ LBM_API lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t s
 }
 
 LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, int32_t *policy_out) {
+  Range range_("lbm_batch_autotune");
   if (!b || steps < 1) return LBM_EINVAL;
   if (b->ctx.empty()) return LBM_OK;
   const int64_t n = (steps + 3) / 4 * 4;   // whole pairs of two-step launches: buffers end where they began
@@ -1478,6 +1496,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shap
 }
 
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+  Range range_("lbm_batch_step");
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (b->ctx.empty() || nsteps == 0) return LBM_OK;
   if (b->dirty) {
