@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--precision-case", default="all", choices=("all", "grf512", "band2048"),
                     help="precision: which workload")
     ap.add_argument("--cavities", type=int, default=256, help="sweep: number of cavities")
+    ap.add_argument("--chunk", type=int, default=120,
+                    help="sweep and serve: steps per batched graph replay (a multiple of 12 lets FP32 and "
+                         "FP64 groups take three steps per launch)")
     ap.add_argument("--until-converged", action="store_true",
                     help="sweep: run every cavity to steady state (residual 1e-8) or --max-steps, "
                          "batched through the serving loop and one by one with plain launches")
@@ -207,9 +210,10 @@ def cpu_baseline(case, target_s):
 def sweep(a):
     """Independent cavities of uneven size and parameters (sides 64..512, aspect 1 or 2,
     Ra, Da, porosity, Le, N drawn per cavity), FP32: aggregate MLUPS of the batch (cache-sized
-    groups, two steps per batched launch, replayed from a HIP graph), against the same
+    groups, two or three steps per batched launch as the batch autotuner chooses, replayed
+    from a HIP graph), against the same
     cavities stepped one by one with one plain launch per step (the one-step kernel, no
-    graph), and one by one with the library defaults (two steps per launch, graph replay)."""
+    graph), and one by one with the library defaults (three steps per launch, graph replay)."""
     import torch
     import workloads
     from paper_1708_07525_amd import Batch, Solver
@@ -239,11 +243,11 @@ def sweep(a):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[mode] = round(nodes * steps / dt / 1e6, 1)
-    b = Batch(len(solvers), chunk=100)
+    b = Batch(len(solvers), chunk=a.chunk)
     for s in solvers:
         b.attach(s)
     t0 = time.perf_counter()
-    chosen = b.autotune(20)
+    chosen = b.autotune(24)
     out["batch_autotune"] = {"seconds": round(time.perf_counter() - t0, 2),
                              "choices": {f"{p}|{c}": {"shape": v[0], "policy": v[1]} for (p, c), v in chosen.items()}}
     b.step(200)
@@ -335,7 +339,7 @@ def sweep_until_converged(a, cav):
     for i, e in enumerate(cav):
         T, C = workloads.cavity_fields(e)
         reqs.append(Request(i, 0.0, e["params"], "fp32", None, T, C))
-    srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=100, check_every=1000, tol=1e-8, max_steps=cap,
+    srv = Server(200 * 10 ** 9, max_slots=len(reqs), chunk=a.chunk, check_every=10 * a.chunk, tol=1e-8, max_steps=cap,
                  autotune_steps=20)
 
     def note(d):
@@ -398,13 +402,15 @@ def serve(a):
     def note(d):
         print("progress", json.dumps(d), file=sys.stderr, flush=True)
 
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap, autotune_steps=20)
+    srv = Server(budget, max_slots=256, chunk=a.chunk, check_every=10 * a.chunk, tol=1e-8, max_steps=cap,
+                 autotune_steps=24)
     _, cs = srv.run(cal, progress=note)
     srv.close()
     capacity = cs["requests"] / cs["wall_s"]
     rate = 0.8 * capacity
     reqs = build(workloads.request_stream(count=a.requests, seed=4, rate=rate))
-    srv = Server(budget, max_slots=256, chunk=100, check_every=1000, tol=1e-8, max_steps=cap, autotune_steps=20)
+    srv = Server(budget, max_slots=256, chunk=a.chunk, check_every=10 * a.chunk, tol=1e-8, max_steps=cap,
+                 autotune_steps=24)
     results, summ = srv.run(reqs, progress=note)
     srv.close()
     torch.cuda.synchronize()

@@ -227,7 +227,7 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 /* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 64 x 8 tiles, 32 x 8
  * for FP64, and a one-node halo staged in LDS, so the global loads of the second step are
  * saved), 3 (the three-step kernel: the same tiles with a two-node halo; FP32 and FP64 storage
- * with walls half a spacing outside, else 2), or 0 for the default (3 for FP64 storage, else 2).  Walls through the
+ * with walls half a spacing outside, else 2), or 0 for the default (2 for FP16 storage, else 3).  Walls through the
  * nodes take 1 with FP16 storage, or when the lattice is smaller than one two-step tile;
  * otherwise the two-step kernel applies the boundary rule in both steps (its last tiles sit
  * against the far walls).  Remaining steps run in shorter launches.  Results do not depend on
@@ -257,7 +257,10 @@ void lbm_destroy(struct lbm_ctx *c);
  * group starts, so its data stays in the 256 MB Infinity Cache from step to step.  With an
  * even chunk that is a multiple of 4 a launch advances two steps (the two-step kernel over
  * tiles of the group's shape: 64 x 8, 32 x 16 or 32 x 8 nodes; FP64 32 x 8, 16 x 16 or 16 x 8),
- * otherwise one.  A group takes the tile shape and cache policy lbm_batch_autotune chose for
+ * otherwise one.  With a chunk that is a multiple of 12, FP32 and FP64 groups may instead
+ * advance three steps per launch (shape index 3: the three-step kernel over the tiles of shape
+ * 0).  Steps that do not fill a launch run one per launch.  A group takes the tile shape and
+ * cache policy lbm_batch_autotune chose for
  * its precision and size class, or by default the first shape and the default cache-policy
  * rule of lbm_set_cache_policy for the group's bytes.  Each launch walks a device-side table of
  * (cavity, tile) work items and the launches are replayed from a captured HIP graph;
@@ -279,16 +282,19 @@ lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
 /* Advances every attached context by nsteps (asynchronous). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Autotuner of the batched launch: for every precision and size class present, times each
- * tile shape of the two-step launch and each cache policy on that class's groups (`steps`
- * steps, rounded up to a multiple of 4, after a warm-up), keeps the fastest, and restores
+ * tile shape of the two-step launch (and three steps per launch, shape 3, where the chunk and
+ * the precision allow it) and each cache policy on that class's groups (`steps` steps, rounded
+ * up to a multiple of 12, after a warm-up of 12), keeps the fastest, and restores
  * every attached state it started from.  shape_out and policy_out (each 12 int32, index
  * precision * 4 + size class; may be NULL) receive the choices of the classes present.
  * Synchronises; allocates a temporary device copy of the attached states. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, int32_t *policy_out);
 /* Sets the launch choice of one precision (lbm_precision) and size class (0-3: width <= 64,
  * <= 128, <= 256, wider) without timing (e.g. from a cache of lbm_batch_autotune results):
- * shape 0-2, policy 0-2 or -1 for the default rule.  Takes effect at the next lbm_batch_step.
- * LBM_EINVAL for an index out of range. */
+ * shape 0-2 (two-step tiles) or 3 (three steps per launch; FP32 and FP64 only; taken as shape 0
+ * with two steps per launch while the chunk is not a multiple of 12), policy 0-2 or -1 for the
+ * default rule.  Takes effect at the next lbm_batch_step.  LBM_EINVAL for an index out of
+ * range and for shape 3 with FP16 storage. */
 lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape, int32_t policy);
 int32_t lbm_batch_size(const lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);

@@ -246,7 +246,9 @@ double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC
 // does not apply the next lower one is taken (two_step_ok, three_step_ok).
 int default_spl(int prec, double nodes) {
   (void)nodes;
-  return prec == PREC_FP64 ? 3 : 2;
+  // three steps per launch win for FP32 and FP64 at every lattice size measured (256^2 to
+  // 4096^2); FP16 storage, held by its arithmetic, keeps two
+  return prec == PREC_FP16S ? 2 : 3;
 }
 
 // Cache policy when none is set: a step that touches at most 400 MB keeps its data in the
@@ -1120,17 +1122,20 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
 // that they stay in the Infinity Cache while the group advances a chunk of steps; items
 // [first, first + count) of the precision's item table.
 struct BatchGroup {
-  int prec, cls, cp, first, count, first2, count2;   // one-step items, two-step items
-  int grid2;   // work-groups of the two-step launch (one per item; count2 rounded up to a
+  int prec, cls, cp, first, count, first2, count2;   // one-step items, multi-step items
+  int grid2;   // work-groups of the multi-step launch (one per item; count2 rounded up to a
                // power of two, so that a graph survives small changes of the group)
-  int shape;   // tile shape of the two-step launch (batch_tile_shape)
+  int shape;   // tile shape of the multi-step items (batch_tile_shape)
+  int spl;     // steps per multi-step launch: 3, 2, or 1 (one-step launches only)
 };
 
-// Launch choice of the groups of one precision and size class: the two-step tile shape and
-// the cache policy (-1: the default rule), set by lbm_batch_autotune.
+// Launch choice of the groups of one precision and size class: the two-step tile shape, or
+// kBatchThree for three steps per launch on the three-step tile (shape 0), and the cache
+// policy (-1: the default rule); set by lbm_batch_set_tile or lbm_batch_autotune.
 struct BatchChoice {
   int shape = 0, cp = -1;
 };
+int batch_three_shape() { return batch_tile_shapes(); }
 
 // size classes of cavities in a batch, by width: <= 64, <= 128, <= 256, wider
 constexpr int kBatchClasses = 4;
@@ -1162,6 +1167,25 @@ namespace {
 
 constexpr double kGroupBytes = 200e6;   // per-step bytes of one group (Infinity Cache: 256 MB)
 
+// Steps per batched two-step launch: 2 when a replay chunk is a multiple of 4 steps (so a
+// replay flips the population and field buffers an even number of times), else 1.
+int batch_spl(const lbm_batch *b) { return b->chunk % 4 == 0 ? 2 : 1; }
+
+// three steps per launch need a chunk that is a multiple of 6 (an even number of launches)
+// and of 4 (the two-step groups of the same replay): of 12; FP32 and FP64 storage only
+bool batch_three_ok(const lbm_batch *b, int prec) { return b->chunk % 12 == 0 && prec != PREC_FP16S; }
+
+// steps per multi-step launch of the groups of one precision under a launch choice
+int batch_group_spl(const lbm_batch *b, int prec, const BatchChoice &ch) {
+  if (ch.shape == batch_three_shape() && batch_three_ok(b, prec)) return 3;
+  return batch_spl(b);
+}
+
+// steps per multi-step launch of an attached cavity (its group's)
+int batch_ctx_spl(const lbm_batch *b, const lbm_ctx *c) {
+  return batch_group_spl(b, c->prec, b->choice[c->prec][batch_class(c->p.nx)]);
+}
+
 void drop_batch_graph(lbm_batch *b) {
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
@@ -1192,12 +1216,14 @@ lbm_status batch_upload(lbm_batch *b) {
       const double nodes = (double)c->p.nx * c->p.ny;
       if (b->groups.empty() || b->groups.back().prec != prec || b->groups.back().cls != cls ||
           (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
-        b->groups.push_back(BatchGroup{prec, cls, 0, (int)items.size(), 0, (int)items2.size(), 0, 1, ch.shape});
+        const int spl = batch_group_spl(b, prec, ch);
+        b->groups.push_back(BatchGroup{prec, cls, 0, (int)items.size(), 0, (int)items2.size(), 0, 1,
+                                       spl == 3 ? 0 : ch.shape, spl});
         gnodes = 0;
       }
       gnodes += nodes;
       int w2 = 0, h2 = 0;
-      batch_tile_shape(prec, ch.shape, &w2, &h2);
+      batch_tile_shape(prec, b->groups.back().shape, &w2, &h2);
       // 256-thread tiles of tw x (256/tw) nodes; tw in {256, 128, 64} wastes the fewest
       // lanes on the ragged right edge (ties go to the wider tile)
       int tw = 256;
@@ -1215,7 +1241,7 @@ lbm_status batch_upload(lbm_batch *b) {
       g.count2 = (int)items2.size() - g.first2;
       g.grid2 = 1;
       while (g.grid2 < g.count2) g.grid2 *= 2;
-      g.cp = ch.cp >= 0 ? ch.cp : default_policy(prec, gnodes, b->chunk % 4 == 0 ? 2 : 1);   // spl as batch_spl
+      g.cp = ch.cp >= 0 ? ch.cp : default_policy(prec, gnodes, g.spl);
     }
     const int n = (int)items.size();
     if (n > b->item_cap[prec]) {
@@ -1280,32 +1306,29 @@ std::vector<int> batch_key(const lbm_batch *b) {
     k.push_back(g.cp);
     k.push_back(g.grid2);
     k.push_back(g.shape);
+    k.push_back(g.spl);
   }
   return k;
 }
 
-// Steps per batched launch: 2 when a replay chunk is a multiple of 4 steps (so a replay
-// flips the population and field buffers an even number of times), else 1.
-int batch_spl(const lbm_batch *b) { return b->chunk % 4 == 0 ? 2 : 1; }
-
-// n steps of group gi: pairs of steps in the two-step kernel, an odd step in the one-step
-// kernel (with the field buffer the pairs left current: parity bit 1)
+// n steps of group gi: multi-step launches (g.spl steps each) while n allows, then single
+// steps.  A multi-step launch flips the population and the field buffers; a single step
+// flips the population buffers and updates the current field buffer in place.
 hipError_t batch_launch_group(lbm_batch *b, size_t gi, int64_t n, hipStream_t s) {
-  const int spl = batch_spl(b);
   const BatchGroup &g = b->groups[gi];
   const int *rg = b->ranges + 4 * gi;
-  int64_t k = 0;
-  if (spl == 2)
-    for (; k + 2 <= n; k += 2) {
-      const int q = (int)((k / 2) & 1);
-      int e = launch_step2_batch(g.prec, g.cp, g.shape, b->descs[g.prec], b->items2[g.prec], rg + 2, g.grid2, q, s);
+  int64_t k = 0, multi = 0;
+  if (g.spl >= 2)
+    for (; k + g.spl <= n; k += g.spl, ++multi) {
+      const int q = (int)(multi & 1);
+      const int e = g.spl == 3 ? launch_step3_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2,
+                                                    g.grid2, q, s)
+                               : launch_step2_batch(g.prec, g.cp, g.shape, b->descs[g.prec], b->items2[g.prec],
+                                                    rg + 2, g.grid2, q, s);
       if (e) return (hipError_t)e;
     }
-  for (; k < n; ++k) {
-    // launches so far: k / 2 two-step ones, then single steps
-    const int launches = (int)(spl == 2 ? k / 2 + (k - 2 * (k / 2)) : k);
-    const int pairs = (int)(spl == 2 ? (k / 2) & 1 : 0);
-    const int parity = (launches & 1) | (pairs << 1);
+  for (int64_t single = 0; k < n; ++k, ++single) {
+    const int parity = (int)((multi + single) & 1) | (int)((multi & 1) << 1);
     int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], rg, b->grid, parity, s);
     if (e) return (hipError_t)e;
   }
@@ -1404,7 +1427,8 @@ LBM_API int32_t lbm_batch_size(const lbm_batch *b) { return b ? (int32_t)b->ctx.
 LBM_API lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape,
                                       int32_t policy) {
   if (!b || precision < 0 || precision > 2 || size_class < 0 || size_class >= kBatchClasses || shape < 0 ||
-      shape >= batch_tile_shapes() || policy < -1 || policy >= CP_COUNT)
+      shape > batch_three_shape() || (shape == batch_three_shape() && precision == PREC_FP16S) || policy < -1 ||
+      policy >= CP_COUNT)
     return LBM_EINVAL;
   b->choice[precision][size_class] = BatchChoice{shape, policy};
   b->dirty = true;
@@ -1415,7 +1439,8 @@ LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shap
   Range range_("lbm_batch_autotune");
   if (!b || steps < 1) return LBM_EINVAL;
   if (b->ctx.empty()) return LBM_OK;
-  const int64_t n = (steps + 3) / 4 * 4;   // whole pairs of two-step launches: buffers end where they began
+  // whole numbers of pairs of two- and of three-step launches: buffers end where they began
+  const int64_t n = (steps + 11) / 12 * 12;
   // save every attached state (current populations, fields, step counters) on the device
   std::vector<size_t> off;
   size_t total = 0;
@@ -1451,7 +1476,8 @@ LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shap
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
   lbm_status st = LBM_OK;
-  const int shapes = batch_spl(b) == 2 ? batch_tile_shapes() : 1;   // one step per launch: no two-step tile
+  // one step per launch: no multi-step tile; three steps per launch where the chunk allows
+  const int two_shapes = batch_spl(b) == 2 ? batch_tile_shapes() : 1;
   for (int prec = 0; prec < 3 && e == hipSuccess && st == LBM_OK; ++prec)
     for (int cls = 0; cls < kBatchClasses && e == hipSuccess && st == LBM_OK; ++cls) {
       bool present = false;
@@ -1459,8 +1485,10 @@ LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shap
       if (!present) continue;
       float best = 3e38f;
       BatchChoice keep = b->choice[prec][cls];
-      for (int shape = 0; shape < shapes && e == hipSuccess && st == LBM_OK; ++shape)
+      const int shapes = two_shapes + (batch_three_ok(b, prec) ? 1 : 0);
+      for (int k = 0; k < shapes && e == hipSuccess && st == LBM_OK; ++k)
         for (int cp = 0; cp < CP_COUNT && e == hipSuccess && st == LBM_OK; ++cp) {
+          const int shape = k < two_shapes ? k : batch_three_shape();
           b->choice[prec][cls] = BatchChoice{shape, cp};
           st = batch_upload(b);
           if (st != LBM_OK) break;
@@ -1469,7 +1497,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shap
             if (pass == 1) e = hipEventRecord(t0, b->stream);
             for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi)
               if (b->groups[gi].prec == prec && b->groups[gi].cls == cls)
-                e = batch_launch_group(b, gi, pass == 0 ? 4 : n, b->stream);
+                e = batch_launch_group(b, gi, pass == 0 ? 12 : n, b->stream);
           }
           if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
           if (e == hipSuccess) e = hipEventSynchronize(t1);
@@ -1530,15 +1558,16 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     }
   }
   if (left > 0 && batch_launch_steps(b, left, b->stream) != hipSuccess) return LBM_EDEVICE;
-  // buffers flipped by the remainder: one per launch (populations), one per pair (fields)
-  const int spl = batch_spl(b);
-  const int64_t launches = spl == 2 ? left / 2 + (left & 1) : left;
-  const int64_t pairs = spl == 2 ? left / 2 : 0;
+  // buffers flipped by the remainder, per cavity as its group launched it: the populations
+  // once per launch, the fields once per multi-step launch
   for (lbm_ctx *c : b->ctx) {
+    const int spl = batch_ctx_spl(b, c);
+    const int64_t multi = spl >= 2 ? left / spl : 0;
+    const int64_t launches = multi + (left - multi * spl);
     c->step += nsteps;
     if (launches & 1) c->cur ^= 1;
-    if (pairs & 1) c->d4cur ^= 1;
+    if (multi & 1) c->d4cur ^= 1;
+    if ((launches & 1) || (multi & 1)) b->dirty = true;   // parities and field buffers in the table changed
   }
-  if ((launches & 1) || (pairs & 1)) b->dirty = true;   // parities and field buffers in the table changed
   return LBM_OK;
 }

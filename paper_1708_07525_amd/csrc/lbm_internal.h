@@ -99,6 +99,10 @@ int launch_step_batch(int prec, int cp, const void *descs, const Item *items, co
 // above for both the population and the field buffers
 int launch_step2_batch(int prec, int cp, int shape, const void *descs, const Item *items, const int *range, int grid,
                        int parity, void *stream);
+// three steps per launch over the items of batch tile shape 0 (the three-step tile), one item
+// per work-group; FP32 and FP64 storage only (else hipErrorInvalidValue); parity as above
+int launch_step3_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                       int parity, void *stream);
 // tile of the single-cavity two-step kernels for a storage precision
 void two_step_tile_shape(int prec, int *w, int *h);
 // tile shapes of the batched two-step kernel

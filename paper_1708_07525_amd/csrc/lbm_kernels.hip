@@ -1401,6 +1401,20 @@ __global__ void __launch_bounds__(SH::THREADS) step2_batch_kernel(const Desc<typ
   two_step_tile<S, CP, false, SH>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
+// Batched three steps over items of ThreeStep<S> tiles (FP32, FP64): one item per work-group,
+// as step2_batch_kernel.
+template <typename S, int CP>
+__global__ void __launch_bounds__(ThreeStep<S>::THREADS, ThreeStep<S>::MIN_WAVES_PER_EU)
+    step3_batch_kernel(const Desc<typename St<S>::R> *__restrict__ descs, const Item *__restrict__ items,
+                       const int *__restrict__ range, int parity) {
+  __shared__ S lpop[NPOP - 3][ThreeStep<S>::RN];
+  const int first = range[0], n = range[1];
+  if ((int)blockIdx.x >= n) return;
+  const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
+  const Item item = items[first + it];
+  three_step_tile<S, CP>(descs[item.cavity], item.x0, item.y0, parity, lpop);
+}
+
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
 // keep every lane busy.
 template <typename S, int CP>
@@ -1844,6 +1858,40 @@ int launch_step2_batch(int prec, int cp, int shape, const void *descs, const Ite
     case PREC_FP64: batch2_t<double>(cp, shape, descs, items, range, grid, parity, s); break;
     case PREC_FP32: batch2_t<float>(cp, shape, descs, items, range, grid, parity, s); break;
     default: batch2_t<_Float16>(cp, shape, descs, items, range, grid, parity, s); break;
+  }
+  return (int)hipGetLastError();
+}
+
+template <typename S>
+static void batch3_t(int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
+                     hipStream_t s) {
+  using D = Desc<typename St<S>::R>;
+  const D *dd = (const D *)descs;
+  const dim3 block(ThreeStep<S>::THREADS);
+  switch (cp) {
+    case CP_STREAM:
+      hipLaunchKernelGGL((step3_batch_kernel<S, CP_STREAM>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step3_batch_kernel<S, CP_RESIDENT>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    default:
+      hipLaunchKernelGGL((step3_batch_kernel<S, CP_TUNED>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+  }
+}
+
+int launch_step3_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                       int parity, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  static_assert(ThreeStep<float>::W == BatchShape<float, 0>::T::W && ThreeStep<float>::H == BatchShape<float, 0>::T::H &&
+                    ThreeStep<double>::W == BatchShape<double, 0>::T::W &&
+                    ThreeStep<double>::H == BatchShape<double, 0>::T::H,
+                "the batched three-step launch takes the items of batch tile shape 0");
+  switch (prec) {
+    case PREC_FP64: batch3_t<double>(cp, descs, items, range, grid, parity, s); break;
+    case PREC_FP32: batch3_t<float>(cp, descs, items, range, grid, parity, s); break;
+    default: return (int)hipErrorInvalidValue;   // FP16 storage: one or two steps per launch
   }
   return (int)hipGetLastError();
 }

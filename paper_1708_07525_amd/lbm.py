@@ -364,7 +364,9 @@ class Batch:
         return out
 
     def set_tile(self, precision: str, size_class: int, shape: int, policy: int = -1):
-        """lbm_batch_set_tile: the launch choice of one precision and size class."""
+        """lbm_batch_set_tile: the launch choice of one precision and size class (shape 0-2:
+        two-step tiles; 3: three steps per launch, FP32 and FP64, with a chunk that is a
+        multiple of 12)."""
         _check(lib().lbm_batch_set_tile(self._h, PRECISION[precision], int(size_class), int(shape), int(policy)),
                None, "lbm_batch_set_tile")
 

@@ -478,11 +478,13 @@ def test_batch_alone_vs_mix_bitwise():
     b.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, "auto"])
-def test_batch_tile_shapes_change_nothing(shape):
-    """Every tile shape of the batched two-step launch, and the autotuner's choice, gives each
+@pytest.mark.parametrize("shape,chunk", [(0, 100), (1, 100), (2, 100), (3, 120), ("auto", 100), ("auto", 120)])
+def test_batch_tile_shapes_change_nothing(shape, chunk):
+    """Every tile shape of the batched two-step launch, three steps per launch (shape 3, FP32
+    and FP64, with a chunk that is a multiple of 12), and the autotuner's choice give each
     cavity the state it reaches alone, bit for bit (cavities of all four size classes and the
-    three storage types; widths that are not multiples of the tiles)."""
+    three storage types; widths that are not multiples of the tiles; two graph replays and a
+    remainder of 8 steps: two three-step launches and two single steps)."""
     from paper_1708_07525_amd import Batch
     Solver = _solver()
     specs = [(workloads.cavity_params(nx=40, ny=52), "fp32"),
@@ -490,7 +492,7 @@ def test_batch_tile_shapes_change_nothing(shape):
              (workloads.cavity_params(nx=200, ny=100, Ra=3e4), "fp16s"),
              (workloads.cavity_params(nx=300, ny=45, Ra=2e4, Le=3.0), "fp64"),
              (workloads.cavity_params(nx=72, ny=72, Ra=5e3), "fp64")]
-    steps = 208     # two replays of 100 steps and 8 more
+    steps = 2 * chunk + 8     # two replays and 8 more
     alone = []
     for i, (p, prec) in enumerate(specs):
         T, C = workloads.noise_fields(p["nx"], p["ny"], (11, i))
@@ -498,7 +500,7 @@ def test_batch_tile_shapes_change_nothing(shape):
         s.step(steps)
         alone.append(s.get_state())
         s.close()
-    b = Batch(len(specs), chunk=100)
+    b = Batch(len(specs), chunk=chunk)
     mix = []
     for i, (p, prec) in enumerate(specs):
         T, C = workloads.noise_fields(p["nx"], p["ny"], (11, i))
@@ -512,6 +514,10 @@ def test_batch_tile_shapes_change_nothing(shape):
                                ("fp64", "<=128")}
     else:
         for prec in ("fp64", "fp32", "fp16s"):
+            if shape == 3 and prec == "fp16s":
+                with pytest.raises(RuntimeError):
+                    b.set_tile(prec, 0, shape, -1)
+                continue
             for cls in range(4):
                 b.set_tile(prec, cls, shape, -1)
     b.step(steps)
