@@ -81,11 +81,14 @@ def parse():
     return ap.parse_args()
 
 
-def copy_probe(mib):
+def copy_rate(mib):
+    """A plain device-to-device copy of `mib` MiB, 10 times after one untimed copy: ms per copy and
+    GB/s counting the bytes read and written (the ceiling a streaming kernel reaches on this GPU)."""
     import torch
     n = mib * 1024 * 1024 // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    b.copy_(a)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -94,8 +97,13 @@ def copy_probe(mib):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 10
-    print(json.dumps({"copy_probe_MiB": mib, "ms_per_copy": ms,
-                      "GB_s_read_plus_write": 2 * mib * 1048576 / (ms * 1e-3) / 1e9}), flush=True)
+    del a, b
+    return ms, 2 * mib * 1048576 / (ms * 1e-3) / 1e9
+
+
+def copy_probe(mib):
+    ms, gbs = copy_rate(mib)
+    print(json.dumps({"copy_probe_MiB": mib, "ms_per_copy": ms, "GB_s_read_plus_write": gbs}), flush=True)
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07525_amd", "csrc", "lbm_kernels.hip")
@@ -527,6 +535,10 @@ def main():
     }
     # the measured HBM traffic of a launch (rocprofv3 counters, when they match this kernel and
     # launch) over the launch's time from the timed region: the real bandwidth the kernel draws
+    # the same launch against what a plain copy reaches on this GPU (1 GiB, read + write)
+    _, copy_gbs = copy_rate(1024)
+    out["roofline"]["copy_ceiling_GB_s"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy_ceiling"] = round(rf["achieved"] / copy_gbs, 4)
     tr = out["roofline"]["traffic"]
     if tr is not None:
         launch_s = rf["launch_us"] * 1e-6

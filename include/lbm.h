@@ -227,11 +227,11 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 /* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 64 x 8 tiles, 32 x 8
  * for FP64, and a one-node halo staged in LDS, so the global loads of the second step are
  * saved), 3 (the three-step kernel: the same tiles with a two-node halo; FP32 and FP64 storage
- * with walls half a spacing outside, else 2), or 0 for the default (2 for FP16 storage, else 3).  Walls through the
- * nodes take 1 with FP16 storage, or when the lattice is smaller than one two-step tile;
- * otherwise the two-step kernel applies the boundary rule in both steps (its last tiles sit
- * against the far walls).  Remaining steps run in shorter launches.  Results do not depend on
- * it (bit for bit).  With 3, a graph replay covers the largest multiple of 6 steps in the
+ * with walls half a spacing outside, else 2), or 0 for the default (2 for FP16 storage, else
+ * 3).  Walls through the nodes take 1 with FP16 storage, or when the lattice is smaller than one
+ * two-step tile; otherwise the two-step kernel applies the boundary rule in both steps (its last
+ * tiles sit against the far walls).  Remaining steps run in shorter launches.  Results do not
+ * depend on it (bit for bit).  With 3, a graph replay covers the largest multiple of 6 steps in the
  * graph chunk.  lbm_get_steps_per_launch returns the count in effect (0 for a NULL context). */
 lbm_status lbm_set_steps_per_launch(struct lbm_ctx *c, int32_t n);
 int32_t lbm_get_steps_per_launch(const struct lbm_ctx *c);
