@@ -274,9 +274,13 @@ typedef struct lbm_batch lbm_batch;
  * stream: hipStream_t the batch runs on (NULL: null stream). */
 lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *stream, lbm_batch **out);
 /* The context must be initialised (lbm_set_fields), on the batch's device and not in
- * another batch; its work moves to the batch's stream until detached.  A context with
- * walls through the boundary nodes (LBM_NEE_* sides) is refused with LBM_EINVAL: it
- * advances with lbm_step only. */
+ * another batch; its work moves to the batch's stream until detached.  A context with walls
+ * through the boundary nodes (LBM_NEE_* sides) joins groups of its own, which advance two
+ * steps per launch on the two-step tile with the last tiles against the far walls (as
+ * lbm_step does); a remaining single step runs as the context's own one-step launch.  Such a
+ * context is refused with LBM_EINVAL when its storage is FP16, when its lattice is smaller
+ * than one two-step tile (64 x 8, FP64 32 x 8), or when the batch's chunk is not a multiple
+ * of 4; it then advances with lbm_step only. */
 lbm_status lbm_batch_attach(lbm_batch *b, struct lbm_ctx *c);
 lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
 /* Advances every attached context by nsteps (asynchronous). */

@@ -1127,6 +1127,8 @@ struct BatchGroup {
                // power of two, so that a graph survives small changes of the group)
   int shape;   // tile shape of the multi-step items (batch_tile_shape)
   int spl;     // steps per multi-step launch: 3, 2, or 1 (one-step launches only)
+  int nee;     // walls through the boundary nodes: two-step launches only, last tiles against
+               // the far walls; a remaining single step runs as the cavity's own launch
 };
 
 // Launch choice of the groups of one precision and size class: the two-step tile shape, or
@@ -1183,6 +1185,7 @@ int batch_group_spl(const lbm_batch *b, int prec, const BatchChoice &ch) {
 
 // steps per multi-step launch of an attached cavity (its group's)
 int batch_ctx_spl(const lbm_batch *b, const lbm_ctx *c) {
+  if (node_walls(&c->p)) return 2;
   return batch_group_spl(b, c->prec, b->choice[c->prec][batch_class(c->p.nx)]);
 }
 
@@ -1199,13 +1202,16 @@ lbm_status batch_upload(lbm_batch *b) {
     std::vector<Desc<double>> d64;
     std::vector<Desc<float>> d32;
     double gnodes = 0;
-    // cavities of this precision by size class (attach order within a class)
+    // cavities of this precision by size class, those with walls through the nodes after the
+    // others of their class (attach order within each)
     std::vector<lbm_ctx *> order;
     for (int cls = 0; cls < kBatchClasses; ++cls)
-      for (lbm_ctx *c : b->ctx)
-        if (c->prec == prec && batch_class(c->p.nx) == cls) order.push_back(c);
+      for (int nee = 0; nee < 2; ++nee)
+        for (lbm_ctx *c : b->ctx)
+          if (c->prec == prec && batch_class(c->p.nx) == cls && (int)node_walls(&c->p) == nee) order.push_back(c);
     for (lbm_ctx *c : order) {
       const int cls = batch_class(c->p.nx);
+      const int nee = node_walls(&c->p) ? 1 : 0;
       const BatchChoice &ch = b->choice[prec][cls];
       const int idx = prec == PREC_FP64 ? (int)d64.size() : (int)d32.size();
       set_parity(c, c->cur);
@@ -1215,10 +1221,12 @@ lbm_status batch_upload(lbm_batch *b) {
       // kGroupBytes (a larger cavity is a group of its own)
       const double nodes = (double)c->p.nx * c->p.ny;
       if (b->groups.empty() || b->groups.back().prec != prec || b->groups.back().cls != cls ||
-          (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
-        const int spl = batch_group_spl(b, prec, ch);
+          b->groups.back().nee != nee || (gnodes > 0 && (gnodes + nodes) * bytes_per_lu(prec) > kGroupBytes)) {
+        // node-wall groups: two steps per launch on the two-step tile (attach checked that the
+        // chunk allows two steps and that the cavity holds one tile)
+        const int spl = nee ? 2 : batch_group_spl(b, prec, ch);
         b->groups.push_back(BatchGroup{prec, cls, 0, (int)items.size(), 0, (int)items2.size(), 0, 1,
-                                       spl == 3 ? 0 : ch.shape, spl});
+                                       (spl == 3 || nee) ? 0 : ch.shape, spl, nee});
         gnodes = 0;
       }
       gnodes += nodes;
@@ -1235,7 +1243,14 @@ lbm_status batch_upload(lbm_batch *b) {
         for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{idx, tx * tw, ty * rows, tw});
       const int ntx2 = (c->p.nx + w2 - 1) / w2, nty2 = (c->p.ny + h2 - 1) / h2;
       for (int ty = 0; ty < nty2; ++ty)
-        for (int tx = 0; tx < ntx2; ++tx) items2.push_back(Item{idx, tx * w2, ty * h2, w2});
+        for (int tx = 0; tx < ntx2; ++tx) {
+          int x0 = tx * w2, y0 = ty * h2;
+          if (nee) {   // as the single-cavity two-step kernel: the last tiles against the far walls
+            x0 = std::min(x0, c->p.nx - w2);
+            y0 = std::min(y0, c->p.ny - h2);
+          }
+          items2.push_back(Item{idx, x0, y0, w2});
+        }
       BatchGroup &g = b->groups.back();
       g.count = (int)items.size() - g.first;
       g.count2 = (int)items2.size() - g.first2;
@@ -1321,12 +1336,17 @@ hipError_t batch_launch_group(lbm_batch *b, size_t gi, int64_t n, hipStream_t s)
   if (g.spl >= 2)
     for (; k + g.spl <= n; k += g.spl, ++multi) {
       const int q = (int)(multi & 1);
-      const int e = g.spl == 3 ? launch_step3_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2,
-                                                    g.grid2, q, s)
-                               : launch_step2_batch(g.prec, g.cp, g.shape, b->descs[g.prec], b->items2[g.prec],
-                                                    rg + 2, g.grid2, q, s);
+      const int e = g.nee      ? launch_step2_batch_nee(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2,
+                                                        g.grid2, q, s)
+                    : g.spl == 3 ? launch_step3_batch(g.prec, g.cp, b->descs[g.prec], b->items2[g.prec], rg + 2,
+                                                      g.grid2, q, s)
+                                 : launch_step2_batch(g.prec, g.cp, g.shape, b->descs[g.prec], b->items2[g.prec],
+                                                      rg + 2, g.grid2, q, s);
       if (e) return (hipError_t)e;
     }
+  // a remaining single step of a node-wall group is the cavity's own one-step launch (the
+  // batched one-step kernel has no perimeter work), taken by lbm_batch_step after this call
+  if (g.nee) return hipSuccess;
   for (int64_t single = 0; k < n; ++k, ++single) {
     const int parity = (int)((multi + single) & 1) | (int)((multi & 1) << 1);
     int e = launch_step_batch(g.prec, g.cp, b->descs[g.prec], b->items[g.prec], rg, b->grid, parity, s);
@@ -1399,7 +1419,21 @@ LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   if (c->in_batch) return fail(c, LBM_ESTATE, "context already in a batch");
   if (c->unstable) return fail(c, LBM_ESTATE, "the fields hold a non-finite value");
   if ((int)b->ctx.size() >= b->cap) return fail(c, LBM_ENOMEM, "batch is full");
-  if (node_walls(&c->p)) return fail(c, LBM_EINVAL, "walls through the boundary nodes are not batched");
+  if (node_walls(&c->p)) {
+    // node-wall cavities advance two steps per batched launch on the two-step tile, placed
+    // against the far walls: FP32 and FP64 storage, at least one tile, a chunk that allows two
+    // steps per launch
+    int w = 0, h = 0;
+    two_step_tile_shape(c->prec, &w, &h);
+    if (c->prec == PREC_FP16S)
+      return fail(c, LBM_EINVAL, "FP16 storage with walls through the boundary nodes is not batched");
+    if (c->p.nx < w || c->p.ny < h)
+      return fail(c, LBM_EINVAL, "walls through the boundary nodes on a lattice smaller than one two-step tile "
+                                 "(%d x %d) are not batched", w, h);
+    if (batch_spl(b) != 2)
+      return fail(c, LBM_EINVAL, "walls through the boundary nodes are not batched with a chunk that is not a "
+                                 "multiple of 4");
+  }
   // make prior work of the context visible to the batch stream
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before attach");
   c->in_batch = true;
@@ -1563,11 +1597,23 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
   for (lbm_ctx *c : b->ctx) {
     const int spl = batch_ctx_spl(b, c);
     const int64_t multi = spl >= 2 ? left / spl : 0;
-    const int64_t launches = multi + (left - multi * spl);
+    const int64_t singles = left - multi * spl;
     c->step += nsteps;
-    if (launches & 1) c->cur ^= 1;
-    if (multi & 1) c->d4cur ^= 1;
-    if ((launches & 1) || (multi & 1)) b->dirty = true;   // parities and field buffers in the table changed
+    if (multi & 1) {
+      c->cur ^= 1;
+      c->d4cur ^= 1;
+      b->dirty = true;   // parities and field buffers in the table changed
+    }
+    if (singles == 0) continue;
+    b->dirty = true;
+    if (node_walls(&c->p)) {
+      // the remaining step of a node-wall cavity: its own one-step launch, on the batch's
+      // stream after the group's two-step launches
+      const lbm_status st = step_plain(c, singles);
+      if (st != LBM_OK) return st;
+    } else if (singles & 1) {
+      c->cur ^= 1;
+    }
   }
   return LBM_OK;
 }

@@ -103,6 +103,11 @@ int launch_step2_batch(int prec, int cp, int shape, const void *descs, const Ite
 // per work-group; FP32 and FP64 storage only (else hipErrorInvalidValue); parity as above
 int launch_step3_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
                        int parity, void *stream);
+// two steps per launch with walls through the boundary nodes over items of two-step tiles
+// (shape 0) placed against the far walls as the single-cavity two-step kernel places its last
+// tiles; FP32 and FP64 only (else hipErrorInvalidValue); parity as above
+int launch_step2_batch_nee(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                           int parity, void *stream);
 // tile of the single-cavity two-step kernels for a storage precision
 void two_step_tile_shape(int prec, int *w, int *h);
 // tile shapes of the batched two-step kernel

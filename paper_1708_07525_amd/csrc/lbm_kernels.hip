@@ -1401,6 +1401,21 @@ __global__ void __launch_bounds__(SH::THREADS) step2_batch_kernel(const Desc<typ
   two_step_tile<S, CP, false, SH>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
+// Batched two steps with walls through the boundary nodes (FP32, FP64): items of two-step tiles
+// placed as step2_kernel places them (the last tile of a row or column against the far wall),
+// one item per work-group.
+template <typename S, int CP>
+__global__ void __launch_bounds__(TwoStep<S>::THREADS)
+    step2_batch_nee_kernel(const Desc<typename St<S>::R> *__restrict__ descs, const Item *__restrict__ items,
+                           const int *__restrict__ range, int parity) {
+  __shared__ S lpop[NPOP][TwoStep<S>::RN];
+  const int first = range[0], n = range[1];
+  if ((int)blockIdx.x >= n) return;
+  const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
+  const Item item = items[first + it];
+  two_step_tile<S, CP, true>(descs[item.cavity], item.x0, item.y0, parity, lpop);
+}
+
 // Batched three steps over items of ThreeStep<S> tiles (FP32, FP64): one item per work-group,
 // as step2_batch_kernel.
 template <typename S, int CP>
@@ -1879,6 +1894,40 @@ static void batch3_t(int cp, const void *descs, const Item *items, const int *ra
       hipLaunchKernelGGL((step3_batch_kernel<S, CP_TUNED>), dim3(grid), block, 0, s, dd, items, range, parity);
       break;
   }
+}
+
+template <typename S>
+static void batch2_nee_t(int cp, const void *descs, const Item *items, const int *range, int grid, int parity,
+                         hipStream_t s) {
+  using D = Desc<typename St<S>::R>;
+  const D *dd = (const D *)descs;
+  const dim3 block(TwoStep<S>::THREADS);
+  switch (cp) {
+    case CP_STREAM:
+      hipLaunchKernelGGL((step2_batch_nee_kernel<S, CP_STREAM>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step2_batch_nee_kernel<S, CP_RESIDENT>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+    default:
+      hipLaunchKernelGGL((step2_batch_nee_kernel<S, CP_TUNED>), dim3(grid), block, 0, s, dd, items, range, parity);
+      break;
+  }
+}
+
+int launch_step2_batch_nee(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
+                           int parity, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  static_assert(TwoStep<float>::W == BatchShape<float, 0>::T::W && TwoStep<float>::H == BatchShape<float, 0>::T::H &&
+                    TwoStep<double>::W == BatchShape<double, 0>::T::W &&
+                    TwoStep<double>::H == BatchShape<double, 0>::T::H,
+                "the batched node-wall launch takes tiles of batch tile shape 0");
+  switch (prec) {
+    case PREC_FP64: batch2_nee_t<double>(cp, descs, items, range, grid, parity, s); break;
+    case PREC_FP32: batch2_nee_t<float>(cp, descs, items, range, grid, parity, s); break;
+    default: return (int)hipErrorInvalidValue;   // FP16 storage: node walls take one step per launch
+  }
+  return (int)hipGetLastError();
 }
 
 int launch_step3_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid,
