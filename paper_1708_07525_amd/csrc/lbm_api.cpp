@@ -79,7 +79,7 @@ Layout plan_layout(int nx, int ny, int prec) {
   L.off_pop0 = take((size_t)NPOP * L.plane * es);
   L.off_pop1 = take((size_t)NPOP * L.plane * es);
   L.off_d4 = take((size_t)ND4 * L.plane * rs);
-  L.off_d4b = take((size_t)ND4 * L.plane * rs);   // second field buffer of the two-step launch
+  L.off_d4b = take((size_t)ND4 * L.plane * rs);   // second field buffer of the multi-step launches
   L.off_phi = take((size_t)L.plane * rs);
   L.off_snap = take((size_t)ND4 * L.plane * rs);
   L.off_counter = take(2 * sizeof(unsigned));
@@ -699,7 +699,8 @@ static int ctx_policy(const lbm_ctx *c) {
   return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny, ctx_spl(c));
 }
 
-// n steps with plain launches: pairs of steps in the two-step kernel, an odd step alone
+// n steps with plain launches: three or two steps per launch as ctx_spl allows, the remainder
+// in shorter launches
 static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   const int cp = ctx_policy(c);
   const int spl = ctx_spl(c);
@@ -1148,8 +1149,8 @@ struct lbm_batch {
   int chunk = 2;
   hipStream_t stream = nullptr;
   std::vector<lbm_ctx *> ctx;
-  // per precision: descriptor table and item tables (device): one-step tiles and two-step
-  // tiles
+  // per precision: descriptor table and item tables (device): one-step tiles and the tiles of
+  // the multi-step launches
   void *descs[3] = {nullptr, nullptr, nullptr};
   Item *items[3] = {nullptr, nullptr, nullptr};
   Item *items2[3] = {nullptr, nullptr, nullptr};
