@@ -491,7 +491,12 @@ def test_batch_tile_shapes_change_nothing(shape, chunk):
              (workloads.cavity_params(nx=96, ny=70, Ra=1e5, N=-1.0, phi=0.5), "fp32"),
              (workloads.cavity_params(nx=200, ny=100, Ra=3e4), "fp16s"),
              (workloads.cavity_params(nx=300, ny=45, Ra=2e4, Le=3.0), "fp64"),
-             (workloads.cavity_params(nx=72, ny=72, Ra=5e3), "fp64")]
+             (workloads.cavity_params(nx=72, ny=72, Ra=5e3), "fp64"),
+             # periodic in x with a moving lid: tiles wrapped across the periodic side
+             (workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "cold", "hot"),
+                                      wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp32"),
+             (workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "cold", "hot"),
+                                      wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp64")]
     steps = 2 * chunk + 8     # two replays and 8 more
     alone = []
     for i, (p, prec) in enumerate(specs):
@@ -622,7 +627,9 @@ def test_batch_with_node_walls_alone_vs_mix(chunk, tune):
              (workloads.cavity_params(nx=50, ny=50, sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")),
               "fp64"),
              (workloads.cavity_params(nx=130, ny=9, sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")),
-              "fp32")]
+              "fp32"),
+             (workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "nee_cold", "nee_hot"),
+                                      wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp32")]
     steps = 2 * chunk + 31
     alone = []
     for i, (p, prec) in enumerate(specs):
