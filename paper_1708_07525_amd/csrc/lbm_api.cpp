@@ -240,14 +240,13 @@ Tile default_tile(const lbm_params *p) {
 // accesses, 1 porosity load)
 double bytes_per_lu(int prec) { return prec == PREC_FP64 ? 376.0 : (prec == PREC_FP32 ? 188.0 : 112.0); }
 
-// Steps per launch when none is set: three for FP64 storage (2048^2: 25.9 against 23.8 GLUPS
-// with two), two otherwise (FP32: three steps per launch 46.5 against 48.5: the third step's
-// arithmetic, barriers and lower occupancy cost more than the saved traffic); where a count
-// does not apply the next lower one is taken (two_step_ok, three_step_ok).
+// Steps per launch when none is set: three for FP32 and FP64 storage (faster than two at every
+// lattice size measured, 256^2 to 4096^2: 2048^2 FP32 60.6 against 49.7 GLUPS, FP64 27.1
+// against 24.2), two for FP16 storage (held by its arithmetic, to which a third step would add
+// a sixth); where a count does not apply the next lower one is taken (two_step_ok,
+// three_step_ok).
 int default_spl(int prec, double nodes) {
   (void)nodes;
-  // three steps per launch win for FP32 and FP64 at every lattice size measured (256^2 to
-  // 4096^2); FP16 storage, held by its arithmetic, keeps two
   return prec == PREC_FP16S ? 2 : 3;
 }
 
@@ -669,8 +668,8 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
   return LBM_OK;
 }
 
-// Time steps per launch: 2 (the LDS-staged two-step kernel) unless the cavity has walls
-// through the nodes, or set otherwise.
+// Time steps per launch: default_spl (three for FP32 and FP64 storage, two for FP16), or the
+// count set by lbm_set_steps_per_launch, lowered to what the cavity allows.
 // With walls through the nodes the two-step kernel places its last tiles against the far
 // walls, so the lattice must hold one tile.  FP16 storage with walls through the nodes always
 // takes one step per launch: the two-step kernel is slower there (2048^2: 41 against 50
