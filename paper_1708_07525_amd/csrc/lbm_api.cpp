@@ -962,7 +962,9 @@ LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h;
   std::memcpy(&h, host, sizeof h);
-  if (std::memcmp(h.magic, "LBMDDPS3", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec)
+  if (std::memcmp(h.magic, "LBMDDPS3", 8) != 0 || h.nx != c->p.nx || h.ny != c->p.ny || h.precision != c->prec ||
+      h.pop_bytes != (uint64_t)NPOP * c->lay.plane * store_size(c->prec) ||
+      h.d4_bytes != (uint64_t)ND4 * c->lay.plane * real_size(c->prec))
     return fail(c, LBM_EINVAL, "state does not match this context");
   const char *src = (const char *)host + sizeof h;
   drop_graph(c);

@@ -400,6 +400,17 @@ def test_checkpoint_roundtrip():
     d = _state_diff(a.get_state(), b.get_state())
     assert d is None, d
     assert a.observables()["step"] == b.observables()["step"] == 600
+    # a state whose header does not match the context (another lattice, or sizes altered) is
+    # refused before anything is copied
+    from paper_1708_07525_amd.lbm import LbmError
+    import struct
+    bad = bytearray(blob)
+    hdr = 8 + 4 * 4 + 8 * 2               # magic, nx, ny, precision, counter, step, snap_step
+    struct.pack_into("<Q", bad, hdr, struct.unpack_from("<Q", bad, hdr)[0] * 2)   # pop_bytes
+    with pytest.raises(LbmError, match="does not match"):
+        b.set_state(bytes(bad))
+    d = _state_diff(a.get_state(), b.get_state())
+    assert d is None, d
 
 
 def test_unstable_is_reported():
