@@ -95,10 +95,14 @@ class Server:
         if len(self.active) >= self.max_slots or self.used + need > self.budget:
             return False
         s = self.be.Solver(req.params, phi=req.phi, T=req.T, C=req.C, precision=req.precision)
-        if _lbm.node_walls(req.params):
-            self.solo.add(id(s))           # walls through the nodes: stepped on its own
-        else:
+        try:
             self.batch.attach(s)
+        except RuntimeError as err:
+            # a cavity the batch does not take (walls through the nodes with FP16 storage or on
+            # a lattice smaller than one two-step tile) is stepped on its own each chunk
+            if getattr(err, "status", None) != _lbm.EINVAL:
+                raise
+            self.solo.add(id(s))
         self.active.append([s, req, now, need, 0])
         self.used += need
         return True

@@ -55,7 +55,9 @@ class FakeBatch:
 
     def attach(self, s):
         assert len(self.members) < self.cap
-        assert not s.node_walls, "cavities with walls through the nodes are not batched"
+        if s.node_walls and s.nx < 64:      # as the library: too small for a two-step tile
+            from paper_1708_07525_amd.lbm import EINVAL, LbmError
+            raise LbmError(EINVAL, "walls through the boundary nodes on a small lattice are not batched")
         self.members.append(s)
 
     def detach(self, s):
@@ -149,8 +151,9 @@ def test_chunk_must_divide_check_interval():
 
 
 def test_node_wall_cavities_step_beside_the_batch():
-    """A cavity with walls through the boundary nodes is never attached to the batch; it is
-    stepped by itself each chunk and stops at the same step as when served alone."""
+    """A cavity the batch refuses (here: walls through the boundary nodes on a small lattice) is
+    stepped by itself each chunk and stops at the same step as when served alone; the others,
+    node-wall cavities the batch takes included, advance in the batch."""
     from paper_1708_07525_amd.lbm import node_walls
     assert node_walls(dict(sides=("nee_hot", "nee_cold", "nee_adiabatic", "nee_adiabatic")))
     assert node_walls(dict(sides=(4, 5, 6, 6)))

@@ -27,8 +27,8 @@ def _requests(node_walls=False):
 
 @pytest.mark.parametrize("node_walls", [False, True])
 def test_alone_equals_mixed(node_walls):
-    """With node_walls, two of the six requests have walls through the boundary nodes and are
-    stepped beside the batch."""
+    """With node_walls, two of the six requests have walls through the boundary nodes: the
+    batch takes an FP32 one of a full two-step tile, the others are stepped beside it."""
     from paper_1708_07525_amd.serving import Request, Server
     reqs = _requests(node_walls)
     mixed = Server(10 ** 10, max_slots=8, chunk=100, check_every=500, tol=1e-6, max_steps=3000, keep_fields=True)
