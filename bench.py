@@ -335,8 +335,9 @@ def precision_report(a):
 
 def sweep_until_converged(a, cav):
     """Every cavity of the sweep to steady state (K-step velocity residual below 1e-8, checked
-    every 1000 steps) or the step cap: all together through the continuous-batching loop, then
-    the same solves one by one with one plain launch per step (one-step kernel, no graph)."""
+    every 10 replay chunks) or the step cap: all together through the continuous-batching loop,
+    then the same solves one by one with one plain launch per step (one-step kernel, no graph),
+    checked at the same steps."""
     import torch
     import workloads
     from paper_1708_07525_amd import Solver
@@ -365,8 +366,8 @@ def sweep_until_converged(a, cav):
         s.set_steps_per_launch(1)
         n = 0
         while True:
-            s.step(1000)
-            n += 1000
+            s.step(10 * a.chunk)
+            n += 10 * a.chunk
             ob = s.observables()
             if converged(ob, 1e-8, 1e-12 * max(s.derived()["U"], 1e-30)) or ob["nonfinite"] or n >= cap:
                 break
