@@ -20,7 +20,7 @@ SIDE = {"hot": 0, "cold": 1, "adiabatic": 2, "periodic": 3,
         "nee_hot": 4, "nee_cold": 5, "nee_adiabatic": 6, "nee_robin": 7}
 MUTATION = {"none": 0, "no_source": 1, "no_half_force": 2, "rho_in_meq": 3, "buoy_sign": 4,
             "model_a_diff": 5, "no_forch": 6, "wall_const": 7, "ergun_exp": 8, "wall_vel": 9,
-            "model_a_map": 10}
+            "model_a_map": 10, "nee_wall_vel": 11}
 
 # Section 4 constants: rho0 = J = sigma = 1, varpi = 2/5 (here: automatic, see varpi),
 # s_rho = s_j = 1, s_e = s_eps = 1.1, s_q = 1.2, zeta0 = eta0 = 1, zeta_e,eps = eta_e,eps = 1.5.

@@ -648,8 +648,9 @@ static void apply_nee(orc *o) {
         boundary_scalar(o, kind, qf.C, qff.C, 1, &Cb);
       } else {
         const int side = onx ? sx : sy;
-        if (onx) uby = p->wall_u[side];
-        else ubx = p->wall_u[side];
+        const double uw = p->mutation == ORC_MUT_NEE_WALL_VEL ? 0.0 : p->wall_u[side];
+        if (onx) uby = uw;
+        else ubx = uw;
         boundary_scalar(o, p->side[side], qf.T, qff.T, 0, &Tb);
         boundary_scalar(o, p->side[side], qf.C, qff.C, 1, &Cb);
       }

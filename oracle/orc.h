@@ -43,7 +43,8 @@ enum {
   ORC_MUT_WALL_CONST = 7,     /* anti-bounce-back constant w_i*T_w instead of 2*w_i*T_w */
   ORC_MUT_ERGUN_EXP = 8,      /* phi^2 instead of phi^3 under the root of Eq. (7)       */
   ORC_MUT_WALL_VEL = 9,       /* moving-wall term of the bounce-back halved             */
-  ORC_MUT_MODEL_A_MAP = 10    /* Model-A equilibria with the present diffusivity mapping */
+  ORC_MUT_MODEL_A_MAP = 10,   /* Model-A equilibria with the present diffusivity mapping */
+  ORC_MUT_NEE_WALL_VEL = 11   /* node walls: equilibrium of Eq. (33) at rest, not the wall's velocity */
 };
 
 typedef struct orc_params {

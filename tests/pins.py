@@ -306,6 +306,23 @@ def couette(make, ny=16, U=0.01, phi=0.7, nu=0.1, steps=20000, **extra):
     return float(np.abs(F["ux"] - exact[:, None]).max() / U), float(np.abs(F["uy"]).max())
 
 
+def couette_node_walls(make, ny=17, U=0.01, phi=0.7, nu=0.1, steps=20000, **extra):
+    """Plane Couette flow between walls through the first and last rows of nodes (Eqs. 33-35):
+    x periodic, the bottom row at rest, the top row moving with U (the wall velocity in the
+    equilibrium of Eq. 33), no force and no drag.  The steady profile is linear through the
+    nodes, u_x = U y/(ny - 1), and the extrapolation is exact for it (the non-equilibrium part
+    of a linear profile is the same at every node).  Returns max |u_x - exact| / U and
+    max |u_y|."""
+    p = dict(nx=3, ny=ny, sides=("periodic", "periodic", "nee_adiabatic", "nee_adiabatic"),
+             wall_u=(0.0, 0.0, 0.0, U), phi=phi, nu=nu, alpha_e=0.1, D_e=0.1, K=1e30, **NO_FLOW)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps)
+    F = s.fields()
+    exact = U * np.arange(ny) / (ny - 1)
+    return float(np.abs(F["ux"] - exact[:, None]).max() / U), float(np.abs(F["uy"]).max())
+
+
 def layered_darcy(make, nx=80, ny=3, phis=(0.4, 0.8), K_mean=1.0, nu=0.05, G=1e-5, steps=3000, **extra):
     """Flow along two porous layers (x < nx/2 and x >= nx/2, periodic in x and y), driven by a
     constant acceleration G along y, without Forchheimer term.  Far from the interface each

@@ -239,6 +239,13 @@ def test_couette_flow_is_exact():
     assert e < 1e-11 and uy < 1e-13
 
 
+def test_couette_flow_between_node_walls_is_exact():
+    """The wall velocity in the equilibrium of Eq. (33): plane Couette flow between walls
+    through the first and last rows of nodes has the exact linear profile through the nodes."""
+    e, uy = pins.couette_node_walls(make_oracle)
+    assert e < 1e-11 and uy < 1e-13
+
+
 @pytest.mark.parametrize("which,kw", [("T", dict(sigma=3.0)), ("C", dict(phi=0.5))])
 def test_model_a_diffusivity(which, kw):
     """Model-A (Eqs. 30-32): with its coupled equilibria the diffusivity is alpha_e =
@@ -423,6 +430,11 @@ def test_mutation_ergun_exponent_is_caught():
 
 def test_mutation_moving_wall_term_is_caught():
     e, _ = pins.couette(make_mutant("wall_vel"))
+    assert e > 0.1
+
+
+def test_mutation_node_wall_velocity_is_caught():
+    e, _ = pins.couette_node_walls(make_mutant("nee_wall_vel"))
     assert e > 0.1
 
 

@@ -620,6 +620,15 @@ def test_gpu_node_wall_pins():
     assert eT < 1e-11 and Nu == pytest.approx(exact, abs=1e-10)
     assert pins.nee_poiseuille(make_gpu("fp64"), 33) < 3e-3
     assert pins.cavity_symmetry(make_gpu("fp64"), sides=pins.NODE_CAVITY) < 1e-12
+    e, uy = pins.couette_node_walls(make_gpu("fp64"))
+    assert e < 1e-11 and uy < 1e-13
+
+
+def test_gpu_couette_flow_is_exact():
+    """The moving-wall term of the half-way bounce-back: the exact linear Couette profile on the
+    GPU path (FP64), as in the oracle's pin."""
+    e, uy = pins.couette(make_gpu("fp64"))
+    assert e < 1e-11 and uy < 1e-13
 
 
 @pytest.mark.parametrize("chunk,tune", [(100, False), (120, True)])
