@@ -49,6 +49,58 @@ def brinkman_poiseuille(make, nx, J=2.0, nu=0.05, K16=50.0, phi=0.7, G=1e-5, ste
     return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
 
 
+def brinkman_forchheimer_reference(nx, nu_e, a, b, phiG, m=200):
+    """Steady channel flow of Eq. (2) with the force of Eq. (5): nu_e u'' - a u - b |u| u + phi G
+    = 0 between no-slip walls at x = -1/2 and nx - 1/2, by second-order finite differences on
+    m points per lattice spacing, Newton's method, and one Richardson step between m and 2m;
+    returns u at the nodes x = 0 .. nx - 1."""
+    from scipy.linalg import solve_banded
+
+    def solve(mm):
+        n = nx * mm - 1                      # interior points; walls at both ends
+        h = 1.0 / mm
+        u = np.full(n, phiG / a)
+        for _ in range(60):
+            lap = np.empty(n)
+            lap[1:-1] = u[:-2] - 2 * u[1:-1] + u[2:]
+            lap[0] = -2 * u[0] + u[1]
+            lap[-1] = u[-2] - 2 * u[-1]
+            r = nu_e * lap / h ** 2 - a * u - b * np.abs(u) * u + phiG
+            ab = np.zeros((3, n))
+            ab[0, 1:] = nu_e / h ** 2
+            ab[2, :-1] = nu_e / h ** 2
+            ab[1, :] = -2 * nu_e / h ** 2 - a - 2 * b * np.abs(u)
+            du = solve_banded((1, 1), ab, -r)
+            u += du
+            if np.abs(du).max() < 1e-15 * np.abs(u).max():
+                break
+        # node x_j = j sits at interior index (j + 1/2) mm - 1
+        return u[[(j * mm + mm // 2) - 1 for j in range(nx)]]
+
+    u1, u2 = solve(m), solve(2 * m)
+    return u2 + (u2 - u1) / 3.0
+
+
+def brinkman_forchheimer_poiseuille(make, nx, J=2.0, nu=0.05, K16=5.0, phi=0.7, G16=1e-4, F16=2.2,
+                                    steps=None, **extra):
+    """Channel flow as brinkman_poiseuille, with the Forchheimer term of Eq. (5): nu_e u'' -
+    (phi nu/K) u - (phi F_phi/sqrt K) |u| u + phi G = 0.  K grows as nx^2, G as 1/nx^2 and F_phi as
+    1/nx, so that the profile is the same at every nx: the channel is about four Brinkman
+    lengths wide, and the Forchheimer drag lowers the core velocity from 0.0076 to 0.0056.
+    Reference: brinkman_forchheimer_reference.  Returns the relative L2 error of u_y."""
+    K = K16 * (nx / 16.0) ** 2
+    G = G16 * (16.0 / nx) ** 2
+    Fphi = F16 * 16.0 / nx
+    p = dict(nx=nx, ny=3, sides=("adiabatic", "adiabatic", "periodic", "periodic"), J=J, phi=phi,
+             nu=nu, alpha_e=0.1, D_e=0.1, K=K, g_ext=(0.0, G), direct=1, gbT=0.0, gbC=0.0, Fphi=Fphi)
+    p.update(extra)
+    s = make(p, T=0.5, C=0.5)
+    s.step(steps or int(20 * nx * nx / (J * nu)))
+    u = s.fields()["uy"][1]
+    ua = brinkman_forchheimer_reference(nx, J * nu, phi * nu / K, phi * Fphi / np.sqrt(K), phi * G)
+    return float(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
+
+
 def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G=(6e-4, 2e-3), Fphi_ref=None,
                           **extra):
     """A fully periodic, spatially uniform state under a constant acceleration G.  Then

@@ -216,6 +216,27 @@ def test_brinkman_poiseuille_second_order():
     assert 3.5 < e16 / e32 < 4.5, (e16, e32)
 
 
+def test_forchheimer_channel_reference_reduces_to_the_brinkman_closed_form():
+    """The finite-difference reference of the Brinkman-Forchheimer channel, without the
+    Forchheimer term, against the closed form of the Brinkman channel."""
+    nx, nu_e, K, phi, G, nu = 16, 0.1, 50.0, 0.7, 1e-5, 0.05
+    u = pins.brinkman_forchheimer_reference(nx, nu_e, phi * nu / K, 0.0, phi * G)
+    x = np.arange(nx)
+    r = np.sqrt(phi * nu / (nu_e * K))
+    exact = (G * K / nu) * (1 - np.cosh(r * (x - (nx - 1) / 2)) / np.cosh(r * nx / 2))
+    assert np.abs(u - exact).max() < 1e-12 * exact.max()
+
+
+def test_brinkman_forchheimer_channel_second_order():
+    """Eq. (5) with its Forchheimer term in a channel four Brinkman lengths wide (the term lowers
+    the core velocity by a quarter): the steady profile against the finite-difference reference,
+    second order (error ratio about 4 per halving)."""
+    e16 = pins.brinkman_forchheimer_poiseuille(make_oracle, 16)
+    e32 = pins.brinkman_forchheimer_poiseuille(make_oracle, 32)
+    assert e32 < 1e-3
+    assert 3.5 < e16 / e32 < 4.5, (e16, e32)
+
+
 def test_uniform_force_recurrence_and_darcy_forchheimer_limit():
     err, got, closed = pins.uniform_force_history(make_oracle)
     assert err < 1e-14
@@ -431,6 +452,10 @@ def test_mutation_ergun_exponent_is_caught():
 def test_mutation_moving_wall_term_is_caught():
     e, _ = pins.couette(make_mutant("wall_vel"))
     assert e > 0.1
+
+
+def test_mutation_no_forchheimer_fails_the_channel_pin():
+    assert pins.brinkman_forchheimer_poiseuille(make_mutant("no_forch"), 16) > 0.1
 
 
 def test_mutation_node_wall_velocity_is_caught():

@@ -246,6 +246,10 @@ def test_gpu_linear_conduction_exact():
 
 def test_gpu_brinkman_poiseuille():
     assert pins.brinkman_poiseuille(make_gpu("fp64"), 32) < 1e-3
+    # with the Forchheimer term of Eq. (5), against the finite-difference channel reference
+    e16 = pins.brinkman_forchheimer_poiseuille(make_gpu("fp64"), 16)
+    e32 = pins.brinkman_forchheimer_poiseuille(make_gpu("fp64"), 32)
+    assert e32 < 1e-3 and 3.5 < e16 / e32 < 4.5, (e16, e32)
 
 
 def test_gpu_uniform_force_recurrence():
