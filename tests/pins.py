@@ -154,11 +154,14 @@ def uniform_force_history(make, steps=200, phi=0.5, nu=0.05, K=20.0, Fphi=0.3, G
     return err, got, float(closed)
 
 
-def sine_decay(make, nx=64, sigma=1.0, phi=1.0, alpha=0.05, u0=0.0, which="T", t1=300, steps=2000, **extra):
+def sine_decay(make, nx=64, sigma=1.0, phi=1.0, alpha=0.05, u0=0.0, which="T", t1=300, steps=2000,
+               exact_operator=False, **extra):
     """A sine mode of T (or C) in a fully periodic domain, at rest or carried by a uniform
     flow u0 (no porous drag, no buoyancy).  Eqs. (3)-(4) give the amplitude decay rate
     alpha_e k^2/sigma (D_e k^2/phi) per step and the phase speed u0/sigma (u0/phi).
-    Returns the relative error of the measured rate between steps t1 and t1 + steps."""
+    Returns the relative error of the measured rate between steps t1 and t1 + steps, against
+    that rate or, with exact_operator (at rest), against the exact rate of the discrete step
+    (d2q5_mode_rate)."""
     p = dict(nx=nx, ny=3, sides=PERIODIC, nu=0.05, alpha_e=alpha, D_e=alpha, K=1e30, sigma=sigma,
              phi=phi, varpi=0.4, **NO_FLOW)
     p.update(extra)
@@ -177,7 +180,31 @@ def sine_decay(make, nx=64, sigma=1.0, phi=1.0, alpha=0.05, u0=0.0, which="T", t
     s.step(steps)
     a1 = amp()
     rate = -np.log(a1 / a0) / steps
+    if exact_operator:
+        return float(rate / d2q5_mode_rate(nx, cap, p["varpi"], alpha) - 1.0)
     return float(rate / (alpha * k * k / cap) - 1.0)
+
+
+def d2q5_mode_rate(nx, cap, varpi, diff, rate_e=1.5, rate_eps=1.5):
+    """Exact per-step decay rate of the slowest sine mode (wavenumber 2 pi/nx along x) of the
+    D2Q5 scheme at rest, present model: the linear step operator on the mode's 5 amplitudes is
+    pull streaming (phase exp(-i k e_x) per direction) after the moment-space collision of
+    Eqs. (21)-(22), g* = g - N^-1 Theta N (g - g^eq), with the equilibrium of Eq. (28) at rest,
+    g0^eq = (cap - varpi) T, g_i^eq = varpi T/4, T = sum g/cap (cap = sigma for g, phi for h),
+    N of Eq. (23) and Theta = diag(1, z, z, rate_e, rate_eps), z = 1/(1/2 + diff/(varpi/2)) from
+    Eq. (29).  Returns -ln of its eigenvalue of largest modulus."""
+    N = np.array([[1, 1, 1, 1, 1], [0, 1, 0, -1, 0], [0, 0, 1, 0, -1], [-4, 1, 1, 1, 1], [0, 1, -1, 1, -1]],
+                 dtype=float)
+    z = 1.0 / (0.5 + diff / (varpi / 2.0))
+    theta = np.diag([1.0, z, z, rate_e, rate_eps])
+    w = np.array([cap - varpi, varpi / 4, varpi / 4, varpi / 4, varpi / 4])
+    W = np.outer(w, np.ones(5)) / cap
+    k = 2 * np.pi / nx
+    ex = np.array([0, 1, 0, -1, 0])
+    P = np.diag(np.exp(-1j * k * ex))
+    A = P @ (np.eye(5) - np.linalg.solve(N, theta @ N) @ (np.eye(5) - W))
+    lam = np.linalg.eigvals(A)
+    return float(-np.log(np.abs(lam).max()))
 
 
 def sine_phase_speed(make, nx=128, sigma=2.0, u0=0.05, steps=400, **extra):

@@ -252,6 +252,14 @@ def test_gpu_brinkman_poiseuille():
     assert e32 < 1e-3 and 3.5 < e16 / e32 < 4.5, (e16, e32)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_gpu_d2q5_decay_equals_the_exact_step_operator(prec, tol):
+    """The decay of a sine mode of T (sigma = 2) and of C (phi = 0.5) on the GPU path against the
+    exact eigenvalue of the D2Q5 step operator, as in the oracle's pin."""
+    assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, sigma=2.0)) < tol
+    assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, phi=0.5, which="C")) < tol
+
+
 def test_gpu_uniform_force_recurrence():
     err, got, closed = pins.uniform_force_history(make_gpu("fp64"), steps=50)
     assert err < 1e-14 and got == pytest.approx(closed, rel=1e-12)
