@@ -181,28 +181,34 @@ def sine_decay(make, nx=64, sigma=1.0, phi=1.0, alpha=0.05, u0=0.0, which="T", t
     a1 = amp()
     rate = -np.log(a1 / a0) / steps
     if exact_operator:
-        return float(rate / d2q5_mode_rate(nx, cap, p["varpi"], alpha) - 1.0)
+        return float(rate / d2q5_mode_rate(nx, cap, p["varpi"], alpha, u0) - 1.0)
     return float(rate / (alpha * k * k / cap) - 1.0)
 
 
-def d2q5_mode_rate(nx, cap, varpi, diff, rate_e=1.5, rate_eps=1.5):
+def d2q5_mode_rate(nx, cap, varpi, diff, u0=0.0, rate_e=1.5, rate_eps=1.5):
     """Exact per-step decay rate of the slowest sine mode (wavenumber 2 pi/nx along x) of the
-    D2Q5 scheme at rest, present model: the linear step operator on the mode's 5 amplitudes is
-    pull streaming (phase exp(-i k e_x) per direction) after the moment-space collision of
-    Eqs. (21)-(22), g* = g - N^-1 Theta N (g - g^eq), with the equilibrium of Eq. (28) at rest,
-    g0^eq = (cap - varpi) T, g_i^eq = varpi T/4, T = sum g/cap (cap = sigma for g, phi for h),
-    N of Eq. (23) and Theta = diag(1, z, z, rate_e, rate_eps), z = 1/(1/2 + diff/(varpi/2)) from
-    Eq. (29).  Returns -ln of its eigenvalue of largest modulus."""
+    D2Q5 scheme, present model, in a uniform flow u0 along x (0: at rest).  The state of the
+    mode is its 5 population amplitudes and the previous step's T (kept for Eq. 27); one step is
+    the moment-space collision of Eqs. (21)-(22) with the source term,
+    n* = n - Theta (n - n^eq) + (I - Theta/2) (0, u0 (T - T_prev), 0, 0, 0),
+    n^eq = (cap T, u0 T, 0, (5 varpi - 4 cap) T, 0) (Eq. 24), T = sum g/cap (cap = sigma for g,
+    phi for h), N of Eq. (23), Theta = diag(1, z, z, rate_e, rate_eps) with z = 1/(1/2 +
+    diff/(varpi/2)) (Eq. 29), followed by pull streaming (phase exp(-i k e_x) per direction).
+    Returns -ln of the modulus of the step operator's eigenvalue of largest modulus."""
     N = np.array([[1, 1, 1, 1, 1], [0, 1, 0, -1, 0], [0, 0, 1, 0, -1], [-4, 1, 1, 1, 1], [0, 1, -1, 1, -1]],
                  dtype=float)
+    Ni = np.linalg.inv(N)
     z = 1.0 / (0.5 + diff / (varpi / 2.0))
-    theta = np.diag([1.0, z, z, rate_e, rate_eps])
-    w = np.array([cap - varpi, varpi / 4, varpi / 4, varpi / 4, varpi / 4])
-    W = np.outer(w, np.ones(5)) / cap
+    th = np.diag([1.0, z, z, rate_e, rate_eps])
+    t = np.ones((1, 5)) / cap                                  # T = t g
+    q = np.array([[cap], [u0], [0.0], [5 * varpi - 4 * cap], [0.0]])
+    src = (np.eye(5) - th / 2) @ np.array([[0.0], [u0], [0.0], [0.0], [0.0]])
     k = 2 * np.pi / nx
-    ex = np.array([0, 1, 0, -1, 0])
-    P = np.diag(np.exp(-1j * k * ex))
-    A = P @ (np.eye(5) - np.linalg.solve(N, theta @ N) @ (np.eye(5) - W))
+    P = np.diag(np.exp(-1j * k * np.array([0, 1, 0, -1, 0])))
+    A = np.zeros((6, 6), dtype=complex)
+    A[:5, :5] = P @ Ni @ ((np.eye(5) - th) @ N + th @ q @ t + src @ t)
+    A[:5, 5:] = P @ Ni @ (-src)
+    A[5:, :5] = t
     lam = np.linalg.eigvals(A)
     return float(-np.log(np.abs(lam).max()))
 

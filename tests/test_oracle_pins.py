@@ -291,17 +291,23 @@ def test_thermal_diffusivity_is_independent_of_sigma(sigma):
 
 
 @pytest.mark.parametrize("kw", [dict(sigma=1.0), dict(sigma=2.0), dict(sigma=3.0, nx=32),
-                                dict(phi=0.5, which="C")])
+                                dict(phi=0.5, which="C"), dict(sigma=2.0, u0=0.05), dict(sigma=1.0, u0=0.05),
+                                dict(phi=0.5, which="C", u0=0.05)])
 def test_d2q5_decay_equals_the_exact_step_operator(kw):
-    """The measured decay of a sine mode at rest equals, to 1e-9, the largest eigenvalue of the
-    D2Q5 step operator written out independently from Eqs. (21)-(23), (28) and (29) (streaming
-    phases times the moment-space collision); exact, where the Chapman-Enskog rate holds to
-    O(k^2)."""
+    """The measured decay of a sine mode, at rest or carried by a uniform flow, equals to 1e-9
+    the eigenvalue of largest modulus of the D2Q5 step operator written out independently from
+    Eqs. (21)-(24), (27)-(29) (streaming phases times the moment-space collision with the source
+    term, the previous step's T as a sixth state variable); exact, where the Chapman-Enskog rate
+    holds to O(k^2)."""
     assert abs(pins.sine_decay(make_oracle, exact_operator=True, **kw)) < 1e-9
 
 
 def test_mutation_model_a_diffusivity_fails_the_exact_operator():
     assert abs(pins.sine_decay(make_mutant("model_a_diff"), exact_operator=True, sigma=2.0)) > 1e-2
+
+
+def test_mutation_no_source_fails_the_exact_operator():
+    assert abs(pins.sine_decay(make_mutant("no_source"), exact_operator=True, sigma=2.0, u0=0.05)) > 1e-3
 
 
 @pytest.mark.parametrize("phi", [1.0, 0.5])

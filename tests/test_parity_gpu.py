@@ -258,6 +258,7 @@ def test_gpu_d2q5_decay_equals_the_exact_step_operator(prec, tol):
     exact eigenvalue of the D2Q5 step operator, as in the oracle's pin."""
     assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, sigma=2.0)) < tol
     assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, phi=0.5, which="C")) < tol
+    assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, sigma=2.0, u0=0.05)) < tol
 
 
 def test_gpu_uniform_force_recurrence():
