@@ -213,6 +213,55 @@ def d2q5_mode_rate(nx, cap, varpi, diff, u0=0.0, rate_e=1.5, rate_eps=1.5):
     return float(-np.log(np.abs(lam).max()))
 
 
+def d2q9_shear_rate(nx, nu_e, rates=(1.0, 1.1, 1.1, 1.0, 1.2, 1.0, 1.2), rho0=1.0):
+    """Exact per-step decay rate of a shear wave u_y = A sin(2 pi x/nx) of the D2Q9 scheme at
+    small amplitude, without drag or force: the linear step operator on the mode's 9 population
+    amplitudes is pull streaming after the moment-space collision of Eq. (10),
+    f* = f - M^-1 S M (f - f^eq), with M built from the Lallemand-Luo polynomials (Eq. 13), the
+    equilibrium of Eq. (20) to first order in u, w_i (rho + rho0 3 e_i.u) with u = j/rho0 (Eqs.
+    17-19 with no drag), and S = diag(s_rho, s_e, s_eps, s_j, s_q, s_j, s_q, s_v, s_v), s_v =
+    1/(1/2 + 3 nu_e) (section 2.2).  `rates` are (s_rho, s_e, s_eps, s_j, s_q, s_j, s_q).
+    Returns -ln of the modulus of the eigenvalue of the shear mode (the eigenvector that carries
+    j_y)."""
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    e2 = ex ** 2 + ey ** 2
+    M = np.array([np.ones(9), -4 + 3 * e2, 4 - 10.5 * e2 + 4.5 * e2 ** 2, ex, (-5 + 3 * e2) * ex, ey,
+                  (-5 + 3 * e2) * ey, ex ** 2 - ey ** 2, ex * ey])
+    sv = 1.0 / (0.5 + 3.0 * nu_e)
+    S = np.diag(list(rates) + [sv, sv])
+    E = np.outer(w, np.ones(9)) + 3 * np.outer(w * ex, ex) + 3 * np.outer(w * ey, ey)
+    k = 2 * np.pi / nx
+    P = np.diag(np.exp(-1j * k * ex))
+    A = P @ (np.eye(9) - np.linalg.solve(M, S @ M) @ (np.eye(9) - E))
+    lam, vec = np.linalg.eig(A)
+    jy = np.abs(ey @ vec) / np.linalg.norm(vec, axis=0)
+    return float(-np.log(np.abs(lam[np.argmax(jy)])))
+
+
+def shear_wave_decay(make, nx=64, nu=0.05, J=1.0, A=1e-5, t1=400, steps=2000, **extra):
+    """A shear wave u_y = A sin(2 pi x/nx) in a fully periodic domain without drag, force or
+    buoyancy: the measured per-step decay rate of its amplitude between steps t1 and
+    t1 + steps, relative to the exact rate of the linear step operator (d2q9_shear_rate), minus
+    one."""
+    p = dict(nx=nx, ny=3, sides=PERIODIC, nu=nu, J=J, alpha_e=0.05, D_e=0.05, K=1e30, phi=0.8, **NO_FLOW)
+    p.update(extra)
+    k = 2 * np.pi / nx
+    uy = A * np.sin(k * np.arange(nx))[None, :].repeat(3, 0)
+    s = make(p, T=0.5, C=0.5, uy=uy)
+
+    def amp():
+        return np.abs(np.fft.fft(s.fields()["uy"][1])[1])
+
+    s.step(t1)
+    a0 = amp()
+    s.step(steps)
+    a1 = amp()
+    rate = -np.log(a1 / a0) / steps
+    return float(rate / d2q9_shear_rate(nx, J * nu) - 1.0)
+
+
 def sine_phase_speed(make, nx=128, sigma=2.0, u0=0.05, steps=400, **extra):
     """Phase speed of an advected sine mode of T relative to u0/sigma (Eq. 3)."""
     p = dict(nx=nx, ny=3, sides=PERIODIC, nu=0.05, alpha_e=0.05, D_e=0.05, K=1e30, sigma=sigma,

@@ -261,6 +261,11 @@ def test_gpu_d2q5_decay_equals_the_exact_step_operator(prec, tol):
     assert abs(pins.sine_decay(make_gpu(prec), exact_operator=True, sigma=2.0, u0=0.05)) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_gpu_d2q9_shear_wave_equals_the_exact_step_operator(prec, tol):
+    assert abs(pins.shear_wave_decay(make_gpu(prec), A=1e-5 if prec == "fp64" else 1e-3)) < tol
+
+
 def test_gpu_uniform_force_recurrence():
     err, got, closed = pins.uniform_force_history(make_gpu("fp64"), steps=50)
     assert err < 1e-14 and got == pytest.approx(closed, rel=1e-12)
