@@ -525,7 +525,11 @@ def test_batch_tile_shapes_change_nothing(shape, chunk):
              (workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "cold", "hot"),
                                       wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp32"),
              (workloads.cavity_params(nx=70, ny=37, sides=("periodic", "periodic", "cold", "hot"),
-                                      wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp64")]
+                                      wall_u=(0.0, 0.0, 0.0, 0.05), Ra=5e4), "fp64"),
+             # lattices smaller than one tile, walled and periodic
+             (workloads.cavity_params(nx=5, ny=7, sides=("periodic", "periodic", "cold", "hot"), Ra=3e3), "fp32"),
+             (workloads.cavity_params(nx=3, ny=3), "fp64"),
+             (workloads.cavity_params(nx=6, ny=4), "fp16s")]
     steps = 2 * chunk + 8     # two replays and 8 more
     alone = []
     for i, (p, prec) in enumerate(specs):
@@ -545,7 +549,7 @@ def test_batch_tile_shapes_change_nothing(shape, chunk):
         chosen = b.autotune(8)
         print("batch autotune:", chosen, flush=True)
         assert set(chosen) == {("fp32", "<=64"), ("fp32", "<=128"), ("fp16s", "<=256"), ("fp64", ">256"),
-                               ("fp64", "<=128")}
+                               ("fp64", "<=128"), ("fp64", "<=64"), ("fp16s", "<=64")}
     else:
         for prec in ("fp64", "fp32", "fp16s"):
             if shape == 3 and prec == "fp16s":
