@@ -14,6 +14,10 @@ import json
 import os
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_dd", "autotune.json")
+# part of every key: raised when the kernels' launch choices change (three steps per launch for
+# FP32, a three-step tile with its rest populations in registers), so that choices timed with
+# older kernels are not applied to newer ones
+KERNEL_GENERATION = 2
 
 
 def cache_path() -> str:
@@ -29,7 +33,8 @@ def size_class(n: int) -> int:
 
 
 def key(device_name: str, precision: str, nx: int, ny: int, porosity_field: bool, node_walls: bool = False) -> str:
-    k = f"{device_name}|{precision}|{size_class(nx)}x{size_class(ny)}|{'field' if porosity_field else 'uniform'}"
+    k = (f"g{KERNEL_GENERATION}|{device_name}|{precision}|{size_class(nx)}x{size_class(ny)}|"
+         f"{'field' if porosity_field else 'uniform'}")
     return k + "|node-walls" if node_walls else k
 
 

@@ -33,8 +33,9 @@ class FakeSolver:
 
 def test_size_class_and_key():
     assert [autotune.size_class(n) for n in (1, 3, 64, 65, 2048)] == [1, 4, 64, 128, 2048]
-    assert autotune.key("MI355X", "fp32", 100, 200, True) == "MI355X|fp32|128x256|field"
-    assert autotune.key("MI355X", "fp32", 100, 200, True, node_walls=True) == "MI355X|fp32|128x256|field|node-walls"
+    g = f"g{autotune.KERNEL_GENERATION}"
+    assert autotune.key("MI355X", "fp32", 100, 200, True) == g + "|MI355X|fp32|128x256|field"
+    assert autotune.key("MI355X", "fp32", 100, 200, True, node_walls=True) == g + "|MI355X|fp32|128x256|field|node-walls"
 
 
 def test_tune_times_once_per_class(tmp_path):
