@@ -185,11 +185,17 @@ lbm_status lbm_observables_static(struct lbm_ctx *c, lbm_obs *out, double *field
  * order, each ny rows of nx) without touching the residual snapshot.  Synchronises. */
 lbm_status lbm_get_fields(struct lbm_ctx *c, double *fields);
 
-/* Lattice values derived from the parameters (valid after lbm_set_fields). */
+/* Lattice values derived from the parameters (valid after lbm_set_fields): wall distance L,
+ * velocity scale U (section 4.1) and viscosities nu, nu_e, diffusivities alpha_e, D_e, the
+ * relaxation rates s_v, zeta_alpha, eta_D of Eqs. (10) and (29), varpi and c_sT^2 = varpi/2
+ * (Eq. 28), g beta_T and g beta_C (Eq. 6), T0, C0, dT, dC, the mean permeability, the smallest
+ * porosity and the FP16 storage pre-scale. */
 typedef struct lbm_derived {
   double L, U, nu, nu_e, alpha_e, D_e, s_v, zeta_a, eta_D, varpi, csT2;
   double gbT, gbC, T0, C0, dT, dC, K_mean, phi_min, fp16_scale;
 } lbm_derived;
+/* Copies the context's derived values into *out (caller-owned).  LBM_EINVAL for NULL
+ * arguments, LBM_ESTATE before lbm_set_fields. */
 lbm_status lbm_get_derived(const struct lbm_ctx *c, lbm_derived *out);
 
 /* The same lattice values computed on the host alone, for the uniform porosity p->phi (the
