@@ -155,9 +155,10 @@ def test_table4_with_extrapolation_walls():
     distance 128): moving top wall held hot, bottom cold, adiabatic sides.  The sweep
     continues in N from N = 0, each run starting from the previous steady fields.  Measured:
     1.0-4.8% below the paper (largest at N = 500); refining to 257 and 513 nodes moves the
-    values onto those of the half-way walls (about 1% below the paper).  For N <= -1000 a run
-    at this resolution leaves the steady branch for a slow oscillation; N = -1000 is checked on a
-    finer grid by the next test."""
+    values toward the paper's at first order (test_table4_extrapolation_walls_grid_convergence).
+    For N <= -1000 a run at this resolution leaves the steady branch for a slow oscillation;
+    N = -1000 is checked on a finer grid
+    (test_table4_extrapolation_walls_strong_opposing_buoyancy)."""
     from paper_1708_07525_amd import Solver
     ref = json.load(open(os.path.join(GOLDEN, "table4_lid_driven.json")))
     paper = dict(zip(ref["N"], ref["Nu_bottom"]))
@@ -181,6 +182,50 @@ def test_table4_with_extrapolation_walls():
         assert steps < 600000, N
         assert Nu == pytest.approx(Sh, rel=1e-6), N
         assert Nu == pytest.approx(paper[N], rel=0.05), N
+
+
+def test_table4_extrapolation_walls_grid_convergence():
+    """The node-wall rows of Table 4 under grid refinement (129, 257, 513 nodes a side, each
+    sweep continued in N from N = 0 as above).  Measured Nu at N = 0 / 100 / 500: 2.0695 /
+    1.4408 / 1.1619 (129), 2.0778 / 1.4523 / 1.1848 (257), 2.0829 / 1.4589 / 1.1968 (513).
+    The values rise toward the paper's with each halving of the spacing, the differences
+    shrinking about twofold (first order: the zero-flux node rule of the adiabatic sides leaks a
+    first-order flux), and the first-order extrapolation 2 Nu(513) - Nu(257) lands within 1.1%
+    of the paper.  At 257 nodes the whole N = -750..500 sweep is within 3% (0.9-3.0% low)."""
+    from paper_1708_07525_amd import Solver
+    paper = dict(zip(*(json.load(open(os.path.join(GOLDEN, "table4_lid_driven.json")))[k]
+                       for k in ("N", "Nu_bottom"))))
+
+    def sweep(n, branches):
+        out = {}
+        for branch in branches:
+            init = dict(T=0.5, C=0.5) if branch[0] == 0 else start
+            for N in branch:
+                p = lid_driven_params(N, n=n)
+                p["sides"] = ("nee_adiabatic", "nee_adiabatic", "nee_cold", "nee_hot")
+                s = Solver(p, precision="fp64", **init)
+                ob, steps = run_to_steady(s, chunk=10000, tol=1e-11, cap=1500000, scalars=True)
+                F = s.fields()
+                init = dict(T=F["T"], C=F["C"], ux=F["ux"], uy=F["uy"])
+                if N == 0:
+                    start = init
+                s.close()
+                print(f"table 4 (extrapolation walls, {n}^2): N={N} Nu={ob['Nu'][2]:.5f} Sh={ob['Sh'][2]:.5f} "
+                      f"paper={paper[N]} steps={steps}", flush=True)
+                assert steps < 1500000, (n, N)
+                assert ob["Nu"][2] == pytest.approx(ob["Sh"][2], rel=1e-6), (n, N)
+                out[N] = ob["Nu"][2]
+        return out
+
+    short = ([0, 100, 500],)
+    nu = {129: sweep(129, short), 257: sweep(257, ([0, -100, -250, -500, -750], [100, 500])), 513: sweep(513, short)}
+    for N, v in nu[257].items():
+        assert v == pytest.approx(paper[N], rel=0.035), N
+    for N in (0, 100, 500):
+        a, b, c = nu[129][N], nu[257][N], nu[513][N]
+        assert a < b < c < paper[N], N                       # monotone, from below
+        assert 1.4 < (b - a) / (c - b) < 2.6, N              # first-order refinement
+        assert 2 * c - b == pytest.approx(paper[N], rel=0.015), N
 
 
 def test_table4_extrapolation_walls_strong_opposing_buoyancy():
