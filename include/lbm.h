@@ -252,7 +252,8 @@ lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32
 /* Text of the last error on this context ("" if none); a static text for c == NULL. */
 const char *lbm_last_error(const struct lbm_ctx *c);
 
-/* Frees the context and its device memory.  NULL is a no-op. */
+/* Frees the context and its device memory.  NULL is a no-op.  A context still attached to a
+ * batch is detached first, once the work queued on the batch's stream has finished. */
 void lbm_destroy(struct lbm_ctx *c);
 
 /* ---- batched stepping of many independent cavities --------------------------------

@@ -103,7 +103,7 @@ struct lbm_ctx {
   bool ready = false;
   bool unstable = false;     // lbm_observables found a non-finite value: lbm_step refuses to go on
   double *scratch = nullptr; // device address of the fixed scratch on this context's device
-  bool in_batch = false;
+  lbm_batch *batch = nullptr;   // the batch this context is attached to, if any
   int cur = 0;               // buffer holding the post-collision state of the current level
   int d4cur = 0;             // field buffer (d4 or d4b) holding the fields of the current level
   int steps_per_launch = 0;  // 1, 2, or 0: chosen by the default rule
@@ -564,8 +564,19 @@ LBM_API lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   return LBM_OK;
 }
 
+static void batch_forget(lbm_batch *b, lbm_ctx *c);
+
 LBM_API void lbm_destroy(lbm_ctx *c) {
   if (!c) return;
+  if (c->batch) {
+    // still attached: the batch forgets it once the work queued on the batch stream is done,
+    // so no later replay reaches the memory freed here
+    lbm_batch *b = c->batch;
+    if (lbm_batch_detach(b, c) != LBM_OK) {
+      (void)hipStreamSynchronize(c->stream);
+      batch_forget(b, c);
+    }
+  }
   drop_graph(c);
   if (c->owned && c->base) (void)hipFree(c->base);
   delete c;
@@ -580,7 +591,7 @@ LBM_API lbm_status lbm_set_fields(lbm_ctx *c, const double *phi, const double *T
                                   const double *ux, const double *uy) {
   Range range_("lbm_set_fields");
   if (!c) return LBM_EINVAL;
-  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (c->batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   c->err.clear();
   const lbm_params *p = &c->p;
   const size_t n = (size_t)p->nx * p->ny;
@@ -796,7 +807,7 @@ LBM_API lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
   Range range_("lbm_step");
   if (!c || nsteps < 0) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_step before lbm_set_fields");
-  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (c->batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   if (c->unstable)
     return fail(c, LBM_ESTATE, "the fields hold a non-finite value (reported at step %lld); restart with "
                 "lbm_set_fields or restore a state with lbm_set_state", (long long)c->step);
@@ -958,7 +969,7 @@ LBM_API lbm_status lbm_get_state(lbm_ctx *c, void *host, uint64_t bytes) {
 LBM_API lbm_status lbm_set_state(lbm_ctx *c, const void *host, uint64_t bytes) {
   if (!c || !host) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_set_fields must run first (it fixes the porosity)");
-  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (c->batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   StateHeader h;
   std::memcpy(&h, host, sizeof h);
@@ -1037,7 +1048,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   Range range_("lbm_autotune");
   if (!c || steps < 2) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_set_fields");
-  if (c->in_batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
+  if (c->batch) return fail(c, LBM_ESTATE, "context is attached to a batch");
   // save the state on the device, try each shape, restore
   const size_t pop_bytes = (size_t)NPOP * c->lay.plane * store_size(c->prec);
   const size_t d4_bytes = (size_t)ND4 * c->lay.plane * real_size(c->prec);
@@ -1402,7 +1413,7 @@ LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *s
 LBM_API void lbm_batch_destroy(lbm_batch *b) {
   if (!b) return;
   for (lbm_ctx *c : b->ctx) {
-    c->in_batch = false;
+    c->batch = nullptr;
     c->stream = (hipStream_t)c->p.stream;
   }
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -1418,7 +1429,7 @@ LBM_API void lbm_batch_destroy(lbm_batch *b) {
 LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   if (!b || !c) return LBM_EINVAL;
   if (!c->ready) return fail(c, LBM_ESTATE, "attach before lbm_set_fields");
-  if (c->in_batch) return fail(c, LBM_ESTATE, "context already in a batch");
+  if (c->batch) return fail(c, LBM_ESTATE, "context already in a batch");
   if (c->unstable) return fail(c, LBM_ESTATE, "the fields hold a non-finite value");
   if ((int)b->ctx.size() >= b->cap) return fail(c, LBM_ENOMEM, "batch is full");
   if (node_walls(&c->p)) {
@@ -1438,7 +1449,7 @@ LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   }
   // make prior work of the context visible to the batch stream
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before attach");
-  c->in_batch = true;
+  c->batch = b;
   c->stream = b->stream;
   drop_graph(c);
   b->ctx.push_back(c);
@@ -1446,15 +1457,22 @@ LBM_API lbm_status lbm_batch_attach(lbm_batch *b, lbm_ctx *c) {
   return LBM_OK;
 }
 
+// drops `c` from the batch's list and gives it back its own stream (the caller has waited for
+// the batch's queued work)
+static void batch_forget(lbm_batch *b, lbm_ctx *c) {
+  auto it = std::find(b->ctx.begin(), b->ctx.end(), c);
+  if (it != b->ctx.end()) b->ctx.erase(it);
+  c->batch = nullptr;
+  c->stream = (hipStream_t)c->p.stream;
+  b->dirty = true;
+}
+
 LBM_API lbm_status lbm_batch_detach(lbm_batch *b, lbm_ctx *c) {
   if (!b || !c) return LBM_EINVAL;
   auto it = std::find(b->ctx.begin(), b->ctx.end(), c);
   if (it == b->ctx.end()) return fail(c, LBM_EINVAL, "context is not in this batch");
   if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(c, LBM_EDEVICE, "sync before detach");
-  b->ctx.erase(it);
-  c->in_batch = false;
-  c->stream = (hipStream_t)c->p.stream;
-  b->dirty = true;
+  batch_forget(b, c);
   return LBM_OK;
 }
 

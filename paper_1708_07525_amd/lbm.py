@@ -214,6 +214,7 @@ class Solver:
             raise RuntimeError("no GPU: the lattice Boltzmann library runs only on a gfx950 GPU")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.precision = precision
+        self._batch = None          # the Batch this solver is attached to
         self.p = dict(params)
         self.nx, self.ny = int(params.get("nx", 64)), int(params.get("ny", 64))
         self._s = make_params(params, precision)
@@ -315,6 +316,10 @@ class Solver:
 
     def close(self):
         if getattr(self, "_h", None):
+            b = getattr(self, "_batch", None)
+            if b is not None and self in b.members:
+                b.members.remove(self)     # lbm_destroy detaches it from the batch
+            self._batch = None
             lib().lbm_destroy(self._h)
             self._h = None
             self._arena = None
@@ -343,10 +348,12 @@ class Batch:
     def attach(self, s: Solver):
         _check(lib().lbm_batch_attach(self._h, s.handle), s.handle, "lbm_batch_attach")
         self.members.append(s)
+        s._batch = self
 
     def detach(self, s: Solver):
         _check(lib().lbm_batch_detach(self._h, s.handle), s.handle, "lbm_batch_detach")
         self.members.remove(s)
+        s._batch = None
 
     def step(self, n: int):
         _check(lib().lbm_batch_step(self._h, int(n)), None, "lbm_batch_step")
@@ -377,6 +384,8 @@ class Batch:
         if getattr(self, "_h", None):
             lib().lbm_batch_destroy(self._h)
             self._h = None
+            for s in self.members:
+                s._batch = None
             self.members = []
 
     def __del__(self):

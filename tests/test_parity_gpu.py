@@ -507,6 +507,32 @@ def test_batch_alone_vs_mix_bitwise():
     b.close()
 
 
+def test_batch_member_closed_while_attached():
+    """Destroying a context that is still attached detaches it first: the batch goes on with the
+    others, which reach the states they reach alone, bit for bit."""
+    from paper_1708_07525_amd import Batch
+    Solver = _solver()
+    specs = [workloads.cavity_params(nx=64, ny=48), workloads.cavity_params(nx=80, ny=80, Ra=1e5, phi=0.5)]
+    fields = [workloads.noise_fields(p["nx"], p["ny"], (11, i)) for i, p in enumerate(specs)]
+    alone = Solver(specs[1], T=fields[1][0], C=fields[1][1], precision="fp32")
+    alone.step(350)
+    ref = alone.get_state()
+    alone.close()
+    b = Batch(2, chunk=100)
+    mix = [Solver(p, T=T, C=C, precision="fp32") for p, (T, C) in zip(specs, fields)]
+    for s in mix:
+        b.attach(s)
+    b.step(250)
+    mix[0].close()                       # not detached first
+    assert len(b) == 1 and b.members == [mix[1]]
+    b.step(100)
+    d = _state_diff(mix[1].get_state(), ref)
+    assert d is None, d
+    b.close()
+    mix[1].step(10)                      # back on its own stream
+    mix[1].close()
+
+
 @pytest.mark.parametrize("shape,chunk", [(0, 100), (1, 100), (2, 100), (3, 120), ("auto", 100), ("auto", 120)])
 def test_batch_tile_shapes_change_nothing(shape, chunk):
     """Every tile shape of the batched two-step launch, three steps per launch (shape 3, FP32
