@@ -308,6 +308,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, i
  * range and for shape 3 with FP16 storage. */
 lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape, int32_t policy);
 int32_t lbm_batch_size(const lbm_batch *b);
+/* Frees the batch once the work queued on its stream has finished; the attached contexts are
+ * released to their own streams and stay valid.  NULL is a no-op. */
 void lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

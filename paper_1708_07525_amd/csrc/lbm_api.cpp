@@ -1276,16 +1276,26 @@ lbm_status batch_upload(lbm_batch *b) {
       // grow the item table; the graph references the old pointer, so drop it
       drop_batch_graph(b);
       if (b->items[prec]) (void)hipFree(b->items[prec]);
+      b->items[prec] = nullptr;
       int cap = std::max(n, 2 * b->item_cap[prec]);
-      if (hipMalloc((void **)&b->items[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
+      b->item_cap[prec] = 0;
+      if (hipMalloc((void **)&b->items[prec], (size_t)cap * sizeof(Item)) != hipSuccess) {
+        b->items[prec] = nullptr;
+        return LBM_ENOMEM;
+      }
       b->item_cap[prec] = cap;
     }
     const int n2 = (int)items2.size();
     if (n2 > b->item2_cap[prec]) {
       drop_batch_graph(b);
       if (b->items2[prec]) (void)hipFree(b->items2[prec]);
+      b->items2[prec] = nullptr;
       int cap = std::max(n2, 2 * b->item2_cap[prec]);
-      if (hipMalloc((void **)&b->items2[prec], (size_t)cap * sizeof(Item)) != hipSuccess) return LBM_ENOMEM;
+      b->item2_cap[prec] = 0;
+      if (hipMalloc((void **)&b->items2[prec], (size_t)cap * sizeof(Item)) != hipSuccess) {
+        b->items2[prec] = nullptr;
+        return LBM_ENOMEM;
+      }
       b->item2_cap[prec] = cap;
     }
     if (n2 && hipMemcpyAsync(b->items2[prec], items2.data(), n2 * sizeof(Item), hipMemcpyHostToDevice, b->stream) !=
@@ -1308,7 +1318,11 @@ lbm_status batch_upload(lbm_batch *b) {
     if (b->ranges) (void)hipFree(b->ranges);
     b->ranges = nullptr;
     const int cap = std::max(ng, 2 * b->range_cap);
-    if (hipMalloc((void **)&b->ranges, (size_t)cap * 4 * sizeof(int)) != hipSuccess) return LBM_ENOMEM;
+    b->range_cap = 0;
+    if (hipMalloc((void **)&b->ranges, (size_t)cap * 4 * sizeof(int)) != hipSuccess) {
+      b->ranges = nullptr;
+      return LBM_ENOMEM;
+    }
     b->range_cap = cap;
   }
   std::vector<int> r;
@@ -1412,6 +1426,8 @@ LBM_API lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *s
 
 LBM_API void lbm_batch_destroy(lbm_batch *b) {
   if (!b) return;
+  // the contexts go back to their own streams: let the work queued on the batch's finish first
+  (void)hipStreamSynchronize(b->stream);
   for (lbm_ctx *c : b->ctx) {
     c->batch = nullptr;
     c->stream = (hipStream_t)c->p.stream;
