@@ -66,3 +66,36 @@ def test_budget_limits_residency():
     results, _ = srv.run(reqs)
     srv.close()
     assert len(results) == len(reqs) and max(seen) <= budget
+
+
+def test_failed_request_is_evicted():
+    """A request whose fields turn non-finite (a NaN in its initial temperature: one FP16-storage
+    and one FP32 request) retires at its first check, unconverged and flagged; every other
+    request's result is bitwise that of the clean mix."""
+    from paper_1708_07525_amd.serving import Request, Server
+    reqs = _requests()
+    bad = {2, 3}
+    sick = []
+    for r in reqs:
+        T = r.T
+        if r.id in bad:
+            T = r.T.copy()
+            T[3, 4] = np.nan
+        sick.append(Request(r.id, r.arrival, r.params, r.precision, None, T, r.C))
+    runs = {}
+    for name, rq in (("clean", reqs), ("sick", sick)):
+        srv = Server(10 ** 10, max_slots=8, chunk=100, check_every=500, tol=1e-6, max_steps=3000, keep_fields=True)
+        res, summ = srv.run(rq)
+        srv.close()
+        assert summ["requests"] == len(rq)
+        runs[name] = {r.id: r for r in res}
+    for i in bad:
+        r = runs["sick"][i]
+        assert r.obs["nonfinite"] and not r.converged and r.steps == 500, i
+    for i, c in runs["clean"].items():
+        if i in bad:
+            continue
+        m = runs["sick"][i]
+        assert c.steps == m.steps and c.converged == m.converged, i
+        for k in ("ux", "uy", "T", "C", "rho"):
+            assert np.array_equal(c.fields[k], m.fields[k]), (i, k)
