@@ -289,8 +289,11 @@ lbm_status lbm_batch_create(int32_t max_cavities, int32_t chunk, void *stream, l
  * than one two-step tile (64 x 8, FP64 32 x 8), or when the batch's chunk is not a multiple
  * of 4; it then advances with lbm_step only. */
 lbm_status lbm_batch_attach(lbm_batch *b, struct lbm_ctx *c);
+/* Removes the context once the work queued on the batch's stream has finished; its work
+ * returns to its own stream and lbm_step applies again.  LBM_EINVAL if it is not in this batch. */
 lbm_status lbm_batch_detach(lbm_batch *b, struct lbm_ctx *c);
-/* Advances every attached context by nsteps (asynchronous). */
+/* Advances every attached context by nsteps (asynchronous, on the batch's stream).  LBM_EINVAL
+ * for nsteps < 0, LBM_ENOMEM when the work tables cannot grow, LBM_EDEVICE on a HIP error. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Autotuner of the batched launch: for every precision and size class present, times each
  * tile shape of the two-step launch (and three steps per launch, shape 3, where the chunk and
@@ -307,6 +310,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *shape_out, i
  * default rule.  Takes effect at the next lbm_batch_step.  LBM_EINVAL for an index out of
  * range and for shape 3 with FP16 storage. */
 lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t precision, int32_t size_class, int32_t shape, int32_t policy);
+/* Number of attached contexts (0 for NULL). */
 int32_t lbm_batch_size(const lbm_batch *b);
 /* Frees the batch once the work queued on its stream has finished; the attached contexts are
  * released to their own streams and stay valid.  NULL is a no-op. */
