@@ -56,6 +56,9 @@ def parse():
                          "policy and steps per launch on the workload before the timed region; default)")
     ap.add_argument("--policy", type=int, default=-1, help="cache policy 0/1/2 with an explicit --tile (-1: rule)")
     ap.add_argument("--spl", type=int, default=0, help="steps per launch 1/2/3 with an explicit --tile (0: rule)")
+    ap.add_argument("--strip", type=int, default=-1,
+                    help="tile order of the multi-step launches with an explicit --tile: 0 row by row, k strips "
+                         "of k tiles (-1: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
@@ -114,7 +117,8 @@ def profiled_traffic(prec, n, launch):
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when there is no
     summary for this workload, the kernel code has changed since the counters were taken, or
-    the launch shape and cache policy [tile_x, tile_y, policy] differ from the profiled ones."""
+    the launch [tile_x, tile_y, policy, steps per launch, strip width] differs from the profiled
+    one."""
     import re
     kernel = {2: "step2_kernel", 3: "step3_kernel"}.get(launch[3], "step_kernel")
     path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_cavity{n}.md")
@@ -139,18 +143,19 @@ def kernel_code_hash():
     return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
 
 
-def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0):
+def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0, strip=-1):
     import torch
     from paper_1708_07525_amd import Solver
 
     s = Solver(case["params"], phi=case["phi"], T=case["T"], C=case["C"], precision=prec,
                tile=None if tile in ("auto", "default") else tile)
     if tile == "auto":
-        s.autotune(20)                 # restores the state it started from
+        s.autotune(120)                # restores the state it started from
     else:
         if policy is not None:
             s.set_cache_policy(policy)
         s.set_steps_per_launch(spl)
+        s.set_strip_width(strip)
     stream = torch.cuda.current_stream()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -163,7 +168,7 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     ob = s.observables()
-    tile_used = list(s.get_tile()) + [s.get_cache_policy(), s.get_steps_per_launch()]
+    tile_used = list(s.get_tile()) + [s.get_cache_policy(), s.get_steps_per_launch(), s.get_strip_width()]
     s.close()
     return ms, wall, ob, tile_used
 
@@ -500,7 +505,7 @@ def main():
     nodes = a.n * a.n
     tile = a.tile if a.tile in ("auto", "default") else tuple(int(v) for v in a.tile.split(","))
     ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile,
-                                        a.policy if a.policy >= 0 else None, a.spl)
+                                        a.policy if a.policy >= 0 else None, a.spl, a.strip)
     mlups = nodes * a.steps / (ms * 1e-3) / 1e6
     spl = tile_used[3]
     rf = roofline_fields(a.precision, nodes, ms / a.steps, spl)
@@ -521,7 +526,7 @@ def main():
         "config": {"workload": f"porous cavity {a.n}x{a.n}, 8 porosity bands U[0.35,0.9] (seed 2), Ra=1e7, "
                                f"Da=1e-4, Pr=0.7, Le=10, N=2, D2Q9+2xD2Q5 MRT, {a.precision} population storage",
                    "nx": a.n, "ny": a.n, "precision": a.precision, "tile": tile_used[:2],
-                   "cache_policy": tile_used[2], "steps_per_launch": tile_used[3],
+                   "cache_policy": tile_used[2], "steps_per_launch": tile_used[3], "strip_width": tile_used[4],
                    "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
         "roofline": {"bound": "hbm", "achieved": rf["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": rf["frac"],
@@ -555,7 +560,7 @@ def main():
             vr = roofline_fields(prec, nodes, vms / a.variant_steps, vt[3])
             var[prec] = {"MLUPS": round(v, 1), "GB_s": vr["achieved"], "frac": vr["frac"],
                          "effective_per_step_frac": vr["effective_per_step_frac"], "steps": a.variant_steps,
-                         "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3]}
+                         "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "strip_width": vt[4]}
         out["precisions"] = var
         # the same cavity with the walls through the boundary nodes (Eqs. 33-37): the boundary
         # rule inside the tiles (two steps per launch) or perimeter work-groups (one step);
@@ -566,7 +571,7 @@ def main():
         vr = roofline_fields(a.precision, nodes, vms / a.variant_steps, vt[3])
         out["node_walls"] = {"MLUPS": round(v, 1), "GB_s": vr["achieved"], "frac": vr["frac"],
                              "effective_per_step_frac": vr["effective_per_step_frac"], "steps": a.variant_steps,
-                             "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3],
+                             "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "strip_width": vt[4],
                              "precision": a.precision, "Nu_hot": vob["Nu"][0]}
         # the 512^2 Gaussian-random-field cavity (FP32): its 53 MB stay in the 256 MB Infinity
         # Cache, so its bytes per second are not HBM bandwidth; the HBM roofline is quoted at

@@ -230,6 +230,16 @@ lbm_status lbm_set_graph_chunk(struct lbm_ctx *c, int32_t chunk);
 lbm_status lbm_set_cache_policy(struct lbm_ctx *c, int32_t policy);
 int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 
+/* Order in which the two- and three-step launches visit their tiles: 0 row by row of tiles,
+ * k >= 1 in vertical strips k tiles wide (the last one narrower), each walked row by row, so
+ * that the halo rows a tile reads were loaded shortly before by its neighbour in the strip and
+ * are still in the L2 of its XCD; -1 the default rule (row by row up to 8 tiles across; strips
+ * of 4 tiles up to 32 tiles across, row by row there for FP16 storage; strips of 8 tiles on
+ * wider lattices).  LBM_EINVAL outside -1..1024.  Results do not depend on it (bit for bit).
+ * lbm_get_strip_width returns the width in effect (-1 for a NULL context). */
+lbm_status lbm_set_strip_width(struct lbm_ctx *c, int32_t tiles);
+int32_t lbm_get_strip_width(const struct lbm_ctx *c);
+
 /* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 64 x 8 tiles, 32 x 8
  * for FP64, and a one-node halo staged in LDS, so the global loads of the second step are
  * saved), 3 (the three-step kernel: the same tiles with a two-node halo; FP32 and FP64 storage
@@ -243,9 +253,11 @@ lbm_status lbm_set_steps_per_launch(struct lbm_ctx *c, int32_t n);
 int32_t lbm_get_steps_per_launch(const struct lbm_ctx *c);
 
 /* Times every supported launch shape, cache policy and steps-per-launch count on this
- * context for `steps` steps each (HIP events), keeps the fastest (read the policy and the
- * count with lbm_get_cache_policy, lbm_get_steps_per_launch), restores the state it started
- * from, and reports the tile and its time per step.  Synchronises. */
+ * context for `steps` steps each (HIP events), the multi-step launches also with their tiles
+ * row by row and in strips of 4 and 8 tiles, keeps the fastest (read the policy, the count and
+ * the strip width with lbm_get_cache_policy, lbm_get_steps_per_launch, lbm_get_strip_width),
+ * restores the state it started from, and reports the tile and its time per step.
+ * Synchronises. */
 lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32_t *tile_y,
                         double *ms_per_step);
 

@@ -111,6 +111,7 @@ struct lbm_ctx {
   int64_t snap_step = 0;
   Tile tile{256, 1};
   int cache_policy = -1;     // CP_* or -1: chosen by the bytes a step touches
+  int strip = -1;            // tile order of the multi-step launches (strip width), -1: default_strip
   lbm_derived dv{};
   bool phi_field = false;
   Desc<double> d64{};
@@ -122,7 +123,7 @@ struct lbm_ctx {
   int graph_cur = -1;
   Tile graph_tile{0, 0};
   int graph_cp = -1;
-  int graph_d4 = -1, graph_spl = 0;
+  int graph_d4 = -1, graph_spl = 0, graph_sw = -1;
   int graph_chunk = kGraphChunk;   // 0: plain launches only
 
   void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
@@ -258,6 +259,23 @@ int default_spl(int prec, double nodes) {
 int default_policy(int prec, double nodes, int spl) {
   if (nodes * bytes_per_lu(prec) <= 400e6) return CP_RESIDENT;
   return (spl >= 2 || prec == PREC_FP32) ? CP_STREAM : CP_TUNED;
+}
+
+// Tile order of the multi-step launches when none is set (lbm_set_strip_width): vertical strips
+// of sw tiles.  Row by row, a tile's halo rows were loaded a whole row of tiles earlier and have
+// left the L2 on wide lattices; in strips they were loaded sw tiles earlier.  Measured, FP32
+// three steps per launch (64 x 8 tiles): 2048^2 62.1 GLUPS with strips of 4 tiles, 61.2 with 8,
+// 60.1 row by row; 4096^2 68.5 with 8, 64.0 with 4, 55.6 row by row; 8192 x 512 62.4 with 8
+// against 55.3.  FP16, two steps per launch: 4096^2 71.9 with 8 against 66.6 row by row, no gain
+// at 2048^2.  Up to 8 tiles across, both orders are the same.
+int default_strip(int prec, int nx, int spl) {
+  if (spl < 2) return 0;
+  int w = 0, h = 0;
+  two_step_tile_shape(prec, &w, &h);
+  const int ntx = (nx + w - 1) / w;
+  if (ntx <= 8) return 0;
+  if (ntx > 32) return 8;
+  return prec == PREC_FP16S ? 0 : 4;
 }
 
 void map_params(const lbm_params *p, lbm_derived &d) {
@@ -709,20 +727,25 @@ static int ctx_policy(const lbm_ctx *c) {
   return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny, ctx_spl(c));
 }
 
+static int ctx_strip(const lbm_ctx *c) {
+  return c->strip >= 0 ? c->strip : default_strip(c->prec, c->p.nx, ctx_spl(c));
+}
+
 // n steps with plain launches: three or two steps per launch as ctx_spl allows, the remainder
 // in shorter launches
 static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   const int cp = ctx_policy(c);
   const int spl = ctx_spl(c);
+  const int sw = ctx_strip(c);
   while (n > 0) {
     set_parity(c, c->cur);
     if (spl == 3 && n >= 3) {
-      int e = launch_step3(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, c->stream);
+      int e = launch_step3(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, sw, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "three-step kernel launch");
       c->d4cur ^= 1;
       n -= 3;
     } else if (spl >= 2 && n >= 2) {
-      int e = launch_step2(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, c->stream);
+      int e = launch_step2(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, sw, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "two-step kernel launch");
       c->d4cur ^= 1;
       n -= 2;
@@ -758,10 +781,11 @@ static void graph_plan(const lbm_ctx *c, int *spl, int *steps) {
 // Graph of one replay (graph_plan): its launches in a fixed order.
 static lbm_status ensure_graph(lbm_ctx *c) {
   const int cp = ctx_policy(c);
+  const int sw = ctx_strip(c);
   int spl = 1, gsteps = 0;
   graph_plan(c, &spl, &gsteps);
   if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty &&
-      c->graph_cp == cp && c->graph_d4 == c->d4cur && c->graph_spl == spl)
+      c->graph_cp == cp && c->graph_d4 == c->d4cur && c->graph_spl == spl && c->graph_sw == sw)
     return LBM_OK;
   drop_graph(c);
   hipStream_t cs;
@@ -774,10 +798,10 @@ static lbm_status ensure_graph(lbm_ctx *c) {
     for (int k = 0; k < gsteps / spl && e == hipSuccess; ++k) {
       set_parity(c, cur, d4);
       if (spl == 3) {
-        e = (hipError_t)launch_step3(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, cs);
+        e = (hipError_t)launch_step3(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, sw, cs);
         d4 ^= 1;
       } else if (spl == 2) {
-        e = (hipError_t)launch_step2(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, cs);
+        e = (hipError_t)launch_step2(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, sw, cs);
         d4 ^= 1;
       } else {
         e = (hipError_t)launch_step(c->prec, c->desc(), c->desc_dev(cur, d4), c->tile, cp, 0, cs);
@@ -800,6 +824,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   c->graph_cp = cp;
   c->graph_d4 = c->d4cur;
   c->graph_spl = spl;
+  c->graph_sw = sw;
   return LBM_OK;
 }
 
@@ -1035,6 +1060,15 @@ LBM_API lbm_status lbm_set_cache_policy(lbm_ctx *c, int32_t policy) {
 
 LBM_API int32_t lbm_get_cache_policy(const lbm_ctx *c) { return c ? ctx_policy(c) : -1; }
 
+LBM_API lbm_status lbm_set_strip_width(lbm_ctx *c, int32_t tiles) {
+  if (!c) return LBM_EINVAL;
+  if (tiles < -1 || tiles > 1024) return fail(c, LBM_EINVAL, "strip width must be -1 (default), 0 or 1..1024 tiles");
+  c->strip = tiles;
+  return LBM_OK;
+}
+
+LBM_API int32_t lbm_get_strip_width(const lbm_ctx *c) { return c ? ctx_strip(c) : -1; }
+
 LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
   if (!c) return LBM_EINVAL;
   if (n < 0 || n > 3) return fail(c, LBM_EINVAL, "steps per launch must be 0 (default), 1, 2 or 3");
@@ -1057,7 +1091,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   const int cur0 = c->cur;
   const int64_t step0 = c->step;
   const Tile tile0 = c->tile;
-  const int cp0 = c->cache_policy, spl0 = c->steps_per_launch, d4cur0 = c->d4cur;
+  const int cp0 = c->cache_policy, spl0 = c->steps_per_launch, d4cur0 = c->d4cur, sw0 = c->strip;
   hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -1067,26 +1101,36 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   if (e == hipSuccess) e = hipEventCreate(&t1);
   double best = 1e300;
   Tile best_tile = tile0;
-  int best_cp = ctx_policy(c), best_spl = ctx_spl(c);
+  int best_cp = ctx_policy(c), best_spl = ctx_spl(c), best_sw = c->strip;
   const int txs[] = {64, 128, 256};
   const int tys[] = {1, 2, 4, 8};
   struct Cand {
-    int spl, cp, tx, ty;
+    int spl, cp, tx, ty, sw;
   };
   std::vector<Cand> cands;
   for (int cp = 0; cp < CP_COUNT; ++cp)
     for (int tx : txs)
-      for (int ty : tys) cands.push_back(Cand{1, cp, tx, ty});
-  if (two_step_ok(c))   // the multi-step kernels have a fixed tile (64 x 8, FP64 32 x 8)
-    for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty});
-  if (three_step_ok(c))
-    for (int cp = 0; cp < CP_COUNT; ++cp) cands.push_back(Cand{3, cp, tile0.tx, tile0.ty});
+      for (int ty : tys) cands.push_back(Cand{1, cp, tx, ty, sw0});
+  // the multi-step kernels have a fixed tile (64 x 8, FP64 32 x 8); their tile order: row by row
+  // or strips of 4 or 8 tiles, where the lattice is wider than the strip
+  int w2 = 0, h2 = 0;
+  two_step_tile_shape(c->prec, &w2, &h2);
+  const int ntx2 = (c->p.nx + w2 - 1) / w2;
+  std::vector<int> sws{0};
+  for (int sw : {4, 8})
+    if (ntx2 > sw) sws.push_back(sw);
+  for (int spl = 2; spl <= 3; ++spl) {
+    if (spl == 2 ? !two_step_ok(c) : !three_step_ok(c)) continue;
+    for (int cp = 0; cp < CP_COUNT; ++cp)
+      for (int sw : sws) cands.push_back(Cand{spl, cp, tile0.tx, tile0.ty, sw});
+  }
   const int nsteps = (steps + 5) / 6 * 6;   // whole launches of two and of three steps
   for (const Cand &k : cands) {
     if (e != hipSuccess) break;
     c->tile = Tile{k.tx, k.ty};
     c->cache_policy = k.cp;
     c->steps_per_launch = k.spl;
+    c->strip = k.sw;
     if (step_plain(c, 6) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
     e = hipEventRecord(t0, c->stream);
     if (e == hipSuccess && step_plain(c, nsteps) != LBM_OK) e = hipErrorUnknown;
@@ -1099,6 +1143,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
       best_tile = c->tile;
       best_cp = k.cp;
       best_spl = k.spl;
+      best_sw = k.sw;
     }
   }
   // restore
@@ -1118,11 +1163,13 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
     c->tile = tile0;
     c->cache_policy = cp0;
     c->steps_per_launch = spl0;
+    c->strip = sw0;
     return hip_fail(c, e, "autotune");
   }
   c->tile = best_tile;
   c->cache_policy = best_cp;
   c->steps_per_launch = best_spl;
+  c->strip = best_sw;
   drop_graph(c);
   if (tx_out) *tx_out = best_tile.tx;
   if (ty_out) *ty_out = best_tile.ty;

@@ -84,12 +84,13 @@ int launch_init(int prec, const void *desc, const double *T, const double *C, co
 // memory, which the step kernels read.  cp: cache policy CP_*
 int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp, int parity, void *stream);
 // two time steps per launch (tiles with a one-node halo staged in LDS); fields read from d4,
-// written to d4b;
-// cavities without walls through the nodes only
-int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream);
+// written to d4b; walls through the nodes with FP32 and FP64 storage on lattices of at least
+// one tile (else hipErrorInvalidValue).  sw: tile order, row by row (0) or in vertical strips of
+// sw tiles
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream);
 // three time steps per launch (tiles with a two-node halo staged in LDS); FP32 and FP64
-// storage, walls half a spacing outside; fields read from d4, written to d4b
-int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream);
+// storage, walls half a spacing outside; fields read from d4, written to d4b; sw as above
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream);
 // range: device pointer to {first item, item count} of the group to step; parity bit 0
 // selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,

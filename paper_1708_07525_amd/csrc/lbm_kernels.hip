@@ -855,6 +855,24 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return k * per + (k < rem ? k : rem) + j;
 }
 
+// tile index -> tile coordinates (tx, ty) of an ntx x nty grid of tiles: row by row (sw = 0),
+// or in vertical strips of sw tiles (the last one narrower when sw does not divide ntx), each
+// strip walked row by row.  With the XCD bands above, the tiles an XCD runs in succession then
+// lie within a strip, so the halo rows a tile reads were loaded by a tile that ran only sw
+// tiles earlier and are still in that XCD's L2 (row by row, on a wide lattice they were loaded a
+// whole row of tiles earlier).  A bijection for every sw >= 0.
+__device__ __forceinline__ void tile_of(int b, int ntx, int nty, int sw, int &tx, int &ty) {
+  if (sw <= 0 || sw >= ntx) {
+    tx = b % ntx;
+    ty = b / ntx;
+    return;
+  }
+  const int st = sw * nty, s = b / st, rem = b - s * st;
+  const int ws = min(sw, ntx - s * sw);
+  tx = s * sw + rem % ws;
+  ty = rem / ws;
+}
+
 // one tile: tile_y rows of blockDim.x nodes starting at (x0, y0)
 // The tile at the origin also advances the step counter: it reads counter[cur] (the count
 // of the state being read) and writes counter[cur ^ 1] (the count of the state being
@@ -1159,11 +1177,13 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
 // ny >= H, checked by the launcher)
 template <typename S, int CP, bool NEE>
 __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
-                                                                    int ntx, int parity) {
+                                                                    int ntx, int parity, int sw) {
   const Desc<typename St<S>::R> &d = *dp;
   __shared__ S lpop[NPOP][TwoStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  int x0 = (b % ntx) * TwoStep<S>::W, y0 = (b / ntx) * TwoStep<S>::H;
+  int tx, ty;
+  tile_of(b, ntx, (int)gridDim.x / ntx, sw, tx, ty);
+  int x0 = tx * TwoStep<S>::W, y0 = ty * TwoStep<S>::H;
   if (NEE) {
     x0 = min(x0, d.nx - TwoStep<S>::W);
     y0 = min(y0, d.ny - TwoStep<S>::H);
@@ -1379,11 +1399,13 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
 
 template <typename S, int CP>
 __global__ void __launch_bounds__(ThreeStep<S>::THREADS, ThreeStep<S>::MIN_WAVES_PER_EU) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
-                                                                      int ntx, int parity) {
+                                                                      int ntx, int parity, int sw) {
   const Desc<typename St<S>::R> &d = *dp;
   __shared__ S lpop[NPOP - 3][ThreeStep<S>::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  three_step_tile<S, CP>(d, (b % ntx) * ThreeStep<S>::W, (b / ntx) * ThreeStep<S>::H, parity, lpop);
+  int tx, ty;
+  tile_of(b, ntx, (int)gridDim.x / ntx, sw, tx, ty);
+  three_step_tile<S, CP>(d, tx * ThreeStep<S>::W, ty * ThreeStep<S>::H, parity, lpop);
 }
 
 // Batched two steps over items of W x H tiles (item.tw = W, the group's shape SH): one item per
@@ -1764,7 +1786,7 @@ int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp,
 }
 
 template <typename S>
-static int step2_t(const void *desc, const void *ddev, int cp, int parity, void *stream) {
+static int step2_t(const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
@@ -1780,36 +1802,36 @@ static int step2_t(const void *desc, const void *ddev, int cp, int parity, void 
       if (d.nx < W || d.ny < H) return (int)hipErrorInvalidValue;
       switch (cp) {
         case CP_STREAM:
-          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, dp, ntx, parity);
+          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, dp, ntx, parity, sw);
           break;
         case CP_RESIDENT:
-          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, dp, ntx, parity);
+          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, dp, ntx, parity, sw);
           break;
-        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, dp, ntx, parity); break;
+        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, dp, ntx, parity, sw); break;
       }
       return (int)hipGetLastError();
     }
   }
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, dp, ntx, parity); break;
+    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, dp, ntx, parity, sw); break;
     case CP_RESIDENT:
-      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, dp, ntx, parity);
+      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, dp, ntx, parity, sw);
       break;
-    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, dp, ntx, parity); break;
+    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, dp, ntx, parity, sw); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream) {
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   switch (prec) {
-    case PREC_FP64: return step2_t<double>(desc, ddev, cp, parity, stream);
-    case PREC_FP32: return step2_t<float>(desc, ddev, cp, parity, stream);
-    default: return step2_t<_Float16>(desc, ddev, cp, parity, stream);
+    case PREC_FP64: return step2_t<double>(desc, ddev, cp, parity, sw, stream);
+    case PREC_FP32: return step2_t<float>(desc, ddev, cp, parity, sw, stream);
+    default: return step2_t<_Float16>(desc, ddev, cp, parity, sw, stream);
   }
 }
 
 template <typename S>
-static int step3_t(const void *desc, const void *ddev, int cp, int parity, void *stream) {
+static int step3_t(const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
@@ -1817,22 +1839,22 @@ static int step3_t(const void *desc, const void *ddev, int cp, int parity, void 
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
   const dim3 grid(ntx * nty), block(ThreeStep<S>::THREADS);
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, dp, ntx, parity); break;
-    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, dp, ntx, parity); break;
-    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, dp, ntx, parity); break;
+    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, dp, ntx, parity, sw); break;
+    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, dp, ntx, parity, sw); break;
+    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, dp, ntx, parity, sw); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, void *stream) {
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   const auto nee = [&](auto *dp) { return dp->nee != 0; };
   switch (prec) {
     case PREC_FP64:
       if (nee((const Desc<double> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<double>(desc, ddev, cp, parity, stream);
+      return step3_t<double>(desc, ddev, cp, parity, sw, stream);
     case PREC_FP32:
       if (nee((const Desc<float> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<float>(desc, ddev, cp, parity, stream);
+      return step3_t<float>(desc, ddev, cp, parity, sw, stream);
     default: return (int)hipErrorInvalidValue;   // FP16 storage: one or two steps per launch
   }
 }

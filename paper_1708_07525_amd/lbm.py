@@ -27,7 +27,8 @@ EXPORTS = (
     "lbm_observables", "lbm_observables_static", "lbm_get_fields", "lbm_get_derived", "lbm_derive",
     "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state",
-    "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_steps_per_launch",
+    "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_strip_width",
+    "lbm_get_strip_width", "lbm_set_steps_per_launch",
     "lbm_get_steps_per_launch", "lbm_set_graph_chunk",
     "lbm_autotune", "lbm_last_error", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_autotune",
@@ -112,6 +113,10 @@ def lib():
         L.lbm_set_cache_policy.restype = ctypes.c_int
         L.lbm_get_cache_policy.argtypes = [_VP]
         L.lbm_get_cache_policy.restype = ctypes.c_int32
+        L.lbm_set_strip_width.argtypes = [_VP, ctypes.c_int32]
+        L.lbm_set_strip_width.restype = ctypes.c_int
+        L.lbm_get_strip_width.argtypes = [_VP]
+        L.lbm_get_strip_width.restype = ctypes.c_int32
         L.lbm_set_steps_per_launch.argtypes = [_VP, ctypes.c_int32]
         L.lbm_set_steps_per_launch.restype = ctypes.c_int
         L.lbm_get_steps_per_launch.argtypes = [_VP]
@@ -294,6 +299,14 @@ class Solver:
 
     def get_cache_policy(self) -> int:
         return int(lib().lbm_get_cache_policy(self._h))
+
+    def set_strip_width(self, tiles: int):
+        """Tile order of the multi-step launches: 0 row by row, k >= 1 vertical strips of k
+        tiles, -1 the default rule (see include/lbm.h)."""
+        _check(lib().lbm_set_strip_width(self._h, int(tiles)), self._h, "lbm_set_strip_width")
+
+    def get_strip_width(self) -> int:
+        return int(lib().lbm_get_strip_width(self._h))
 
     def set_steps_per_launch(self, n: int):
         """1, 2 (two-step LDS kernel), 3 (three-step LDS kernel) or 0 for the default (see

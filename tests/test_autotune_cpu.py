@@ -30,6 +30,12 @@ class FakeSolver:
     def get_steps_per_launch(self):
         return getattr(self, "spl", 2)
 
+    def set_strip_width(self, n):
+        self.strip = n
+
+    def get_strip_width(self):
+        return getattr(self, "strip", 4)
+
 
 def test_size_class_and_key():
     assert [autotune.size_class(n) for n in (1, 3, 64, 65, 2048)] == [1, 4, 64, 128, 2048]
@@ -46,7 +52,7 @@ def test_tune_times_once_per_class(tmp_path):
     b = FakeSolver(120, 90)          # same class: 128x128, uniform, fp32
     b.tile = (64, 8)
     assert autotune.tune(b, "gpu", False, path=path) == ((128, 2), None)
-    assert b.timed == 0 and b.tile == (128, 2) and b.policy == 1
+    assert b.timed == 0 and b.tile == (128, 2) and b.policy == 1 and b.strip == 4
     c = FakeSolver(120, 90, "fp16s")  # other precision: timed again
     autotune.tune(c, "gpu", False, path=path)
     assert c.timed == 1

@@ -9,7 +9,8 @@ places the last tile of each row and column against the far wall, x0 = min(t W, 
 y0 = min(t H, ny - H).  The first tests check, for every tile of many lattice shapes, that every
 LDS read of that rule stays in the tile's region and lands on a node the first step computed,
 and that a tile the kernel treats as interior holds no boundary node in its region.  The last
-one checks the region bookkeeping of three steps per launch.
+ones check the region bookkeeping of three steps per launch and that the order in which a launch
+visits its tiles (row by row or in vertical strips) covers every tile once.
 """
 import pytest
 
@@ -174,3 +175,27 @@ def test_three_step_rings_cover_the_region_and_feed_every_stored_node(W, H):
         for ny in (3, 5, 9, 37):
             for perx, pery in ((False, False), (True, False), (False, True), (True, True)):
                 _check_three_step(W, H, nx, ny, perx, pery)
+
+
+def _tile_of(b, ntx, nty, sw):
+    """The kernels' tile order: row by row (sw = 0, or sw >= ntx), or vertical strips of sw
+    tiles, the last one narrower, each walked row by row."""
+    if sw <= 0 or sw >= ntx:
+        return b % ntx, b // ntx
+    st = sw * nty
+    s, rem = divmod(b, st)
+    ws = min(sw, ntx - s * sw)
+    return s * sw + rem % ws, rem // ws
+
+
+@pytest.mark.parametrize("sw", [0, 1, 2, 3, 4, 5, 8, 16, 64])
+def test_tile_order_is_a_permutation(sw):
+    """Every tile of the launch grid is visited once, for every strip width and grid shape."""
+    for ntx in list(range(1, 40)) + [64, 128, 234]:
+        for nty in (1, 2, 5, 8, 33, 256):
+            seen = {_tile_of(b, ntx, nty, sw) for b in range(ntx * nty)}
+            assert len(seen) == ntx * nty, (ntx, nty)
+            assert all(0 <= x < ntx and 0 <= y < nty for x, y in seen), (ntx, nty)
+    # within a full strip, consecutive tiles run along a row of the strip, then down
+    assert [_tile_of(b, 10, 3, 4) for b in range(6)] == [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1)]
+    assert _tile_of(24, 10, 3, 4) == (8, 0) and _tile_of(25, 10, 3, 4) == (9, 0) and _tile_of(26, 10, 3, 4) == (8, 1)
