@@ -59,9 +59,9 @@ def store(entries: dict, path: str | None = None) -> None:
 
 def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: str | None = None,
          force: bool = False, node_walls: bool = False):
-    """Apply the cached tile shape, cache policy, steps per launch and strip width for this solver's class
-    (walls through the boundary nodes are a class of their own), or time all of them and cache
-    the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
+    """Apply the cached tile shape, cache policy, steps per launch, strip width and three-step
+    rows for this solver's class (walls through the boundary nodes are a class of their own), or
+    time all of them and cache the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
     k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field, node_walls)
     entries = load(path)
     if not force and k in entries:
@@ -70,11 +70,13 @@ def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: 
         solver.set_cache_policy(int(entries[k].get("policy", -1)))
         solver.set_steps_per_launch(int(entries[k].get("steps_per_launch", 0)))
         solver.set_strip_width(int(entries[k].get("strip_width", -1)))
+        solver.set_three_step_rows(int(entries[k].get("three_step_rows", 0)))
         return (tx, ty), None
     (tx, ty), ms = solver.autotune(steps)
     entries = load(path)          # re-read: another process may have added entries
     entries[k] = {"tile": [tx, ty], "policy": solver.get_cache_policy(),
                   "steps_per_launch": solver.get_steps_per_launch(), "strip_width": solver.get_strip_width(),
+                  "three_step_rows": solver.get_three_step_rows(),
                   "ms_per_step": ms, "steps": steps}
     store(entries, path)
     return (tx, ty), ms

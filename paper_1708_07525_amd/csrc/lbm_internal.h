@@ -89,8 +89,9 @@ int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp,
 // sw tiles
 int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream);
 // three time steps per launch (tiles with a two-node halo staged in LDS); FP32 and FP64
-// storage, walls half a spacing outside; fields read from d4, written to d4b; sw as above
-int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream);
+// storage, walls half a spacing outside; fields read from d4, written to d4b; sw as above;
+// rows: tile rows, 8 (64 x 8, FP64 32 x 8) or, FP32 only, 12 (64 x 12); else hipErrorInvalidValue
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, int rows, void *stream);
 // range: device pointer to {first item, item count} of the group to step; parity bit 0
 // selects the population buffers, bit 1 the field buffer (d4b when set)
 int launch_step_batch(int prec, int cp, const void *descs, const Item *items, const int *range, int grid, int parity,

@@ -1204,29 +1204,41 @@ __global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(const Desc<t
 // of the outer ring (threads [N1, N1 + N2)).  The values kept in LDS are rounded to the
 // storage type as a store and a reload would round them, so the result is bitwise that of
 // three one-step launches.
-template <typename S>
-struct ThreeStep {
-  static constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
+template <int W_, int H_, int MINW>
+struct Shape3 {
+  static constexpr int W = W_, H = H_;
   static constexpr int RW = W + 4, RH = H + 4, RN = RW * RH, THREADS = W * H;
   static constexpr int N1 = 2 * (W + 2) + 2 * H;        // inner ring
   static constexpr int N2 = 2 * RW + 2 * (H + 2);       // outer ring
-  // FP32: 80 VGPRs and 51 KB of LDS let three work-groups (24 waves) share a CU
-  static constexpr int MIN_WAVES_PER_EU = sizeof(S) == 4 ? 6 : 1;
+  static constexpr int MIN_WAVES_PER_EU = MINW;
 };
+// Tiles of the batched three-step launch: those of batch tile shape 0 (FP32 64 x 8: 80 VGPRs and
+// 51 KB of LDS let three work-groups of 8 waves share a CU; FP64 32 x 8)
+template <typename S>
+using ThreeStep = Shape3<TwoStep<S>::W, TwoStep<S>::H, sizeof(S) == 4 ? 6 : 1>;
+// The taller FP32 tile of the single-lattice three-step launch, 64 x 12 (80 VGPRs, 68 KB of LDS:
+// two work-groups of 12 waves per CU, 8% fewer halo collisions per stored update than 64 x 8),
+// for lattices that stream from HBM.  Measured with the tiles in strips (banded cavity): 2048^2
+// 67.3 GLUPS against 62.9 for 64 x 8 and 53.5 for 64 x 16 (one work-group per CU), 4096^2 74.4
+// against 68.6; but 1024^2 61.1 against 65.0 and 512^2 43.5 against 48.8, where the lattice stays
+// in the Infinity Cache and the third work-group per CU matters more.  Row by row 64 x 12 loses
+// at 2048^2 too (58.2 against 60.2): its larger region pays once the halo rows come from the L2.
+// FP64 keeps 32 x 8 (32 x 12: 26.2 against 30.7 GLUPS).
+using TallThree = Shape3<64, 12, 6>;
 
 // LDS plane of moving population i (0-8 f, 9-13 g, 14-18 h) when the rest populations f0,
 // g0, h0 stay in registers: the 16 moving populations in order
 __host__ __device__ constexpr int lp(int i) { return i - 1 - (i > 9 ? 1 : 0) - (i > 14 ? 1 : 0); }
 
-template <typename S, int CP>
+template <typename S, int CP, typename TS>
 __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d, int x0, int y0, int parity,
-                                                S (*lpop)[ThreeStep<S>::RN]) {
+                                                S (*lpop)[TS::RN]) {
   static_assert(!kScaled<S>, "three steps per launch: FP32 and FP64 storage");
   using R = typename St<S>::R;
   using FIO = FieldIO<S, CP>;
-  constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H, RW = ThreeStep<S>::RW, RH = ThreeStep<S>::RH;
-  constexpr int N1 = ThreeStep<S>::N1, N2 = ThreeStep<S>::N2;
-  static_assert(N1 + N2 <= ThreeStep<S>::THREADS, "one ring node per thread at most");
+  constexpr int W = TS::W, H = TS::H, RW = TS::RW, RH = TS::RH;
+  constexpr int N1 = TS::N1, N2 = TS::N2;
+  static_assert(N1 + N2 <= TS::THREADS, "one ring node per thread at most");
   constexpr uint32_t RS = sizeof(R);
   const uint32_t PR = (uint32_t)d.plane * RS;
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -1397,15 +1409,15 @@ __device__ __forceinline__ void three_step_tile(const Desc<typename St<S>::R> &d
   }
 }
 
-template <typename S, int CP>
-__global__ void __launch_bounds__(ThreeStep<S>::THREADS, ThreeStep<S>::MIN_WAVES_PER_EU) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
+template <typename S, int CP, typename TS>
+__global__ void __launch_bounds__(TS::THREADS, TS::MIN_WAVES_PER_EU) step3_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
                                                                       int ntx, int parity, int sw) {
   const Desc<typename St<S>::R> &d = *dp;
-  __shared__ S lpop[NPOP - 3][ThreeStep<S>::RN];
+  __shared__ S lpop[NPOP - 3][TS::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int tx, ty;
   tile_of(b, ntx, (int)gridDim.x / ntx, sw, tx, ty);
-  three_step_tile<S, CP>(d, tx * ThreeStep<S>::W, ty * ThreeStep<S>::H, parity, lpop);
+  three_step_tile<S, CP, TS>(d, tx * TS::W, ty * TS::H, parity, lpop);
 }
 
 // Batched two steps over items of W x H tiles (item.tw = W, the group's shape SH): one item per
@@ -1449,7 +1461,7 @@ __global__ void __launch_bounds__(ThreeStep<S>::THREADS, ThreeStep<S>::MIN_WAVES
   if ((int)blockIdx.x >= n) return;
   const int it = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, n) : (int)blockIdx.x;
   const Item item = items[first + it];
-  three_step_tile<S, CP>(descs[item.cavity], item.x0, item.y0, parity, lpop);
+  three_step_tile<S, CP, ThreeStep<S>>(descs[item.cavity], item.x0, item.y0, parity, lpop);
 }
 
 // A 256-thread tile of tw x (256/tw) nodes (tw = 64, 128 or 256), so that narrow cavities
@@ -1830,31 +1842,35 @@ int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parit
   }
 }
 
-template <typename S>
+template <typename S, typename TS>
 static int step3_t(const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
-  constexpr int W = ThreeStep<S>::W, H = ThreeStep<S>::H;
+  constexpr int W = TS::W, H = TS::H;
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
-  const dim3 grid(ntx * nty), block(ThreeStep<S>::THREADS);
+  const dim3 grid(ntx * nty), block(TS::THREADS);
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM>), grid, block, 0, s, dp, ntx, parity, sw); break;
-    case CP_RESIDENT: hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT>), grid, block, 0, s, dp, ntx, parity, sw); break;
-    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED>), grid, block, 0, s, dp, ntx, parity, sw); break;
+    case CP_STREAM: hipLaunchKernelGGL((step3_kernel<S, CP_STREAM, TS>), grid, block, 0, s, dp, ntx, parity, sw); break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step3_kernel<S, CP_RESIDENT, TS>), grid, block, 0, s, dp, ntx, parity, sw);
+      break;
+    default: hipLaunchKernelGGL((step3_kernel<S, CP_TUNED, TS>), grid, block, 0, s, dp, ntx, parity, sw); break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
+int launch_step3(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, int rows, void *stream) {
   const auto nee = [&](auto *dp) { return dp->nee != 0; };
   switch (prec) {
     case PREC_FP64:
-      if (nee((const Desc<double> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<double>(desc, ddev, cp, parity, sw, stream);
+      if (nee((const Desc<double> *)desc) || rows != ThreeStep<double>::H) return (int)hipErrorInvalidValue;
+      return step3_t<double, ThreeStep<double>>(desc, ddev, cp, parity, sw, stream);
     case PREC_FP32:
       if (nee((const Desc<float> *)desc)) return (int)hipErrorInvalidValue;
-      return step3_t<float>(desc, ddev, cp, parity, sw, stream);
+      if (rows == TallThree::H) return step3_t<float, TallThree>(desc, ddev, cp, parity, sw, stream);
+      if (rows != ThreeStep<float>::H) return (int)hipErrorInvalidValue;
+      return step3_t<float, ThreeStep<float>>(desc, ddev, cp, parity, sw, stream);
     default: return (int)hipErrorInvalidValue;   // FP16 storage: one or two steps per launch
   }
 }

@@ -198,8 +198,9 @@ def test_minimum_lattice():
 def test_degenerate_calls_and_smallest_lattices():
     """Zero steps change nothing; a negative count is refused; an empty batch steps as a no-op;
     the 3x3 lattice, with walls and periodic in one or both directions, gives the same state
-    bit for bit with one, two and three steps per launch (tiles far wider than the lattice,
-    halo nodes wrapped more than once across a periodic side)."""
+    bit for bit with one, two and three steps per launch (three on FP32's 64 x 8 and 64 x 12
+    tiles; tiles far wider than the lattice, halo nodes wrapped more than once across a periodic
+    side)."""
     from paper_1708_07525_amd import Batch
     from paper_1708_07525_amd.lbm import LbmError
     Solver = _solver()
@@ -225,9 +226,12 @@ def test_degenerate_calls_and_smallest_lattices():
             pp = workloads.cavity_params(nx=3, ny=3, sides=sides, g_ext=g_ext)
             T, C = workloads.noise_fields(3, 3, 9)
             states = []
-            for spl in (1, 2, 3):
+            for spl, rows in ((1, 0), (2, 0), (3, 8), (3, 12)):
+                if rows == 12 and prec != "fp32":
+                    continue
                 sv = Solver(pp, T=T, C=C, precision=prec)
                 sv.set_steps_per_launch(spl)
+                sv.set_three_step_rows(rows)
                 sv.step(61)
                 states.append(sv.get_state())
                 sv.close()
@@ -399,34 +403,40 @@ def test_two_step_kernel_matches_one_step(prec, case):
 @pytest.mark.parametrize("walls", ["half_way", "nee", "periodic"])
 def test_tile_order_changes_nothing(prec, walls):
     """The multi-step launches visit their tiles row by row or in vertical strips of k tiles
-    (the last strip narrower): the state is the same bit for bit, on a wide ragged lattice
+    (the last strip narrower), and FP32's three-step launch runs on 64 x 8 or 64 x 12 tiles:
+    the state is the same bit for bit, on a wide ragged lattice
     (600 x 41: 10 tiles of 64 nodes across, 19 of 32 for FP64, a part-filled last row of
     tiles) with a porosity field, with half-way walls, walls through the nodes and periodic
-    sides, with graph replays and plain launches."""
+    sides under a moving lid, with graph replays and plain launches."""
     Solver = _solver()
     nx, ny = 600, 41
     sides = {"half_way": ("hot", "cold", "adiabatic", "adiabatic"),
              "nee": ("nee_hot", "nee_cold", "nee_adiabatic", "nee_robin"),
              "periodic": ("periodic", "periodic", "cold", "hot")}[walls]
-    p = workloads.cavity_params(nx=nx, ny=ny, sides=sides, Ra=5e4, Bi_T=2.0, Bi_C=0.5)
+    lid = (0.0, 0.0, 0.0, 0.05 if walls == "periodic" else 0.0)       # a moving top wall
+    p = workloads.cavity_params(nx=nx, ny=ny, sides=sides, Ra=5e4, Bi_T=2.0, Bi_C=0.5, wall_u=lid)
     phi = workloads.grf_porosity(nx, ny, 9, ell=8.0, lo=0.4, hi=0.9)
     T, C = workloads.noise_fields(nx, ny, 9)
     w = 32 if prec == "fp64" else 64
     ntx = (nx + w - 1) // w
     states = {}
+    rows = (8, 12) if prec == "fp32" else (8,)
     for sw in (-1, 0, 1, 3, 4, 8, 64):
         for chunk in (0, 64):
-            s = Solver(p, phi=phi, T=T, C=C, precision=prec)
-            s.set_graph_chunk(chunk)
-            s.set_strip_width(sw)
-            if sw == -1:      # the default rule: strips of 4 up to 32 tiles across (FP16: row by row)
-                assert s.get_strip_width() == (0 if prec == "fp16s" or ntx <= 8 else 4)
-            else:
-                assert s.get_strip_width() == sw
-            s.step(131)
-            states[(sw, chunk)] = s.get_state()
-            s.close()
-    ref = states[(0, 0)]
+            for r in rows:
+                s = Solver(p, phi=phi, T=T, C=C, precision=prec)
+                s.set_graph_chunk(chunk)
+                s.set_strip_width(sw)
+                s.set_three_step_rows(r)
+                assert s.get_three_step_rows() == r
+                if sw == -1:      # the default rule: strips of 4 up to 32 tiles across (FP16: row by row)
+                    assert s.get_strip_width() == (0 if prec == "fp16s" or ntx <= 8 else 4)
+                else:
+                    assert s.get_strip_width() == sw
+                s.step(131)
+                states[(sw, chunk, r)] = s.get_state()
+                s.close()
+    ref = states[(0, 0, 8)]
     for k, st in states.items():
         d = _state_diff(st, ref)
         assert d is None, (k, d)

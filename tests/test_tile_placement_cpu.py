@@ -169,7 +169,7 @@ def _check_three_step(W, H, nx, ny, perx, pery):
                             assert r_ in step1 and valid(r_), (p, q, r_)
 
 
-@pytest.mark.parametrize("W,H", TILES)
+@pytest.mark.parametrize("W,H", TILES + [(64, 12)])
 def test_three_step_rings_cover_the_region_and_feed_every_stored_node(W, H):
     for nx in (3, 5, 65, 70, 129):
         for ny in (3, 5, 9, 37):
