@@ -267,16 +267,17 @@ int default_policy(int prec, double nodes, int spl) {
 // left the L2 on wide lattices; in strips they were loaded sw tiles earlier.  Measured, FP32
 // three steps per launch (64 x 8 tiles): 2048^2 62.1 GLUPS with strips of 4 tiles, 61.2 with 8,
 // 60.1 row by row; 4096^2 68.5 with 8, 64.0 with 4, 55.6 row by row; 8192 x 512 62.4 with 8
-// against 55.3.  FP16, two steps per launch: 4096^2 71.9 with 8 against 66.6 row by row, no gain
-// at 2048^2.  Up to 8 tiles across, both orders are the same.
+// against 55.3.  Two steps per launch gain only on wider lattices: FP16 4096^2 71.9 with 8
+// against 66.6 row by row, FP32 with walls through the nodes 52.2 against 47.6; at 2048^2 they
+// lose (walls through the nodes 48.7 row by row, 43.3 with strips of 4, 46.6 with 8).  Up to 8
+// tiles across, both orders are the same.
 int default_strip(int prec, int nx, int spl) {
   if (spl < 2) return 0;
   int w = 0, h = 0;
   two_step_tile_shape(prec, &w, &h);
   const int ntx = (nx + w - 1) / w;
-  if (ntx <= 8) return 0;
   if (ntx > 32) return 8;
-  return prec == PREC_FP16S ? 0 : 4;
+  return (spl == 3 && ntx > 8) ? 4 : 0;
 }
 
 // Rows of the three-step tile when none is set (lbm_set_three_step_rows): FP32 takes the 64 x 12

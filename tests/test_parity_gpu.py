@@ -429,8 +429,10 @@ def test_tile_order_changes_nothing(prec, walls):
                 s.set_strip_width(sw)
                 s.set_three_step_rows(r)
                 assert s.get_three_step_rows() == r
-                if sw == -1:      # the default rule: strips of 4 up to 32 tiles across (FP16: row by row)
-                    assert s.get_strip_width() == (0 if prec == "fp16s" or ntx <= 8 else 4)
+                if sw == -1:      # the default rule: three-step launches strips of 4 from 9 up to
+                    # 32 tiles across, two-step launches (FP16, walls through the nodes) row by row
+                    three = prec != "fp16s" and walls != "nee"
+                    assert s.get_strip_width() == (4 if three and ntx > 8 else 0)
                 else:
                     assert s.get_strip_width() == sw
                 s.step(131)
