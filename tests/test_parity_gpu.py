@@ -444,6 +444,27 @@ def test_tile_order_changes_nothing(prec, walls):
         assert d is None, (k, d)
 
 
+def test_launch_defaults_follow_the_lattice():
+    """The default launch choices: FP32 three-step tiles of 12 rows where a step touches more
+    than 400 MB (the lattice streams from HBM), 8 rows below and for FP64; strips of 4 tiles for
+    three-step launches from 9 up to 32 tiles across, 8 beyond; invalid settings refused."""
+    from paper_1708_07525_amd.lbm import LbmError
+    Solver = _solver()
+    for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 4), (1456, 1460, "fp32"): (8, 4),
+                                       (2100, 400, "fp32"): (8, 8), (500, 400, "fp32"): (8, 0),
+                                       (1460, 1460, "fp64"): (8, 8), (1460, 1460, "fp16s"): (8, 0)}.items():
+        s = Solver(workloads.cavity_params(nx=nx, ny=ny), T=0.5, C=0.5, precision=prec)
+        assert (s.get_three_step_rows(), s.get_strip_width()) == (rows, sw), (nx, ny, prec)
+        with pytest.raises(LbmError):
+            s.set_three_step_rows(10)
+        if prec != "fp32":
+            with pytest.raises(LbmError):
+                s.set_three_step_rows(12)
+        with pytest.raises(LbmError):
+            s.set_strip_width(-2)
+        s.close()
+
+
 def test_graph_replays_match_plain_launches():
     """lbm_step uses a captured graph for chunks of 64 steps; replays interleaved with other
     work must give the same state as one launch per step."""
