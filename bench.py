@@ -59,8 +59,9 @@ def parse():
     ap.add_argument("--strip", type=int, default=-1,
                     help="tile order of the multi-step launches with an explicit --tile: 0 row by row, k strips "
                          "of k tiles (-1: rule)")
-    ap.add_argument("--rows3", type=int, default=0,
-                    help="rows of the three-step tile with an explicit --tile: 8 or 12 (FP32) (0: rule)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="rows of the FP32 three-step / FP16 two-step tile with an explicit --tile: 8 or 12 "
+                         "(0: rule)")
     ap.add_argument("--workload", default="cavity", choices=("cavity", "sweep", "serve", "precision"),
                     help="cavity: the 2048^2 throughput line (default); sweep: 256 independent cavities, "
                          "batched launch vs one by one; serve: continuous-batching request stream; "
@@ -119,8 +120,8 @@ def profiled_traffic(prec, n, launch):
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when there is no
     summary for this workload, the kernel code has changed since the counters were taken, or
-    the launch [tile_x, tile_y, policy, steps per launch, strip width, three-step rows] differs
-    from the profiled one."""
+    the launch [tile_x, tile_y, policy, steps per launch, strip width, tile rows] differs from
+    the profiled one."""
     import re
     kernel = {2: "step2_kernel", 3: "step3_kernel"}.get(launch[3], "step_kernel")
     path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_cavity{n}.md")
@@ -145,7 +146,7 @@ def kernel_code_hash():
     return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
 
 
-def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0, strip=-1, rows3=0):
+def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0, strip=-1, rows=0):
     import torch
     from paper_1708_07525_amd import Solver
 
@@ -158,7 +159,7 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0, strip=
             s.set_cache_policy(policy)
         s.set_steps_per_launch(spl)
         s.set_strip_width(strip)
-        s.set_three_step_rows(rows3 if prec == "fp32" else 0)   # the taller tile is FP32's
+        s.set_tile_rows(rows if prec != "fp64" else 0)   # FP64 has 8-row tiles only
     stream = torch.cuda.current_stream()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -172,7 +173,7 @@ def timed_run(case, prec, steps, warmup, tile="auto", policy=None, spl=0, strip=
     ms = e0.elapsed_time(e1)
     ob = s.observables()
     tile_used = list(s.get_tile()) + [s.get_cache_policy(), s.get_steps_per_launch(), s.get_strip_width(),
-                                      s.get_three_step_rows()]
+                                      s.get_tile_rows()]
     s.close()
     return ms, wall, ob, tile_used
 
@@ -509,7 +510,7 @@ def main():
     nodes = a.n * a.n
     tile = a.tile if a.tile in ("auto", "default") else tuple(int(v) for v in a.tile.split(","))
     ms, wall, ob, tile_used = timed_run(case, a.precision, a.steps, a.warmup, tile,
-                                        a.policy if a.policy >= 0 else None, a.spl, a.strip, a.rows3)
+                                        a.policy if a.policy >= 0 else None, a.spl, a.strip, a.rows)
     mlups = nodes * a.steps / (ms * 1e-3) / 1e6
     spl = tile_used[3]
     rf = roofline_fields(a.precision, nodes, ms / a.steps, spl)
@@ -531,7 +532,7 @@ def main():
                                f"Da=1e-4, Pr=0.7, Le=10, N=2, D2Q9+2xD2Q5 MRT, {a.precision} population storage",
                    "nx": a.n, "ny": a.n, "precision": a.precision, "tile": tile_used[:2],
                    "cache_policy": tile_used[2], "steps_per_launch": tile_used[3], "strip_width": tile_used[4],
-                   "three_step_rows": tile_used[5],
+                   "tile_rows": tile_used[5],
                    "launch_shape": "autotuned" if tile == "auto" else str(a.tile)},
         "roofline": {"bound": "hbm", "achieved": rf["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": rf["frac"],
@@ -566,7 +567,7 @@ def main():
             var[prec] = {"MLUPS": round(v, 1), "GB_s": vr["achieved"], "frac": vr["frac"],
                          "effective_per_step_frac": vr["effective_per_step_frac"], "steps": a.variant_steps,
                          "tile": vt[:2], "cache_policy": vt[2], "steps_per_launch": vt[3], "strip_width": vt[4],
-                         "three_step_rows": vt[5]}
+                         "tile_rows": vt[5]}
         out["precisions"] = var
         # the same cavity with the walls through the boundary nodes (Eqs. 33-37): the boundary
         # rule inside the tiles (two steps per launch) or perimeter work-groups (one step);

@@ -241,19 +241,20 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 lbm_status lbm_set_strip_width(struct lbm_ctx *c, int32_t tiles);
 int32_t lbm_get_strip_width(const struct lbm_ctx *c);
 
-/* Rows of the three-step tile: 8 (64 x 8 nodes, FP64 32 x 8) or, with FP32 storage, 12 (64 x 12:
- * fewer halo collisions per update, two work-groups per CU instead of three), or 0 for the
- * default rule (FP32: 12 where a step touches more than 400 MB, i.e. the lattice streams from
- * HBM, else 8).  LBM_EINVAL for other values.  Results do not depend on it (bit for bit).
- * lbm_get_three_step_rows returns the rows in effect (0 for a NULL context). */
-lbm_status lbm_set_three_step_rows(struct lbm_ctx *c, int32_t rows);
-int32_t lbm_get_three_step_rows(const struct lbm_ctx *c);
+/* Rows of the multi-step tile of the FP32 three-step and the FP16 two-step launch: 8 (64 x 8 nodes)
+ * or 12 (64 x 12: fewer halo collisions per update, two work-groups per CU instead of three), or
+ * 0 for the default rule (12 where a step touches more than 400 MB, i.e. the lattice streams from
+ * HBM, else 8).  FP64 (32 x 8) and the node-wall launches have 8-row tiles only.  LBM_EINVAL for
+ * other values (12 with FP64 storage).  Results do not depend on it (bit for bit).
+ * lbm_get_tile_rows returns the rows in effect (0 for a NULL context). */
+lbm_status lbm_set_tile_rows(struct lbm_ctx *c, int32_t rows);
+int32_t lbm_get_tile_rows(const struct lbm_ctx *c);
 
 /* Time steps per kernel launch: 1 (step_kernel), 2 (the two-step kernel: 64 x 8 tiles, 32 x 8
- * for FP64, and a one-node halo staged in LDS, so the global loads of the second step are
- * saved), 3 (the three-step kernel: tiles of lbm_set_three_step_rows rows with a two-node halo;
- * FP32 and FP64 storage with walls half a spacing outside, else 2), or 0 for the default (2 for FP16 storage, else
- * 3).  Walls through the nodes take 1 with FP16 storage, or when the lattice is smaller than one
+ * for FP64, FP16 tiles of lbm_set_tile_rows rows, and a one-node halo staged in LDS, so the
+ * global loads of the second step are saved), 3 (the three-step kernel: a two-node halo, FP32
+ * tiles of lbm_set_tile_rows rows; FP32 and FP64 storage with walls half a spacing outside,
+ * else 2), or 0 for the default (2 for FP16 storage, else 3).  Walls through the nodes take 1 with FP16 storage, or when the lattice is smaller than one
  * two-step tile; otherwise the two-step kernel applies the boundary rule in both steps (its last
  * tiles sit against the far walls).  Remaining steps run in shorter launches.  Results do not
  * depend on it (bit for bit).  With 3, a graph replay covers the largest multiple of 6 steps in the
@@ -263,9 +264,10 @@ int32_t lbm_get_steps_per_launch(const struct lbm_ctx *c);
 
 /* Times every supported launch shape, cache policy and steps-per-launch count on this
  * context for `steps` steps each (HIP events), the multi-step launches also with their tiles
- * row by row and in strips of 4 and 8 tiles, and the FP32 three-step launch on both its tiles,
+ * row by row and in strips of 4 and 8 tiles, and the FP32 three-step and FP16 two-step launches on
+ * both their tiles,
  * keeps the fastest (read the choices with lbm_get_cache_policy, lbm_get_steps_per_launch,
- * lbm_get_strip_width, lbm_get_three_step_rows),
+ * lbm_get_strip_width, lbm_get_tile_rows),
  * restores the state it started from, and reports the tile and its time per step.
  * Synchronises. */
 lbm_status lbm_autotune(struct lbm_ctx *c, int32_t steps, int32_t *tile_x, int32_t *tile_y,

@@ -16,8 +16,9 @@ import os
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_dd", "autotune.json")
 # part of every key: raised when the kernels' launch choices change (three steps per launch for
 # FP32, a three-step tile with its rest populations in registers, the tile order of the
-# multi-step launches), so that choices timed with older kernels are not applied to newer ones
-KERNEL_GENERATION = 3
+# multi-step launches, their taller tiles), so that choices timed with older kernels are not
+# applied to newer ones
+KERNEL_GENERATION = 4
 
 
 def cache_path() -> str:
@@ -59,8 +60,8 @@ def store(entries: dict, path: str | None = None) -> None:
 
 def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: str | None = None,
          force: bool = False, node_walls: bool = False):
-    """Apply the cached tile shape, cache policy, steps per launch, strip width and three-step
-    rows for this solver's class (walls through the boundary nodes are a class of their own), or
+    """Apply the cached tile shape, cache policy, steps per launch, strip width and multi-step
+    tile rows for this solver's class (walls through the boundary nodes are a class of their own), or
     time all of them and cache the fastest.  Returns (tile_x, tile_y), ms_per_step (None when taken from the cache)."""
     k = key(device_name, solver.precision, solver.nx, solver.ny, porosity_field, node_walls)
     entries = load(path)
@@ -70,13 +71,13 @@ def tune(solver, device_name: str, porosity_field: bool, steps: int = 20, path: 
         solver.set_cache_policy(int(entries[k].get("policy", -1)))
         solver.set_steps_per_launch(int(entries[k].get("steps_per_launch", 0)))
         solver.set_strip_width(int(entries[k].get("strip_width", -1)))
-        solver.set_three_step_rows(int(entries[k].get("three_step_rows", 0)))
+        solver.set_tile_rows(int(entries[k].get("tile_rows", 0)))
         return (tx, ty), None
     (tx, ty), ms = solver.autotune(steps)
     entries = load(path)          # re-read: another process may have added entries
     entries[k] = {"tile": [tx, ty], "policy": solver.get_cache_policy(),
                   "steps_per_launch": solver.get_steps_per_launch(), "strip_width": solver.get_strip_width(),
-                  "three_step_rows": solver.get_three_step_rows(),
+                  "tile_rows": solver.get_tile_rows(),
                   "ms_per_step": ms, "steps": steps}
     store(entries, path)
     return (tx, ty), ms

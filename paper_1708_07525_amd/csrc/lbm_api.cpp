@@ -112,7 +112,7 @@ struct lbm_ctx {
   Tile tile{256, 1};
   int cache_policy = -1;     // CP_* or -1: chosen by the bytes a step touches
   int strip = -1;            // tile order of the multi-step launches (strip width), -1: default_strip
-  int rows3 = 0;             // rows of the three-step tile, 0: default_rows3
+  int tile_rows = 0;         // rows of the FP32 three-step / FP16 two-step tile, 0: default_rows
   lbm_derived dv{};
   bool phi_field = false;
   Desc<double> d64{};
@@ -124,7 +124,7 @@ struct lbm_ctx {
   int graph_cur = -1;
   Tile graph_tile{0, 0};
   int graph_cp = -1;
-  int graph_d4 = -1, graph_spl = 0, graph_sw = -1, graph_rows3 = 0;
+  int graph_d4 = -1, graph_spl = 0, graph_sw = -1, graph_rows = 0;
   int graph_chunk = kGraphChunk;   // 0: plain launches only
 
   void *pop(int i) const { return base + (i ? lay.off_pop1 : lay.off_pop0); }
@@ -280,13 +280,14 @@ int default_strip(int prec, int nx, int spl) {
   return (spl == 3 && ntx > 8) ? 4 : 0;
 }
 
-// Rows of the three-step tile when none is set (lbm_set_three_step_rows): FP32 takes the 64 x 12
-// tile where a step touches more than 400 MB (the lattice streams from HBM: 2048^2 67.3 against
-// 62.9 GLUPS for 64 x 8, 4096^2 74.4 against 68.6) and 64 x 8 below (the lattice stays in the
-// Infinity Cache, where the third work-group per CU of the smaller tile wins: 1024^2 65.0 against
-// 61.1); FP64 has the 32 x 8 tile only.
-int default_rows3(int prec, double nodes) {
-  return (prec == PREC_FP32 && nodes * bytes_per_lu(prec) > 400e6) ? 12 : 8;
+// Rows of the multi-step tile when none is set (lbm_set_tile_rows): the FP32 three-step and the
+// FP16 two-step launch take the 64 x 12 tile where a step touches more than 400 MB (the lattice
+// streams from HBM: FP32 2048^2 67.3 against 62.9 GLUPS for 64 x 8, 4096^2 74.4 against 68.6;
+// FP16 2048^2 69.5 against 67.3, 4096^2 76.2 against 71.9) and 64 x 8 below (the lattice stays in
+// the Infinity Cache, where the third work-group per CU of the smaller tile wins: FP32 1024^2 65.0
+// against 61.1); FP64 and the node-wall launches have the 8-row tile only.
+int default_rows(int prec, double nodes) {
+  return (prec != PREC_FP64 && nodes * bytes_per_lu(prec) > 400e6) ? 12 : 8;
 }
 
 void map_params(const lbm_params *p, lbm_derived &d) {
@@ -742,16 +743,22 @@ static int ctx_strip(const lbm_ctx *c) {
   return c->strip >= 0 ? c->strip : default_strip(c->prec, c->p.nx, ctx_spl(c));
 }
 
-static int ctx_rows3(const lbm_ctx *c) {
-  return c->rows3 > 0 ? c->rows3 : default_rows3(c->prec, (double)c->p.nx * c->p.ny);
+static int ctx_rows(const lbm_ctx *c) {
+  if (node_walls(&c->p)) return 8;
+  return c->tile_rows > 0 ? c->tile_rows : default_rows(c->prec, (double)c->p.nx * c->p.ny);
 }
+
+// the rows each multi-step launch takes: the tile rows apply to FP32's three-step and FP16's
+// two-step launch, the others have 8-row tiles
+static int rows2_of(const lbm_ctx *c) { return c->prec == PREC_FP16S ? ctx_rows(c) : 8; }
+static int rows3_of(const lbm_ctx *c) { return c->prec == PREC_FP32 ? ctx_rows(c) : 8; }
 
 // n steps with plain launches: three or two steps per launch as ctx_spl allows, the remainder
 // in shorter launches
 static lbm_status step_plain(lbm_ctx *c, int64_t n) {
   const int cp = ctx_policy(c);
   const int spl = ctx_spl(c);
-  const int sw = ctx_strip(c), rows3 = ctx_rows3(c);
+  const int sw = ctx_strip(c), rows2 = rows2_of(c), rows3 = rows3_of(c);
   while (n > 0) {
     set_parity(c, c->cur);
     if (spl == 3 && n >= 3) {
@@ -760,7 +767,7 @@ static lbm_status step_plain(lbm_ctx *c, int64_t n) {
       c->d4cur ^= 1;
       n -= 3;
     } else if (spl >= 2 && n >= 2) {
-      int e = launch_step2(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, sw, c->stream);
+      int e = launch_step2(c->prec, c->desc(), c->desc_dev(c->cur, c->d4cur), cp, 0, sw, rows2, c->stream);
       if (e) return hip_fail(c, (hipError_t)e, "two-step kernel launch");
       c->d4cur ^= 1;
       n -= 2;
@@ -796,12 +803,12 @@ static void graph_plan(const lbm_ctx *c, int *spl, int *steps) {
 // Graph of one replay (graph_plan): its launches in a fixed order.
 static lbm_status ensure_graph(lbm_ctx *c) {
   const int cp = ctx_policy(c);
-  const int sw = ctx_strip(c), rows3 = ctx_rows3(c);
+  const int sw = ctx_strip(c), rows = ctx_rows(c), rows2 = rows2_of(c), rows3 = rows3_of(c);
   int spl = 1, gsteps = 0;
   graph_plan(c, &spl, &gsteps);
   if (c->graph && c->graph_cur == c->cur && c->graph_tile.tx == c->tile.tx && c->graph_tile.ty == c->tile.ty &&
       c->graph_cp == cp && c->graph_d4 == c->d4cur && c->graph_spl == spl && c->graph_sw == sw &&
-      c->graph_rows3 == rows3)
+      c->graph_rows == rows)
     return LBM_OK;
   drop_graph(c);
   hipStream_t cs;
@@ -817,7 +824,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
         e = (hipError_t)launch_step3(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, sw, rows3, cs);
         d4 ^= 1;
       } else if (spl == 2) {
-        e = (hipError_t)launch_step2(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, sw, cs);
+        e = (hipError_t)launch_step2(c->prec, c->desc(), c->desc_dev(cur, d4), cp, 0, sw, rows2, cs);
         d4 ^= 1;
       } else {
         e = (hipError_t)launch_step(c->prec, c->desc(), c->desc_dev(cur, d4), c->tile, cp, 0, cs);
@@ -841,7 +848,7 @@ static lbm_status ensure_graph(lbm_ctx *c) {
   c->graph_d4 = c->d4cur;
   c->graph_spl = spl;
   c->graph_sw = sw;
-  c->graph_rows3 = rows3;
+  c->graph_rows = rows;
   return LBM_OK;
 }
 
@@ -1086,15 +1093,15 @@ LBM_API lbm_status lbm_set_strip_width(lbm_ctx *c, int32_t tiles) {
 
 LBM_API int32_t lbm_get_strip_width(const lbm_ctx *c) { return c ? ctx_strip(c) : -1; }
 
-LBM_API lbm_status lbm_set_three_step_rows(lbm_ctx *c, int32_t rows) {
+LBM_API lbm_status lbm_set_tile_rows(lbm_ctx *c, int32_t rows) {
   if (!c) return LBM_EINVAL;
-  if (rows != 0 && rows != 8 && !(rows == 12 && c->prec == PREC_FP32))
-    return fail(c, LBM_EINVAL, "three-step tile rows must be 0 (default), 8 or, with FP32 storage, 12");
-  c->rows3 = rows;
+  if (rows != 0 && rows != 8 && !(rows == 12 && c->prec != PREC_FP64))
+    return fail(c, LBM_EINVAL, "tile rows must be 0 (default), 8 or, with FP32 and FP16 storage, 12");
+  c->tile_rows = rows;
   return LBM_OK;
 }
 
-LBM_API int32_t lbm_get_three_step_rows(const lbm_ctx *c) { return c ? ctx_rows3(c) : 0; }
+LBM_API int32_t lbm_get_tile_rows(const lbm_ctx *c) { return c ? ctx_rows(c) : 0; }
 
 LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
   if (!c) return LBM_EINVAL;
@@ -1119,7 +1126,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   const int64_t step0 = c->step;
   const Tile tile0 = c->tile;
   const int cp0 = c->cache_policy, spl0 = c->steps_per_launch, d4cur0 = c->d4cur, sw0 = c->strip;
-  const int rows0 = c->rows3;
+  const int rows0 = c->tile_rows;
   hipError_t e = hipMemcpyAsync(save, c->pop(cur0), pop_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save + pop_bytes, c->d4(), d4_bytes, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -1129,7 +1136,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   if (e == hipSuccess) e = hipEventCreate(&t1);
   double best = 1e300;
   Tile best_tile = tile0;
-  int best_cp = ctx_policy(c), best_spl = ctx_spl(c), best_sw = c->strip, best_rows = c->rows3;
+  int best_cp = ctx_policy(c), best_spl = ctx_spl(c), best_sw = c->strip, best_rows = c->tile_rows;
   const int txs[] = {64, 128, 256};
   const int tys[] = {1, 2, 4, 8};
   struct Cand {
@@ -1148,8 +1155,11 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   for (int sw : {4, 8})
     if (ntx2 > sw) sws.push_back(sw);
   if (two_step_ok(c))
-    for (int cp = 0; cp < CP_COUNT; ++cp)
-      for (int sw : sws) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty, sw, rows0});
+    for (int rows : {8, 12}) {   // FP16 without node walls: the 64 x 8 and the 64 x 12 tile
+      if (rows == 12 && (c->prec != PREC_FP16S || node_walls(&c->p))) continue;
+      for (int cp = 0; cp < CP_COUNT; ++cp)
+        for (int sw : sws) cands.push_back(Cand{2, cp, tile0.tx, tile0.ty, sw, rows});
+    }
   if (three_step_ok(c))   // FP32: the 64 x 8 and the 64 x 12 tile
     for (int rows : {8, 12}) {
       if (rows == 12 && c->prec != PREC_FP32) continue;
@@ -1163,7 +1173,7 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
     c->cache_policy = k.cp;
     c->steps_per_launch = k.spl;
     c->strip = k.sw;
-    c->rows3 = k.rows;
+    c->tile_rows = k.rows;
     if (step_plain(c, 6) != LBM_OK) { e = hipErrorUnknown; break; }   // warm-up
     e = hipEventRecord(t0, c->stream);
     if (e == hipSuccess && step_plain(c, nsteps) != LBM_OK) e = hipErrorUnknown;
@@ -1198,14 +1208,14 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
     c->cache_policy = cp0;
     c->steps_per_launch = spl0;
     c->strip = sw0;
-    c->rows3 = rows0;
+    c->tile_rows = rows0;
     return hip_fail(c, e, "autotune");
   }
   c->tile = best_tile;
   c->cache_policy = best_cp;
   c->steps_per_launch = best_spl;
   c->strip = best_sw;
-  c->rows3 = best_rows;
+  c->tile_rows = best_rows;
   drop_graph(c);
   if (tx_out) *tx_out = best_tile.tx;
   if (ty_out) *ty_out = best_tile.ty;

@@ -86,8 +86,9 @@ int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp,
 // two time steps per launch (tiles with a one-node halo staged in LDS); fields read from d4,
 // written to d4b; walls through the nodes with FP32 and FP64 storage on lattices of at least
 // one tile (else hipErrorInvalidValue).  sw: tile order, row by row (0) or in vertical strips of
-// sw tiles
-int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream);
+// sw tiles; rows: tile rows, 8 (64 x 8, FP64 32 x 8) or, FP16 storage without node walls only,
+// 12 (64 x 12); else hipErrorInvalidValue
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, int rows, void *stream);
 // three time steps per launch (tiles with a two-node halo staged in LDS); FP32 and FP64
 // storage, walls half a spacing outside; fields read from d4, written to d4b; sw as above;
 // rows: tile rows, 8 (64 x 8, FP64 32 x 8) or, FP32 only, 12 (64 x 12); else hipErrorInvalidValue

@@ -1175,21 +1175,27 @@ __device__ __forceinline__ void two_step_tile(const Desc<typename St<S>::R> &d, 
 
 // NEE: the last tile of each row and column is placed against the far side (nx >= W and
 // ny >= H, checked by the launcher)
-template <typename S, int CP, bool NEE>
-__global__ void __launch_bounds__(TwoStep<S>::THREADS) step2_kernel(const Desc<typename St<S>::R> *__restrict__ dp,
-                                                                    int ntx, int parity, int sw) {
+template <typename S, int CP, bool NEE, typename SH = TwoStep<S>>
+__global__ void __launch_bounds__(SH::THREADS) step2_kernel(const Desc<typename St<S>::R> *__restrict__ dp, int ntx,
+                                                            int parity, int sw) {
   const Desc<typename St<S>::R> &d = *dp;
-  __shared__ S lpop[NPOP][TwoStep<S>::RN];
+  __shared__ S lpop[NPOP][SH::RN];
   const int b = Pol<S, CP>::xcd_bands ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int tx, ty;
   tile_of(b, ntx, (int)gridDim.x / ntx, sw, tx, ty);
-  int x0 = tx * TwoStep<S>::W, y0 = ty * TwoStep<S>::H;
+  int x0 = tx * SH::W, y0 = ty * SH::H;
   if (NEE) {
-    x0 = min(x0, d.nx - TwoStep<S>::W);
-    y0 = min(y0, d.ny - TwoStep<S>::H);
+    x0 = min(x0, d.nx - SH::W);
+    y0 = min(y0, d.ny - SH::H);
   }
-  two_step_tile<S, CP, NEE>(d, x0, y0, parity, lpop);
+  two_step_tile<S, CP, NEE, SH>(d, x0, y0, parity, lpop);
 }
+
+// The taller FP16 tile of the single-lattice two-step launch, 64 x 12 (65 VGPRs, 35 KB of LDS: two
+// work-groups of 12 waves per CU), for lattices that stream from HBM.  Measured with the tiles in
+// strips (banded cavity, streaming policy): 2048^2 69.5 GLUPS against 67.3 for 64 x 8 row by row,
+// 4096^2 76.2 against 71.9 for 64 x 8 in strips.
+using TallTwo = Shape2<64, 12>;
 
 // ---------------------------------------------------------------- three steps per launch
 // One work-group of W x H threads advances a W x H tile by three time steps (storage FP32 or
@@ -1797,14 +1803,14 @@ int launch_step(int prec, const void *desc, const void *ddev, Tile tile, int cp,
   }
 }
 
-template <typename S>
+template <typename S, typename SH = TwoStep<S>>
 static int step2_t(const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
   const auto &d = *(const Desc<typename St<S>::R> *)desc;
   const auto *dp = (const Desc<typename St<S>::R> *)ddev;
   hipStream_t s = (hipStream_t)stream;
-  constexpr int W = TwoStep<S>::W, H = TwoStep<S>::H;
+  constexpr int W = SH::W, H = SH::H;
   const int ntx = (d.nx + W - 1) / W, nty = (d.ny + H - 1) / H;
-  const dim3 grid(ntx * nty), block(TwoStep<S>::THREADS);
+  const dim3 grid(ntx * nty), block(SH::THREADS);
   if (d.nee) {
     // FP16 storage with walls through the nodes runs one step per launch; the tiles placed
     // against the far sides must fit in the lattice
@@ -1814,31 +1820,47 @@ static int step2_t(const void *desc, const void *ddev, int cp, int parity, int s
       if (d.nx < W || d.ny < H) return (int)hipErrorInvalidValue;
       switch (cp) {
         case CP_STREAM:
-          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true>), grid, block, 0, s, dp, ntx, parity, sw);
+          hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, true, SH>), grid, block, 0, s, dp, ntx, parity, sw);
           break;
         case CP_RESIDENT:
-          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true>), grid, block, 0, s, dp, ntx, parity, sw);
+          hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, true, SH>), grid, block, 0, s, dp, ntx, parity, sw);
           break;
-        default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true>), grid, block, 0, s, dp, ntx, parity, sw); break;
+        default:
+          hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, true, SH>), grid, block, 0, s, dp, ntx, parity, sw);
+          break;
       }
       return (int)hipGetLastError();
     }
   }
   switch (cp) {
-    case CP_STREAM: hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false>), grid, block, 0, s, dp, ntx, parity, sw); break;
-    case CP_RESIDENT:
-      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false>), grid, block, 0, s, dp, ntx, parity, sw);
+    case CP_STREAM:
+      hipLaunchKernelGGL((step2_kernel<S, CP_STREAM, false, SH>), grid, block, 0, s, dp, ntx, parity, sw);
       break;
-    default: hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false>), grid, block, 0, s, dp, ntx, parity, sw); break;
+    case CP_RESIDENT:
+      hipLaunchKernelGGL((step2_kernel<S, CP_RESIDENT, false, SH>), grid, block, 0, s, dp, ntx, parity, sw);
+      break;
+    default:
+      hipLaunchKernelGGL((step2_kernel<S, CP_TUNED, false, SH>), grid, block, 0, s, dp, ntx, parity, sw);
+      break;
   }
   return (int)hipGetLastError();
 }
 
-int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, void *stream) {
+int launch_step2(int prec, const void *desc, const void *ddev, int cp, int parity, int sw, int rows, void *stream) {
   switch (prec) {
-    case PREC_FP64: return step2_t<double>(desc, ddev, cp, parity, sw, stream);
-    case PREC_FP32: return step2_t<float>(desc, ddev, cp, parity, sw, stream);
-    default: return step2_t<_Float16>(desc, ddev, cp, parity, sw, stream);
+    case PREC_FP64:
+      if (rows != TwoStep<double>::H) return (int)hipErrorInvalidValue;
+      return step2_t<double>(desc, ddev, cp, parity, sw, stream);
+    case PREC_FP32:
+      if (rows != TwoStep<float>::H) return (int)hipErrorInvalidValue;
+      return step2_t<float>(desc, ddev, cp, parity, sw, stream);
+    default:
+      if (rows == TallTwo::H) {
+        if (((const Desc<float> *)desc)->nee) return (int)hipErrorInvalidValue;
+        return step2_t<_Float16, TallTwo>(desc, ddev, cp, parity, sw, stream);
+      }
+      if (rows != TwoStep<_Float16>::H) return (int)hipErrorInvalidValue;
+      return step2_t<_Float16>(desc, ddev, cp, parity, sw, stream);
   }
 }
 

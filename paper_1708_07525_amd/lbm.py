@@ -28,7 +28,7 @@ EXPORTS = (
     "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state",
     "lbm_set_tile", "lbm_get_tile", "lbm_set_cache_policy", "lbm_get_cache_policy", "lbm_set_strip_width",
-    "lbm_get_strip_width", "lbm_set_three_step_rows", "lbm_get_three_step_rows", "lbm_set_steps_per_launch",
+    "lbm_get_strip_width", "lbm_set_tile_rows", "lbm_get_tile_rows", "lbm_set_steps_per_launch",
     "lbm_get_steps_per_launch", "lbm_set_graph_chunk",
     "lbm_autotune", "lbm_last_error", "lbm_destroy",
     "lbm_batch_create", "lbm_batch_attach", "lbm_batch_detach", "lbm_batch_step", "lbm_batch_autotune",
@@ -117,10 +117,10 @@ def lib():
         L.lbm_set_strip_width.restype = ctypes.c_int
         L.lbm_get_strip_width.argtypes = [_VP]
         L.lbm_get_strip_width.restype = ctypes.c_int32
-        L.lbm_set_three_step_rows.argtypes = [_VP, ctypes.c_int32]
-        L.lbm_set_three_step_rows.restype = ctypes.c_int
-        L.lbm_get_three_step_rows.argtypes = [_VP]
-        L.lbm_get_three_step_rows.restype = ctypes.c_int32
+        L.lbm_set_tile_rows.argtypes = [_VP, ctypes.c_int32]
+        L.lbm_set_tile_rows.restype = ctypes.c_int
+        L.lbm_get_tile_rows.argtypes = [_VP]
+        L.lbm_get_tile_rows.restype = ctypes.c_int32
         L.lbm_set_steps_per_launch.argtypes = [_VP, ctypes.c_int32]
         L.lbm_set_steps_per_launch.restype = ctypes.c_int
         L.lbm_get_steps_per_launch.argtypes = [_VP]
@@ -312,13 +312,13 @@ class Solver:
     def get_strip_width(self) -> int:
         return int(lib().lbm_get_strip_width(self._h))
 
-    def set_three_step_rows(self, rows: int):
-        """Rows of the three-step tile: 8, 12 (FP32 only) or 0 for the default rule (see
-        include/lbm.h)."""
-        _check(lib().lbm_set_three_step_rows(self._h, int(rows)), self._h, "lbm_set_three_step_rows")
+    def set_tile_rows(self, rows: int):
+        """Rows of the FP32 three-step and FP16 two-step tile: 8, 12 or 0 for the default rule
+        (see include/lbm.h)."""
+        _check(lib().lbm_set_tile_rows(self._h, int(rows)), self._h, "lbm_set_tile_rows")
 
-    def get_three_step_rows(self) -> int:
-        return int(lib().lbm_get_three_step_rows(self._h))
+    def get_tile_rows(self) -> int:
+        return int(lib().lbm_get_tile_rows(self._h))
 
     def set_steps_per_launch(self, n: int):
         """1, 2 (two-step LDS kernel), 3 (three-step LDS kernel) or 0 for the default (see

@@ -36,11 +36,11 @@ class FakeSolver:
     def get_strip_width(self):
         return getattr(self, "strip", 4)
 
-    def set_three_step_rows(self, n):
-        self.rows3 = n
+    def set_tile_rows(self, n):
+        self.rows = n
 
-    def get_three_step_rows(self):
-        return getattr(self, "rows3", 12)
+    def get_tile_rows(self):
+        return getattr(self, "rows", 12)
 
 
 def test_size_class_and_key():
@@ -58,7 +58,7 @@ def test_tune_times_once_per_class(tmp_path):
     b = FakeSolver(120, 90)          # same class: 128x128, uniform, fp32
     b.tile = (64, 8)
     assert autotune.tune(b, "gpu", False, path=path) == ((128, 2), None)
-    assert b.timed == 0 and b.tile == (128, 2) and b.policy == 1 and b.strip == 4 and b.rows3 == 12
+    assert b.timed == 0 and b.tile == (128, 2) and b.policy == 1 and b.strip == 4 and b.rows == 12
     c = FakeSolver(120, 90, "fp16s")  # other precision: timed again
     autotune.tune(c, "gpu", False, path=path)
     assert c.timed == 1

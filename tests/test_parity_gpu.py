@@ -231,7 +231,7 @@ def test_degenerate_calls_and_smallest_lattices():
                     continue
                 sv = Solver(pp, T=T, C=C, precision=prec)
                 sv.set_steps_per_launch(spl)
-                sv.set_three_step_rows(rows)
+                sv.set_tile_rows(rows)
                 sv.step(61)
                 states.append(sv.get_state())
                 sv.close()
@@ -403,7 +403,8 @@ def test_two_step_kernel_matches_one_step(prec, case):
 @pytest.mark.parametrize("walls", ["half_way", "nee", "periodic"])
 def test_tile_order_changes_nothing(prec, walls):
     """The multi-step launches visit their tiles row by row or in vertical strips of k tiles
-    (the last strip narrower), and FP32's three-step launch runs on 64 x 8 or 64 x 12 tiles:
+    (the last strip narrower), and FP32's three-step and FP16's two-step launches run on 64 x 8
+    or 64 x 12 tiles:
     the state is the same bit for bit, on a wide ragged lattice
     (600 x 41: 10 tiles of 64 nodes across, 19 of 32 for FP64, a part-filled last row of
     tiles) with a porosity field, with half-way walls, walls through the nodes and periodic
@@ -420,15 +421,15 @@ def test_tile_order_changes_nothing(prec, walls):
     w = 32 if prec == "fp64" else 64
     ntx = (nx + w - 1) // w
     states = {}
-    rows = (8, 12) if prec == "fp32" else (8,)
+    rows = (8, 12) if prec != "fp64" else (8,)
     for sw in (-1, 0, 1, 3, 4, 8, 64):
         for chunk in (0, 64):
             for r in rows:
                 s = Solver(p, phi=phi, T=T, C=C, precision=prec)
                 s.set_graph_chunk(chunk)
                 s.set_strip_width(sw)
-                s.set_three_step_rows(r)
-                assert s.get_three_step_rows() == r
+                s.set_tile_rows(r)
+                assert s.get_tile_rows() == (8 if walls == "nee" else r)   # node walls: 8-row tiles
                 if sw == -1:      # the default rule: three-step launches strips of 4 from 9 up to
                     # 32 tiles across, two-step launches (FP16, walls through the nodes) row by row
                     three = prec != "fp16s" and walls != "nee"
@@ -445,21 +446,23 @@ def test_tile_order_changes_nothing(prec, walls):
 
 
 def test_launch_defaults_follow_the_lattice():
-    """The default launch choices: FP32 three-step tiles of 12 rows where a step touches more
-    than 400 MB (the lattice streams from HBM), 8 rows below and for FP64; strips of 4 tiles for
-    three-step launches from 9 up to 32 tiles across, 8 beyond; invalid settings refused."""
+    """The default launch choices: FP32 three-step and FP16 two-step tiles of 12 rows where a
+    step touches more than 400 MB (the lattice streams from HBM), 8 rows below and for FP64;
+    strips of 4 tiles for three-step launches from 9 up to 32 tiles across, 8 beyond; invalid
+    settings refused."""
     from paper_1708_07525_amd.lbm import LbmError
     Solver = _solver()
     for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 4), (1456, 1460, "fp32"): (8, 4),
                                        (2100, 400, "fp32"): (8, 8), (500, 400, "fp32"): (8, 0),
-                                       (1460, 1460, "fp64"): (8, 8), (1460, 1460, "fp16s"): (8, 0)}.items():
+                                       (1460, 1460, "fp64"): (8, 8), (1460, 1460, "fp16s"): (8, 0),
+                                       (1900, 1900, "fp16s"): (12, 0)}.items():
         s = Solver(workloads.cavity_params(nx=nx, ny=ny), T=0.5, C=0.5, precision=prec)
-        assert (s.get_three_step_rows(), s.get_strip_width()) == (rows, sw), (nx, ny, prec)
+        assert (s.get_tile_rows(), s.get_strip_width()) == (rows, sw), (nx, ny, prec)
         with pytest.raises(LbmError):
-            s.set_three_step_rows(10)
-        if prec != "fp32":
+            s.set_tile_rows(10)
+        if prec == "fp64":
             with pytest.raises(LbmError):
-                s.set_three_step_rows(12)
+                s.set_tile_rows(12)
         with pytest.raises(LbmError):
             s.set_strip_width(-2)
         s.close()
