@@ -233,10 +233,10 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 /* Order in which the two- and three-step launches visit their tiles: 0 row by row of tiles,
  * k >= 1 in vertical strips k tiles wide (the last one narrower), each walked row by row, so
  * that the halo rows a tile reads were loaded shortly before by its neighbour in the strip and
- * are still in the L2 of its XCD; -1 the default rule (strips of 8 tiles on lattices more than
- * 32 tiles across; below that, three-step launches use strips of 4 tiles from 9 tiles across and
- * two-step launches go row by row).  LBM_EINVAL outside -1..1024.  Results do not depend on it
- * (bit for bit).
+ * are still in the L2 of its XCD; -1 the default rule (row by row up to 8 tiles across; strips
+ * of 8 tiles beyond 32 tiles across; in between, strips of 4 for three-step launches, of 8 for
+ * two-step launches on 12-row tiles, row by row for two-step launches on 8-row tiles).
+ * LBM_EINVAL outside -1..1024.  Results do not depend on it (bit for bit).
  * lbm_get_strip_width returns the width in effect (-1 for a NULL context). */
 lbm_status lbm_set_strip_width(struct lbm_ctx *c, int32_t tiles);
 int32_t lbm_get_strip_width(const struct lbm_ctx *c);

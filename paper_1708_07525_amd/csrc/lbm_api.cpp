@@ -267,17 +267,20 @@ int default_policy(int prec, double nodes, int spl) {
 // left the L2 on wide lattices; in strips they were loaded sw tiles earlier.  Measured, FP32
 // three steps per launch (64 x 8 tiles): 2048^2 62.1 GLUPS with strips of 4 tiles, 61.2 with 8,
 // 60.1 row by row; 4096^2 68.5 with 8, 64.0 with 4, 55.6 row by row; 8192 x 512 62.4 with 8
-// against 55.3.  Two steps per launch gain only on wider lattices: FP16 4096^2 71.9 with 8
-// against 66.6 row by row, FP32 with walls through the nodes 52.2 against 47.6; at 2048^2 they
-// lose (walls through the nodes 48.7 row by row, 43.3 with strips of 4, 46.6 with 8).  Up to 8
-// tiles across, both orders are the same.
-int default_strip(int prec, int nx, int spl) {
+// against 55.3.  Two steps per launch on 64 x 8 tiles gain only on wider lattices: FP16 4096^2
+// 71.9 with 8 against 66.6 row by row, FP32 with walls through the nodes 52.2 against 47.6; at
+// 2048^2 they lose (walls through the nodes 48.7 row by row, 43.3 with strips of 4, 46.6 with 8);
+// FP16 on 64 x 12 tiles gains there too (69.5 with 8, 68.7 with 4, 64.8 row by row).  `rows` is
+// the tile rows of the launch.  Up to 8 tiles across, both orders are the same.
+int default_strip(int prec, int nx, int spl, int rows) {
   if (spl < 2) return 0;
   int w = 0, h = 0;
   two_step_tile_shape(prec, &w, &h);
   const int ntx = (nx + w - 1) / w;
+  if (ntx <= 8) return 0;
   if (ntx > 32) return 8;
-  return (spl == 3 && ntx > 8) ? 4 : 0;
+  if (spl == 3) return 4;
+  return rows == 12 ? 8 : 0;
 }
 
 // Rows of the multi-step tile when none is set (lbm_set_tile_rows): the FP32 three-step and the
@@ -739,10 +742,6 @@ static int ctx_policy(const lbm_ctx *c) {
   return c->cache_policy >= 0 ? c->cache_policy : default_policy(c->prec, (double)c->p.nx * c->p.ny, ctx_spl(c));
 }
 
-static int ctx_strip(const lbm_ctx *c) {
-  return c->strip >= 0 ? c->strip : default_strip(c->prec, c->p.nx, ctx_spl(c));
-}
-
 static int ctx_rows(const lbm_ctx *c) {
   if (node_walls(&c->p)) return 8;
   return c->tile_rows > 0 ? c->tile_rows : default_rows(c->prec, (double)c->p.nx * c->p.ny);
@@ -752,6 +751,12 @@ static int ctx_rows(const lbm_ctx *c) {
 // two-step launch, the others have 8-row tiles
 static int rows2_of(const lbm_ctx *c) { return c->prec == PREC_FP16S ? ctx_rows(c) : 8; }
 static int rows3_of(const lbm_ctx *c) { return c->prec == PREC_FP32 ? ctx_rows(c) : 8; }
+
+static int ctx_strip(const lbm_ctx *c) {
+  if (c->strip >= 0) return c->strip;
+  const int spl = ctx_spl(c);
+  return default_strip(c->prec, c->p.nx, spl, spl == 3 ? rows3_of(c) : rows2_of(c));
+}
 
 // n steps with plain launches: three or two steps per launch as ctx_spl allows, the remainder
 // in shorter launches
