@@ -246,7 +246,8 @@ int32_t lbm_get_strip_width(const struct lbm_ctx *c);
  * 0 for the default rule (12 where a step touches more than 400 MB, i.e. the lattice streams from
  * HBM, else 8).  FP64 (32 x 8) and the node-wall launches have 8-row tiles only.  LBM_EINVAL for
  * other values (12 with FP64 storage).  Results do not depend on it (bit for bit).
- * lbm_get_tile_rows returns the rows in effect (0 for a NULL context). */
+ * lbm_get_tile_rows returns the rows of the multi-step launch in effect (8 for the other launches
+ * and for one step per launch; 0 for a NULL context). */
 lbm_status lbm_set_tile_rows(struct lbm_ctx *c, int32_t rows);
 int32_t lbm_get_tile_rows(const struct lbm_ctx *c);
 

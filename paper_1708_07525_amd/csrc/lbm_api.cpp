@@ -1106,7 +1106,13 @@ LBM_API lbm_status lbm_set_tile_rows(lbm_ctx *c, int32_t rows) {
   return LBM_OK;
 }
 
-LBM_API int32_t lbm_get_tile_rows(const lbm_ctx *c) { return c ? ctx_rows(c) : 0; }
+// the rows of the multi-step launch in effect (8 where the steps per launch leave no tile rows to
+// choose)
+LBM_API int32_t lbm_get_tile_rows(const lbm_ctx *c) {
+  if (!c) return 0;
+  const int spl = ctx_spl(c);
+  return spl == 3 ? rows3_of(c) : spl == 2 ? rows2_of(c) : 8;
+}
 
 LBM_API lbm_status lbm_set_steps_per_launch(lbm_ctx *c, int32_t n) {
   if (!c) return LBM_EINVAL;
