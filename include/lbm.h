@@ -233,10 +233,13 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
 /* Order in which the two- and three-step launches visit their tiles: 0 row by row of tiles,
  * k >= 1 in vertical strips k tiles wide (the last one narrower), each walked row by row, so
  * that the halo rows a tile reads were loaded shortly before by its neighbour in the strip and
- * are still in the L2 of its XCD; -1 the default rule (row by row up to 8 tiles across; strips
- * of 8 tiles beyond 32 tiles across; in between, strips of 4 for three-step launches, of 8 for
- * two-step launches on 12-row tiles, row by row for two-step launches on 8-row tiles).
- * LBM_EINVAL outside -1..1024.  Results do not depend on it (bit for bit).
+ * are still in the L2 of its XCD; -1 the default rule: row by row up to 8 tiles across and
+ * where a step touches at most 400 MB (the lattice stays in the Infinity Cache); otherwise for
+ * three-step launches and two-step launches on 12-row tiles one strip per XCD band (tiles across
+ * / 8, halved while above 8) when the tiles across are a multiple of 8, else strips of 4 up to 32
+ * tiles across and of 8 beyond; two-step launches on 8-row tiles row by row up to 32 tiles
+ * across, strips of 8 beyond.  LBM_EINVAL outside -1..1024.  Results do not depend on it (bit for
+ * bit).
  * lbm_get_strip_width returns the width in effect (-1 for a NULL context). */
 lbm_status lbm_set_strip_width(struct lbm_ctx *c, int32_t tiles);
 int32_t lbm_get_strip_width(const struct lbm_ctx *c);
@@ -265,7 +268,8 @@ int32_t lbm_get_steps_per_launch(const struct lbm_ctx *c);
 
 /* Times every supported launch shape, cache policy and steps-per-launch count on this
  * context for `steps` steps each (HIP events), the multi-step launches also with their tiles
- * row by row and in strips of 4 and 8 tiles, and the FP32 three-step and FP16 two-step launches on
+ * row by row, in strips of 4 and 8 tiles and of one strip per XCD band, and the FP32 three-step
+ * and FP16 two-step launches on
  * both their tiles,
  * keeps the fastest (read the choices with lbm_get_cache_policy, lbm_get_steps_per_launch,
  * lbm_get_strip_width, lbm_get_tile_rows),

@@ -264,23 +264,32 @@ int default_policy(int prec, double nodes, int spl) {
 
 // Tile order of the multi-step launches when none is set (lbm_set_strip_width): vertical strips
 // of sw tiles.  Row by row, a tile's halo rows were loaded a whole row of tiles earlier and have
-// left the L2 on wide lattices; in strips they were loaded sw tiles earlier.  Measured, FP32
-// three steps per launch (64 x 8 tiles): 2048^2 62.1 GLUPS with strips of 4 tiles, 61.2 with 8,
-// 60.1 row by row; 4096^2 68.5 with 8, 64.0 with 4, 55.6 row by row; 8192 x 512 62.4 with 8
-// against 55.3.  Two steps per launch on 64 x 8 tiles gain only on wider lattices: FP16 4096^2
-// 71.9 with 8 against 66.6 row by row, FP32 with walls through the nodes 52.2 against 47.6; at
-// 2048^2 they lose (walls through the nodes 48.7 row by row, 43.3 with strips of 4, 46.6 with 8);
-// FP16 on 64 x 12 tiles gains there too (69.5 with 8, 68.7 with 4, 64.8 row by row).  `rows` is
-// the tile rows of the launch.  Up to 8 tiles across, both orders are the same.
-int default_strip(int prec, int nx, int spl, int rows) {
+// left the L2 on wide lattices; in strips they were loaded sw tiles earlier.  The strips pay most
+// when they line up with the 8 XCD bands of the launch (an XCD's band is a whole number of
+// strips, or the reverse): FP32 three steps per launch on 64 x 12 tiles, 1536^2 (24 tiles across)
+// 63.9 GLUPS with strips of 3 against 58.8 with 4 and 62.2 row by row; 2560^2 (40) 69.7 with 5
+// against 65.9 with 8; 3072^2 (48) 72.0 with 6 against 67.4 with 8; 2048^2 (32) 67.3 with 4;
+// 4096^2 (64) 73.2 with 8; FP16 two steps on 64 x 12 tiles 2560^2 72.5 with 5 against 69.2 with 8,
+// 3072^2 74.7 with 6.  Narrow strips of 2 lose to their edge columns (2048^2, 64 x 8: 55.2).  Rule
+// for the three-step launches and the two-step ones on 12-row tiles: ntx/8 tiles when the tiles
+// across are a multiple of 8 (halved while above 8), else 4 up to 32 tiles across and 8 beyond.
+// Two-step launches on 64 x 8 tiles (walls through the nodes) lose with strips at 2048^2 (48.7 row
+// by row, 43.3 with 4, 46.6 with 8) and gain at 4096^2 (52.2 with 8 against 47.6): row by row up
+// to 32 tiles across, 8 beyond.  Lattices that stay in the Infinity Cache (at most 400 MB per
+// step) go row by row (1024^2, 64 x 8: 65.0 against 62.9-64.4 with strips).
+int default_strip(int prec, int nx, int ny, int spl, int rows) {
   if (spl < 2) return 0;
   int w = 0, h = 0;
   two_step_tile_shape(prec, &w, &h);
   const int ntx = (nx + w - 1) / w;
-  if (ntx <= 8) return 0;
-  if (ntx > 32) return 8;
-  if (spl == 3) return 4;
-  return rows == 12 ? 8 : 0;
+  if (ntx <= 8 || (double)nx * ny * bytes_per_lu(prec) <= 400e6) return 0;
+  if (spl == 2 && rows != 12) return ntx > 32 ? 8 : 0;
+  if (ntx % 8 == 0) {
+    int a = ntx / 8;
+    while (a > 8 && a % 2 == 0) a /= 2;
+    if (a >= 3 && a <= 16) return a;
+  }
+  return ntx > 32 ? 8 : 4;
 }
 
 // Rows of the multi-step tile when none is set (lbm_set_tile_rows): the FP32 three-step and the
@@ -755,7 +764,7 @@ static int rows3_of(const lbm_ctx *c) { return c->prec == PREC_FP32 ? ctx_rows(c
 static int ctx_strip(const lbm_ctx *c) {
   if (c->strip >= 0) return c->strip;
   const int spl = ctx_spl(c);
-  return default_strip(c->prec, c->p.nx, spl, spl == 3 ? rows3_of(c) : rows2_of(c));
+  return default_strip(c->prec, c->p.nx, c->p.ny, spl, spl == 3 ? rows3_of(c) : rows2_of(c));
 }
 
 // n steps with plain launches: three or two steps per launch as ctx_spl allows, the remainder
@@ -1165,6 +1174,8 @@ LBM_API lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, int32_t *tx_out, int3
   std::vector<int> sws{0};
   for (int sw : {4, 8})
     if (ntx2 > sw) sws.push_back(sw);
+  const int aligned = ntx2 % 8 == 0 ? ntx2 / 8 : 0;   // one strip per XCD band
+  if (aligned >= 3 && aligned <= 16 && aligned != 4 && aligned != 8) sws.push_back(aligned);
   if (two_step_ok(c))
     for (int rows : {8, 12}) {   // FP16 without node walls: the 64 x 8 and the 64 x 12 tile
       if (rows == 12 && (c->prec != PREC_FP16S || node_walls(&c->p))) continue;

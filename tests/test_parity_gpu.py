@@ -430,13 +430,8 @@ def test_tile_order_changes_nothing(prec, walls):
                 s.set_strip_width(sw)
                 s.set_tile_rows(r)
                 assert s.get_tile_rows() == (8 if walls == "nee" else r)   # node walls: 8-row tiles
-                if sw == -1:      # the default rule, 9 to 32 tiles across: three-step launches
-                    # strips of 4, FP16 two-step launches on 12-row tiles strips of 8, other
-                    # two-step launches (8-row tiles, walls through the nodes) row by row
-                    three = prec != "fp16s" and walls != "nee"
-                    tall_two = prec == "fp16s" and walls != "nee" and r == 12
-                    want = 0 if ntx <= 8 else (4 if three else (8 if tall_two else 0))
-                    assert s.get_strip_width() == want
+                if sw == -1:      # the default rule: row by row on a lattice that stays in the
+                    assert s.get_strip_width() == 0              # Infinity Cache
                 else:
                     assert s.get_strip_width() == sw
                 s.step(131)
@@ -451,14 +446,17 @@ def test_tile_order_changes_nothing(prec, walls):
 def test_launch_defaults_follow_the_lattice():
     """The default launch choices: FP32 three-step and FP16 two-step tiles of 12 rows where a
     step touches more than 400 MB (the lattice streams from HBM), 8 rows below and for FP64;
-    strips of 4 tiles for three-step launches and of 8 for FP16's 12-row two-step tiles from 9
-    up to 32 tiles across, 8 beyond; invalid settings refused."""
+    there, one strip of tiles per XCD band when the tiles across are a multiple of 8, else
+    strips of 4 up to 32 tiles across and 8 beyond; row by row where the lattice stays in the
+    Infinity Cache; invalid settings refused."""
     from paper_1708_07525_amd.lbm import LbmError
     Solver = _solver()
-    for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 4), (1456, 1460, "fp32"): (8, 4),
-                                       (2100, 400, "fp32"): (8, 8), (500, 400, "fp32"): (8, 0),
+    for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 4), (1456, 1460, "fp32"): (8, 0),
+                                       (2100, 400, "fp32"): (8, 0), (500, 400, "fp32"): (8, 0),
+                                       (1536, 1536, "fp32"): (12, 3), (3072, 800, "fp32"): (12, 6),
+                                       (8192, 300, "fp32"): (12, 8), (2200, 1000, "fp32"): (12, 8),
                                        (1460, 1460, "fp64"): (8, 8), (1460, 1460, "fp16s"): (8, 0),
-                                       (1900, 1900, "fp16s"): (12, 8)}.items():
+                                       (1900, 1900, "fp16s"): (12, 4), (2560, 1500, "fp16s"): (12, 5)}.items():
         s = Solver(workloads.cavity_params(nx=nx, ny=ny), T=0.5, C=0.5, precision=prec)
         assert (s.get_tile_rows(), s.get_strip_width()) == (rows, sw), (nx, ny, prec)
         with pytest.raises(LbmError):
