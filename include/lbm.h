@@ -236,8 +236,8 @@ int32_t lbm_get_cache_policy(const struct lbm_ctx *c);
  * are still in the L2 of its XCD; -1 the default rule: row by row up to 8 tiles across and
  * where a step touches at most 400 MB (the lattice stays in the Infinity Cache); otherwise for
  * three-step launches and two-step launches on 12-row tiles one strip per XCD band (tiles across
- * / 8, halved while above 8) when the tiles across are a multiple of 8, else strips of 4 up to 32
- * tiles across and of 8 beyond; two-step launches on 8-row tiles row by row up to 32 tiles
+ * / 8, halved while above 8) when the tiles across are a multiple of 8, else strips of 8 tiles;
+ * two-step launches on 8-row tiles row by row up to 32 tiles
  * across, strips of 8 beyond.  LBM_EINVAL outside -1..1024.  Results do not depend on it (bit for
  * bit).
  * lbm_get_strip_width returns the width in effect (-1 for a NULL context). */

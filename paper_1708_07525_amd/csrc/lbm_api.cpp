@@ -270,9 +270,12 @@ int default_policy(int prec, double nodes, int spl) {
 // 63.9 GLUPS with strips of 3 against 58.8 with 4 and 62.2 row by row; 2560^2 (40) 69.7 with 5
 // against 65.9 with 8; 3072^2 (48) 72.0 with 6 against 67.4 with 8; 2048^2 (32) 67.3 with 4;
 // 4096^2 (64) 73.2 with 8; FP16 two steps on 64 x 12 tiles 2560^2 72.5 with 5 against 69.2 with 8,
-// 3072^2 74.7 with 6.  Narrow strips of 2 lose to their edge columns (2048^2, 64 x 8: 55.2).  Rule
-// for the three-step launches and the two-step ones on 12-row tiles: ntx/8 tiles when the tiles
-// across are a multiple of 8 (halved while above 8), else 4 up to 32 tiles across and 8 beyond.
+// 3072^2 74.7 with 6.  Narrow strips of 2 lose to their edge columns (2048^2, 64 x 8: 55.2), and
+// where the tiles across are not a multiple of 8, strips of 8 come within 2% of the best width
+// while 4 loses up to 8% (1800^2 FP32 62.5 with 8, 56.9 with 4; 1900^2 FP16 67.0 against 61.6;
+// 2600 x 1600 63.9 against 57.7, best 65.1 with 7).  Rule for the three-step launches and the
+// two-step ones on 12-row tiles: ntx/8 tiles when the tiles across are a multiple of 8 (halved
+// while above 8), else 8.
 // Two-step launches on 64 x 8 tiles (walls through the nodes) lose with strips at 2048^2 (48.7 row
 // by row, 43.3 with 4, 46.6 with 8) and gain at 4096^2 (52.2 with 8 against 47.6): row by row up
 // to 32 tiles across, 8 beyond.  Lattices that stay in the Infinity Cache (at most 400 MB per
@@ -289,7 +292,7 @@ int default_strip(int prec, int nx, int ny, int spl, int rows) {
     while (a > 8 && a % 2 == 0) a /= 2;
     if (a >= 3 && a <= 16) return a;
   }
-  return ntx > 32 ? 8 : 4;
+  return 8;
 }
 
 // Rows of the multi-step tile when none is set (lbm_set_tile_rows): the FP32 three-step and the

@@ -447,16 +447,17 @@ def test_launch_defaults_follow_the_lattice():
     """The default launch choices: FP32 three-step and FP16 two-step tiles of 12 rows where a
     step touches more than 400 MB (the lattice streams from HBM), 8 rows below and for FP64;
     there, one strip of tiles per XCD band when the tiles across are a multiple of 8, else
-    strips of 4 up to 32 tiles across and 8 beyond; row by row where the lattice stays in the
-    Infinity Cache; invalid settings refused."""
+    strips of 8; row by row where the lattice stays in the Infinity Cache; invalid settings
+    refused."""
     from paper_1708_07525_amd.lbm import LbmError
     Solver = _solver()
-    for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 4), (1456, 1460, "fp32"): (8, 0),
+    for (nx, ny, prec), (rows, sw) in {(1460, 1460, "fp32"): (12, 8), (1456, 1460, "fp32"): (8, 0),
                                        (2100, 400, "fp32"): (8, 0), (500, 400, "fp32"): (8, 0),
                                        (1536, 1536, "fp32"): (12, 3), (3072, 800, "fp32"): (12, 6),
                                        (8192, 300, "fp32"): (12, 8), (2200, 1000, "fp32"): (12, 8),
                                        (1460, 1460, "fp64"): (8, 8), (1460, 1460, "fp16s"): (8, 0),
-                                       (1900, 1900, "fp16s"): (12, 4), (2560, 1500, "fp16s"): (12, 5)}.items():
+                                       (1900, 1900, "fp16s"): (12, 8), (2560, 1500, "fp16s"): (12, 5),
+                                       (2048, 1200, "fp32"): (12, 4)}.items():
         s = Solver(workloads.cavity_params(nx=nx, ny=ny), T=0.5, C=0.5, precision=prec)
         assert (s.get_tile_rows(), s.get_strip_width()) == (rows, sw), (nx, ny, prec)
         with pytest.raises(LbmError):
